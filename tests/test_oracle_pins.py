@@ -1,0 +1,342 @@
+"""Pins for the CPU oracle: every check here compares it with something other
+than itself -- brute-force path enumeration with exact rationals (Eq.(1)),
+networkx's Brandes implementation, closed forms, invariants the paper
+proves, and published generator outputs.  No GPU."""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import bruteforce as BF
+from paper_1708_08739_amd import graphgen as gg
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def close(a, b, rel=1e-12):
+    return abs(a - b) <= rel * max(1.0, abs(b))
+
+
+# ------------------------------------------------------------ brute force
+
+def test_all_digraphs_on_four_vertices(oracle):
+    """Every one of the 4,096 digraphs on 4 vertices, every r: the oracle's
+    E-BCD equals Eq.(1) evaluated by path enumeration; RV(r) equals the
+    transitive-closure set (Def.1 vs Def.3, Prop.2)."""
+    for code in range(1 << 12):
+        g = gg.digraph_from_code(4, code)
+        bc = BF.betweenness(g)
+        for r in range(4):
+            got, st = oracle.bc_exact(g, r, threads=1)
+            assert close(got, float(bc[r])), (code, r, got, bc[r])
+            rv = oracle.rv(g, r).tolist()
+            assert rv == BF.reachers(g, r), (code, r)
+            if g.out_degree()[r] == 0:
+                assert st["rv_size"] == -1 and got == 0.0
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("weighted", [False, True])
+def test_random_small_against_bruteforce(oracle, seed, weighted):
+    """Random digraphs of 7-10 vertices, unweighted and with weights in
+    {1,2,3} (which forces ties): BC(r) for every r, and delta_s.(r) for every
+    pair, from the oracle's Eq.(4) recursion vs Eq.(1)/(2) by enumeration."""
+    n = 7 + seed % 4
+    g = gg.random_small(n, 0.3, seed=1000 + seed, max_weight=3 if weighted else 0)
+    paths = BF.all_pairs_paths(g)
+    bc = [Fraction(0)] * n
+    for (s, t), (_, cnt, through) in paths.items():
+        for v, c in through.items():
+            if v != s and v != t:
+                bc[v] += Fraction(c, cnt)
+    for r in range(n):
+        got, _ = oracle.bc_exact(g, r, threads=1)
+        assert close(got, float(bc[r])), (r, got, bc[r])
+        rvset = set(oracle.rv(g, r).tolist())
+        for s in range(n):
+            want = BF.dependency(g, s, r, paths)
+            dep, _ = oracle.dependencies(g, r, [s], threads=1)
+            assert close(dep[0], float(want)), (s, r)
+            if s not in rvset:
+                assert dep[0] == 0.0  # Prop.1: sources outside RV(r) add exactly 0
+
+
+def test_distances_and_counts_bruteforce(oracle):
+    """d and sigma from one source vs enumeration (lengths and path counts)."""
+    for seed in range(6):
+        g = gg.random_small(9, 0.35, seed=77 + seed, max_weight=3 if seed % 2 else 0)
+        paths = BF.all_pairs_paths(g)
+        for s in range(g.n):
+            dist, sig, _, ovf, _ = oracle.source_pass(g, s)
+            assert not ovf
+            for t in range(g.n):
+                if t == s:
+                    assert dist[t] == 0 and sig[t] == 1
+                elif (s, t) in paths:
+                    L, cnt, _ = paths[(s, t)]
+                    assert int(dist[t]) == L and int(sig[t]) == cnt
+                else:
+                    assert dist[t] == oracle.INF and sig[t] == 0
+
+
+# ---------------------------------------------------------------- library
+
+def test_networkx_config_er2000(oracle):
+    """All of the ER n=2,000 m=10,000 workload: networkx's unnormalised
+    directed betweenness of the query vertex and of 20 other vertices."""
+    nx = pytest.importorskip("networkx")
+    g, (r,) = gg.er_2000()
+    G = nx.DiGraph()
+    G.add_nodes_from(range(g.n))
+    s, d = g.arcs()
+    G.add_edges_from(zip(s.tolist(), d.tolist()))
+    ref = nx.betweenness_centrality(G, normalized=False)
+    for v in [r] + gg.uniform_vertices(g.n, 20, seed=5, exclude=[r]):
+        got, _ = oracle.bc_exact(g, v)
+        assert close(got, ref[v], 1e-12), (v, got, ref[v])
+
+
+def test_networkx_weighted(oracle):
+    nx = pytest.importorskip("networkx")
+    g = gg.with_weights(gg.erdos_renyi(300, 1500, seed=9), seed=19, max_weight=4)
+    G = nx.DiGraph()
+    G.add_nodes_from(range(g.n))
+    s, d = g.arcs()
+    for a, b, w in zip(s.tolist(), d.tolist(), g.weight.tolist()):
+        G.add_edge(a, b, weight=w)
+    ref = nx.betweenness_centrality(G, normalized=False, weight="weight")
+    for v in gg.uniform_vertices(g.n, 25, seed=3):
+        got, _ = oracle.bc_exact(g, v)
+        assert close(got, ref[v], 1e-11), (v, got, ref[v])
+
+
+# ------------------------------------------------------------ closed forms
+
+def test_directed_path(oracle):
+    n = 40
+    g = gg.directed_path(n)
+    for i in range(n):
+        got, st = oracle.bc_exact(g, i)
+        assert got == i * (n - 1 - i)
+        assert oracle.rv(g, i).tolist() == list(range(i))
+
+
+def test_bidirected_path(oracle):
+    n = 25
+    g = gg.bidirected_path(n)
+    for i in range(n):
+        assert oracle.bc_exact(g, i)[0] == 2 * i * (n - 1 - i)
+
+
+def test_directed_cycle(oracle):
+    n = 17
+    g = gg.directed_cycle(n)
+    for i in range(n):
+        assert oracle.bc_exact(g, i)[0] == (n - 1) * (n - 2) / 2
+
+
+def test_in_out_star(oracle):
+    g, c = gg.in_out_star(7, 5)
+    assert oracle.bc_exact(g, c)[0] == 35.0
+    for v in range(1, g.n):
+        assert oracle.bc_exact(g, v)[0] == 0.0
+
+
+def test_tournament_and_complete(oracle):
+    t = gg.transitive_tournament(12)
+    k = gg.complete_digraph(9)
+    for v in range(12):
+        got, st = oracle.bc_exact(t, v)
+        assert got == 0.0
+    assert oracle.bc_exact(t, 11)[1]["rv_size"] == -1  # out-degree 0
+    assert len(oracle.rv(t, 11)) == 11                 # yet every vertex reaches it
+    for v in range(9):
+        got, st = oracle.bc_exact(k, v)
+        assert got == 0.0 and st["rv_size"] == 8
+
+
+def test_diamond_chain_formulas(oracle):
+    k = 9
+    g, ids = gg.diamond_chain(k)
+    for i in range(1, k):
+        assert oracle.bc_exact(g, ids["x"][i])[0] == 9 * i * (k - i)
+    for i in range(1, k + 1):
+        want = (3 * i - 2) * (3 * k - 3 * i + 1) / 2
+        assert oracle.bc_exact(g, ids["a"][i])[0] == want
+        assert oracle.bc_exact(g, ids["b"][i])[0] == want
+
+
+def test_sigma_exact_at_limit_and_overflow(oracle):
+    """Diamond chain: sigma(x_k) = 2^k from x_0.  k = 63 fits uint64 and
+    every dependency ratio is a power of two, so BC is exact; k = 64 wraps
+    and must be reported."""
+    g, ids = gg.diamond_chain(63)
+    dist, sig, _, ovf, _ = oracle.source_pass(g, 0)
+    assert not ovf and int(sig[ids["x"][63]]) == 1 << 63
+    assert oracle.bc_exact(g, ids["x"][31])[0] == 9 * 31 * 32
+    g64, ids64 = gg.diamond_chain(64)
+    _, sig, _, ovf, _ = oracle.source_pass(g64, 0)
+    assert ovf
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bc_exact(g64, ids64["x"][40])
+    assert e.value.code == oracle.OVERFLOW
+
+
+def test_grid_binomials_and_overflow(oracle):
+    """Right/down grid from the corner: sigma(i, j) = C(i+j, i).  34x34 fits
+    (C(66,33) < 2^64); 35x35 overflows at (34, 34)."""
+    g = gg.grid_right_down(34, 34)
+    dist, sig, _, ovf, _ = oracle.source_pass(g, 0)
+    assert not ovf
+    for i in range(34):
+        for j in range(34):
+            assert int(sig[i * 34 + j]) == math.comb(i + j, i)
+            assert int(dist[i * 34 + j]) == i + j
+    g35 = gg.grid_right_down(35, 35)
+    _, _, _, ovf, _ = oracle.source_pass(g35, 0)
+    assert ovf
+
+
+# ------------------------------------------------------------- invariants
+
+def test_pruned_equals_unpruned_bitwise(oracle):
+    """Prop.1: sources outside RV(r) contribute exactly 0.0, so the pruned
+    sum equals the sum over all s != r bit for bit."""
+    g = gg.rmat(10, 8, seed=21)
+    for r in gg.queries_top_and_random(g, seed=4, top=3, rnd=5):
+        a, sa = oracle.bc_exact(g, r, pruned=True)
+        b, sb = oracle.bc_exact(g, r, pruned=False)
+        assert a == b
+        others = np.setdiff1d(np.arange(g.n), np.append(oracle.rv(g, r), r))
+        dep, _ = oracle.dependencies(g, r, others[:200])
+        assert np.all(dep == 0.0)
+
+
+def test_recursion_vs_pair_formula(oracle):
+    """Eq.(4) recursion vs the definition through d(s,r)+d(r,t)=d(s,t)."""
+    for weighted in (False, True):
+        g = gg.erdos_renyi(200, 900, seed=31)
+        if weighted:
+            g = gg.with_weights(g, seed=8, max_weight=5)
+        for r in gg.uniform_vertices(g.n, 4, seed=2):
+            src = oracle.rv(g, r)[:40]
+            dep, _ = oracle.dependencies(g, r, src)
+            for s, d in zip(src.tolist(), dep.tolist()):
+                assert close(d, oracle.pair_dependency(g, s, r), 1e-12)
+
+
+def test_sum_of_betweenness_identity(oracle):
+    """Unweighted: sum_v BC(v) = sum over reachable ordered pairs of
+    (d(s,t) - 1), since each shortest s-t path has d-1 interior vertices."""
+    g = gg.erdos_renyi(120, 400, seed=12)
+    bc, _ = oracle.bc_set(g, list(range(g.n)))
+    total = 0
+    for s in range(g.n):
+        dist, *_ = oracle.source_pass(g, s)
+        fin = dist[(dist != oracle.INF) & (dist > 0)]
+        total += int((fin - 1).sum())
+    assert close(float(bc.sum()), float(total), 1e-11)
+
+
+def test_weights_one_and_scaled(oracle):
+    g = gg.rmat(9, 6, seed=5)
+    g1 = gg.with_unit_weights(g)
+    gw = gg.with_weights(g, seed=11, max_weight=7)
+    g3 = gg.Digraph(gw.n, gw.row_ptr, gw.col, gw.weight * np.uint32(3))
+    for s in gg.uniform_vertices(g.n, 5, seed=6):
+        a = oracle.source_pass(g, s)
+        b = oracle.source_pass(g1, s)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert np.array_equal(a[2], b[2])
+        c = oracle.source_pass(gw, s)
+        d = oracle.source_pass(g3, s)
+        fin = c[0] != oracle.INF
+        assert np.array_equal(c[0][fin] * np.uint64(3), d[0][fin])
+        assert np.array_equal(c[1], d[1]) and np.array_equal(c[2], d[2])
+    for r in gg.top_out_degree(g, 3):
+        assert oracle.bc_exact(g, r)[0] == oracle.bc_exact(g1, r)[0]
+        assert oracle.bc_exact(gw, r)[0] == oracle.bc_exact(g3, r)[0]
+
+
+def test_set_equals_single(oracle):
+    g = gg.rmat(10, 8, seed=23)
+    rs = gg.queries_top_and_random(g, seed=9, top=3, rnd=4)
+    rs = rs + [rs[0]]  # repeats allowed
+    bc, _ = oracle.bc_set(g, rs)
+    for r, b in zip(rs, bc.tolist()):
+        assert close(b, oracle.bc_exact(g, r)[0], 1e-13)
+
+
+def test_thread_count_does_not_change_result(oracle):
+    g = gg.rmat(11, 8, seed=2)
+    r = gg.top_out_degree(g, 1)[0]
+    assert oracle.bc_exact(g, r, threads=1)[0] == oracle.bc_exact(g, r, threads=7)[0]
+
+
+# ---------------------------------------------------------------- sampling
+
+def test_splitmix_reference_vectors(oracle):
+    """The oracle's generator against the published SplitMix64 outputs, and
+    the index map floor(x * k / 2^64) against exact integer arithmetic."""
+    with open(os.path.join(GOLD, "splitmix64.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for row in rows:
+        seed, outs = int(row[0]), [int(x) for x in row[1:]]
+        for t, x in enumerate(outs):
+            for k in (1, 7, 1000, 2 ** 31 - 1):
+                assert oracle.draw_index(seed, t, k) == (x * k) >> 64
+        assert [int(v) for v in gg.stream(seed, 0, len(outs))] == outs
+
+
+def test_sample_count_eq8(oracle):
+    with open(os.path.join(GOLD, "sample_count_eq8.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for eps, delta, K, rv, T in rows:
+        assert oracle.sample_count(float(eps), float(delta), float(K), int(rv)) == int(T)
+    assert oracle.sample_count(1e-9, 0.1, 1e6, 10 ** 7) == 2 ** 63 - 1  # saturates
+
+
+def test_sampled_single_reacher(oracle):
+    """|RV(r)| = 1: every draw is that vertex, so bc = delta_v.(r)."""
+    g = gg.directed_path(6)
+    bc, st = oracle.bc_sampled(g, 1, T=17, seed=5)
+    assert st["rv_size"] == 1 and bc == oracle.bc_exact(g, 1)[0] == 4.0
+
+
+def test_sampled_matches_definition(oracle):
+    g = gg.rmat(10, 8, seed=7)
+    r = gg.top_out_degree(g, 1)[0]
+    rv = oracle.rv(g, r)
+    T, seed = 50, 1234
+    idx = [(int(x) * len(rv)) >> 64 for x in gg.stream(seed, 0, T)]
+    dep, _ = oracle.dependencies(g, r, rv[idx])
+    want = float(np.sum(dep)) * len(rv) / T
+    got, st = oracle.bc_sampled(g, r, T, seed)
+    assert close(got, want, 1e-12) and st["samples"] == T
+
+
+def test_prop3_unbiased_and_prop4_tail(oracle):
+    """Prop.3: the estimator's mean over many seeds is within 4 standard
+    errors of BC(r).  Prop.4: the fraction of runs off by more than eps is
+    at most the Hoeffding bound 2 exp(-2 T (eps / (K |RV|))^2), K = #FR."""
+    g = gg.rmat(9, 6, seed=14)
+    r = gg.top_out_degree(g, 1)[0]
+    exact, st = oracle.bc_exact(g, r)
+    rv = oracle.rv(g, r)
+    dep, _ = oracle.dependencies(g, r, rv)
+    K = oracle.fr_count(g, r)
+    T = 40
+    ests = []
+    for seed in range(1500):
+        idx = [(int(x) * len(rv)) >> 64 for x in gg.stream(seed, 0, T)]
+        ests.append(float(np.sum(dep[idx])) * len(rv) / T)
+    ests = np.array(ests)
+    se = ests.std(ddof=1) / math.sqrt(len(ests))
+    assert abs(ests.mean() - exact) <= 4 * se
+    for s in (0, 1, 2):  # the oracle's own estimator is the same numbers
+        assert close(oracle.bc_sampled(g, r, T, s)[0], ests[s], 1e-12)
+    eps = 0.25 * K * len(rv)
+    bound = 2 * math.exp(-2 * T * (eps / (K * len(rv))) ** 2)
+    assert np.mean(np.abs(ests - exact) > eps) <= bound
