@@ -23,7 +23,7 @@ INF = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fPIC", "-shared",
+        cmd = ["gcc", "-O3", "-ffp-contract=off", "-fPIC", "-shared",
                "-std=gnu11", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm", "-lpthread"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)

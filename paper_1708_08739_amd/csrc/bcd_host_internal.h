@@ -1,0 +1,136 @@
+// Host-side objects of libbcd: the resident graph and per-call workspaces.
+#pragma once
+
+#include <atomic>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/bcd.h"
+#include "bcd_internal.h"
+
+namespace bcd {
+
+constexpr int kCtrSlots = 16384;      // max workgroups of a traversal launch
+constexpr int kLevelChunkMax = 64;    // level launches enqueued between host checks
+
+bcd_status fail(bcd_status s, const std::string &msg);
+bcd_status hip_fail(hipError_t e, const char *what);
+bcd_status device_check(int *cus);
+
+inline int default_groups(int64_t n) {
+  // keep the two [G][n][64] state arrays near 1 GiB, at least one group
+  int64_t g = (1ll << 30) / (2 * 8 * 64 * std::max<int64_t>(n, 1));
+  if (g < 1) g = 1;
+  if (g > 16) g = 16;
+  while (g > 1 && (uint64_t)g * (uint64_t)n >= (1ull << 32)) --g;
+  return (int)g;
+}
+
+struct Graph;
+
+struct Workspace {
+  Graph *graph = nullptr;
+  int64_t n = 0;
+  hipStream_t stream = nullptr;
+  // batched engine
+  bool batch_ready = false;
+  int G = 0;
+  BatchState S{};
+  size_t res_cap = 0;
+  uint32_t *d_items0 = nullptr;
+  unsigned long long *d_masks0 = nullptr;
+  int32_t *d_lane_slot = nullptr;
+  uint32_t *h_items0 = nullptr;
+  unsigned long long *h_masks0 = nullptr;
+  double *h_res = nullptr;
+  int last_depth = 8;
+  // plain engine
+  bool plain_ready = false;
+  PlainState P{};
+  // reachability
+  bool reach_ready = false;
+  uint32_t *bitmap = nullptr;
+  int32_t *rq[2] = {nullptr, nullptr};
+  uint32_t *rqn = nullptr;
+  uint32_t *h_bitmap = nullptr;
+  // host staging
+  uint32_t *h_cnt = nullptr;
+  uint64_t *h_misc = nullptr;
+  uint64_t *h_ctr = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+
+  ~Workspace();
+  void release();
+  bcd_status init_common(Graph *g);
+  bcd_status ensure_reach();
+  bcd_status ensure_batch(int G);
+  bcd_status ensure_res(size_t need);
+  bcd_status ensure_dout();
+  bcd_status grow_items();
+  bcd_status reset_batch_dense();
+  bcd_status ensure_plain();
+  std::pair<hipEvent_t, hipEvent_t> event_pair(size_t i);
+};
+
+struct Graph {
+  int64_t n = 0, m = 0;
+  bool weighted = false;
+  uint32_t max_w = 1;
+  int cus = 1;
+  std::vector<int64_t> h_rp;
+  int64_t *d_rp = nullptr;
+  int32_t *d_col = nullptr;
+  uint32_t *d_w = nullptr;
+  int64_t *d_irp = nullptr;
+  int32_t *d_icol = nullptr;
+  uint32_t *d_iw = nullptr;
+  mutable std::mutex cfg_mu;
+  bcd_config cfg{};
+  std::mutex pool_mu;
+  std::vector<std::unique_ptr<Workspace>> pool;
+  std::atomic<bool> profiling{false};
+  mutable std::mutex prof_mu;
+  bcd_kernel_profile prof[2]{};
+
+  ~Graph();
+  DevGraph dev() const;
+  Launch launch() const;
+  bcd_config config() const;
+  std::unique_ptr<Workspace> acquire();
+  void release(std::unique_ptr<Workspace> w);
+  void add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes);
+  int64_t outdeg(int64_t v) const { return h_rp[(size_t)v + 1] - h_rp[(size_t)v]; }
+};
+
+// Scoped workspace lease.
+struct Lease {
+  Graph *g;
+  std::unique_ptr<Workspace> w;
+  explicit Lease(Graph *g_) : g(g_), w(g_->acquire()) {}
+  ~Lease() { g->release(std::move(w)); }
+  Workspace *operator->() { return w.get(); }
+  bool ok() const { return (bool)w; }
+};
+
+// Per-source results of one run over a source list.
+struct SourceRun {
+  std::vector<double> dep;          // [ns][ntgt]
+  std::vector<uint64_t> counters;   // [ns][3] when requested
+  uint64_t te = 0, reached = 0, dag = 0;
+  int32_t width = 0;
+};
+
+// Query layer (bcd_query.hip).
+bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::vector<uint32_t> &bits,
+                     int64_t *count);
+bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
+                        const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
+bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t k, uint64_t *dist,
+                                      uint64_t *sigma, double *delta);
+bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
+                       const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
+
+}  // namespace bcd

@@ -1,0 +1,118 @@
+// Internal declarations shared by the host layer and the HIP kernels of
+// libbcd.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bcd {
+
+constexpr int kLanes = 64;  // sources per column group = wavefront width on gfx950
+
+// Entry of the backward pass's level-tagged mask table: which lanes of a
+// vertex sit on level `lev` of batch `epoch`.
+struct __align__(16) LevMask {
+  unsigned long long mask;
+  uint32_t lev;
+  uint32_t epoch;
+};
+
+// Counters accumulated per workgroup slot (no atomics), reduced on the host.
+enum Ctr {
+  C_FWD_VPAIRS = 0,  // (source, vertex) pairs expanded by the forward kernel
+  C_FWD_APAIRS = 1,  // (source, arc) pairs scanned by the forward kernel  (= sum m_s)
+  C_FWD_DPAIRS = 2,  // (source, DAG arc) pairs the forward kernel pushed sigma along (= sum a_s)
+  C_BWD_VPAIRS = 3,  // (source, vertex) pairs whose psi the backward kernel produced
+  C_BWD_APAIRS = 4,  // (source, arc) pairs the backward kernel scanned
+  C_BWD_DPAIRS = 5,  // (source, DAG arc) pairs the backward kernel accumulated
+  C_COUNT = 8
+};
+
+// Device state of one batch of G column groups (64 sources each) over an
+// n-vertex graph.  All [G][n][64] arrays are vertex-major inside a group, so
+// the 64 sources of one vertex are one contiguous row a wavefront reads or
+// writes with one coalesced access.
+struct BatchState {
+  int64_t n;
+  int G;
+  unsigned long long *sig;   // [G][n][64] path counts
+  double *psi;               // [G][n][64] (1 + delta) / sigma
+  double *dout;              // [G][n][64] delta, verification hook only (may be null)
+  unsigned long long *vis;   // [G][n] lanes settled on a level < current (lagging, see kernel)
+  unsigned long long *fr;    // [3][G][n] rotating level masks: current, next, retiring
+  LevMask *bt;               // [2][G][n] backward level masks, by level parity
+  uint32_t *items;           // [cap] g * n + v, grouped by level
+  unsigned long long *imask; // [cap] lanes of the item on its level
+  uint64_t cap;
+  uint32_t *cnt;             // [n + 2] items per level
+  uint64_t *off;             // [n + 2] first item of each level
+  uint32_t *tlev;            // [G][64] smallest level at which the lane met a target
+  uint32_t *tmin;            // [1] smallest over all lanes
+  int32_t *tgt_of;           // [n] target index of a vertex, -1 if none
+  double *res;               // [ntgt][G][64] delta of lane on target
+  uint64_t *ctr;             // [grid][C_COUNT] per-workgroup counters
+  uint32_t *flags;           // [4]: 0 sigma overflow, 1 item capacity exceeded
+  uint32_t epoch;
+  int ctr_slots;
+};
+
+// Plain engine state (one source).
+struct PlainState {
+  int64_t n;
+  int32_t *d;                // [n] level, -1 unreached
+  unsigned long long *sig;   // [n]
+  double *psi;               // [n]
+  double *dout;              // [n] delta, verification only
+  int32_t *queue;            // [n] vertices by level
+  uint32_t *cnt;             // [n + 2]
+  uint64_t *off;             // [n + 2]
+  uint64_t *ctr;             // [grid][C_COUNT]
+  uint32_t *flags;           // [4]
+  int ctr_slots;
+};
+
+struct DevGraph {
+  int64_t n, m;
+  const int64_t *rp;    // [n+1]
+  const int32_t *col;   // [m]
+  const uint32_t *w;    // [m] or null
+  const int64_t *irp;   // transpose
+  const int32_t *icol;
+  const uint32_t *iw;
+};
+
+struct Launch {
+  int block;  // threads per workgroup
+  int grid;   // workgroups
+};
+
+// ---- launchers (bcd_kernels.hip) ----
+hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const unsigned long long *masks0,
+                             int k, hipStream_t st);
+hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st);
+hipError_t launch_bwd_level(const DevGraph &G, const BatchState &S, int level, int ntgt, int full,
+                            Launch L, hipStream_t st);
+hipError_t launch_batch_cleanup(const BatchState &S, uint64_t total_items, Launch L, hipStream_t st);
+hipError_t launch_batch_export(const BatchState &S, int level, uint64_t begin, uint64_t count,
+                               const int32_t *lane_slot, uint64_t *dist, unsigned long long *sigma,
+                               double *delta, int64_t k, hipStream_t st);
+
+hipError_t launch_plain_init(const PlainState &P, int32_t s, hipStream_t st);
+hipError_t launch_plain_fwd(const DevGraph &G, const PlainState &P, int level, Launch L, hipStream_t st);
+hipError_t launch_plain_bwd(const DevGraph &G, const PlainState &P, int level, int32_t target, int full,
+                            Launch L, hipStream_t st);
+hipError_t launch_plain_cleanup(const PlainState &P, uint64_t total, hipStream_t st);
+hipError_t launch_plain_export(const PlainState &P, uint64_t total, uint64_t *dist,
+                               unsigned long long *sigma, double *delta, hipStream_t st);
+
+// Reachability BFS over one CSR (reverse graph for RV, forward for FR).
+hipError_t launch_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t root, hipStream_t st);
+hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap, const int32_t *qin,
+                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, Launch L,
+                              hipStream_t st);
+hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set, hipStream_t st);
+hipError_t launch_plain_gather(const PlainState &P, const int32_t *verts, int k, int32_t *d_out,
+                               double *delta_out, hipStream_t st);
+hipError_t launch_copy_probe(const double *src, double *dst, int64_t n, hipStream_t st);
+
+}  // namespace bcd

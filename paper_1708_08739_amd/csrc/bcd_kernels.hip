@@ -1,0 +1,623 @@
+// HIP kernels for gfx950 (CDNA4, wave64): the per-source shortest-path pass
+// of the paper's Alg.1 / Alg.2 (forward path counting, then the Eq.(4)
+// dependency accumulation), the RV(r) reachability traversal of Def.3, and
+// a copy probe.
+//
+// Batched engine layout: a column group is 64 sources, one per wavefront
+// lane.  A frontier item is (group g, vertex v) with a 64-bit mask of the
+// lanes for which v sits on the current BFS level; one wavefront expands one
+// item, lane b working for source b, so the 64 path counts of v are one
+// coalesced 512-byte row.  Level masks per (g, v) are single 64-bit words,
+// so testing "has source b already settled w" for all 64 sources costs two
+// 8-byte loads per arc.
+#include "bcd_internal.h"
+
+namespace bcd {
+
+typedef unsigned long long ull;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ int lanes_below(ull m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t read_lane(uint32_t x, int j) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, j);
+}
+
+__device__ __forceinline__ ull read_lane64(ull x, int j) {
+  uint32_t lo = read_lane((uint32_t)x, j);
+  uint32_t hi = read_lane((uint32_t)(x >> 32), j);
+  return ((ull)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t first_lane64(uint64_t x) {
+  uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum three per-thread counters over the workgroup and add them into this
+// workgroup's private counter slot (one writer per slot per launch).
+template <int BLOCK>
+__device__ __forceinline__ void flush_counters(uint64_t *ctr, int slots, int k0, uint64_t a, uint64_t b,
+                                               uint64_t c, bool ovf, uint32_t *flags) {
+  __shared__ uint64_t red[3][BLOCK / 64];
+  __shared__ int any_ovf;
+  if (threadIdx.x == 0) any_ovf = 0;
+  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_down(a, off);
+    b += __shfl_down(b, off);
+    c += __shfl_down(c, off);
+  }
+  if (ovf) any_ovf = 1;
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t s0 = 0, s1 = 0, s2 = 0;
+    for (int i = 0; i < BLOCK / 64; ++i) {
+      s0 += red[0][i];
+      s1 += red[1][i];
+      s2 += red[2][i];
+    }
+    if ((int)blockIdx.x < slots) {
+      uint64_t *p = ctr + (size_t)blockIdx.x * C_COUNT + k0;
+      p[0] += s0;
+      p[1] += s1;
+      p[2] += s2;
+    }
+    if (any_ovf) atomicOr(&flags[0], 1u);
+  }
+}
+
+// ------------------------------------------------------------ batched
+
+// Level 0: each item is (g, source vertex) with the lanes it is the source
+// of; sigma = 1 on those lanes.
+__global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *masks0, int k) {
+  const size_t GN = (size_t)S.G * (size_t)S.n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const uint32_t it = items0[i];
+    const ull m = masks0[i];
+    S.fr[it] = m;  // fr[0] = level-0 masks
+    S.items[i] = it;
+    for (int b = 0; b < kLanes; ++b)
+      if ((m >> b) & 1ull) S.sig[(size_t)it * kLanes + b] = 1ull;
+  }
+  (void)GN;
+}
+
+// One BFS level of the batched forward pass (unweighted graphs).
+//   For every item (g, v, mask) on `level`: for every out-arc (v, w), the
+//   lanes b in mask for which w is not settled on a level <= `level` are
+//   exactly the lanes where (v, w) is a shortest-path-DAG arc; those lanes
+//   add sigma(v) to sigma(w) (the forward half of the pass that Eq.(4)
+//   then walks backwards).  The first wavefront to flag (g, w) for level+1
+//   appends it to the next level's item list.
+// Visibility: masks of `level` (cur) were completed by the previous launch.
+// vis lags: the owner of (g, v) ORs cur into vis during this launch, so a
+// reader sees vis | cur, which is the same union either way.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, int level) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t GN = (uint64_t)S.G * n;
+  const uint64_t base = S.off[level];
+  uint64_t count = S.cnt[level];
+  const uint64_t nbase = base + count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.off[level + 1] = nbase;
+  if (S.flags[1] != 0u || nbase > S.cap) return;  // capacity exceeded earlier: batch is redone
+  const int lane = lane_id();
+  ull *cur = S.fr + (uint64_t)(level % 3) * GN;
+  ull *nxt = S.fr + (uint64_t)((level + 1) % 3) * GN;
+  ull *old = S.fr + (uint64_t)((level + 2) % 3) * GN;
+
+  // retire the masks of level-1 so that array can collect level+2
+  if (level > 0) {
+    const uint64_t pb = S.off[level - 1];
+    const uint64_t pc = S.cnt[level - 1];
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pc; i += (uint64_t)gridDim.x * BLOCK)
+      old[S.items[pb + i]] = 0ull;
+  }
+
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  bool ovf = false;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.items[base + i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    const ull mask = cur[it];
+    if (lane == 0) {
+      S.imask[base + i] = mask;
+      S.vis[it] = S.vis[it] | mask;
+    }
+    const bool act = (mask >> lane) & 1ull;
+    const ull sv = act ? S.sig[(uint64_t)it * kLanes + lane] : 0ull;
+    if (S.tgt_of[v] >= 0) {
+      if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
+      if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
+    }
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    const uint64_t pc = (uint64_t)__popcll(mask);
+    if (lane == 0) {
+      c_v += pc;
+      c_a += pc * (uint64_t)(e1 - e0);
+    }
+    for (int64_t e = e0; e < e1; e += 64) {
+      const int64_t my = e + lane;
+      uint32_t w = 0;
+      ull dag = 0ull;
+      if (my < e1) {
+        w = (uint32_t)G.col[my];
+        const ull vm = S.vis[gbase + w] | cur[gbase + w];
+        dag = mask & ~vm;
+      }
+      bool enq = false;
+      if (dag != 0ull) enq = (atomicOr(&nxt[gbase + w], dag) == 0ull);
+      const ull eb = __ballot(enq);
+      if (eb != 0ull) {
+        uint32_t p0 = 0;
+        if (lane == 0) p0 = atomicAdd(&S.cnt[level + 1], (uint32_t)__popcll(eb));
+        p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+        if (enq) {
+          const uint64_t p = nbase + p0 + (uint64_t)lanes_below(eb);
+          if (p < S.cap) S.items[p] = (uint32_t)(gbase + w);
+          else atomicOr(&S.flags[1], 1u);
+        }
+      }
+      c_d += (uint64_t)__popcll(dag);
+      ull bits = __ballot(dag != 0ull);
+      while (bits != 0ull) {
+        const int j = __ffsll((long long)bits) - 1;
+        bits &= bits - 1ull;
+        const uint32_t wj = read_lane(w, j);
+        const ull dj = read_lane64(dag, j);
+        if ((dj >> lane) & 1ull) {
+          const ull o = atomicAdd(&S.sig[(gbase + wj) * kLanes + lane], sv);
+          if (o + sv < o) ovf = true;
+        }
+      }
+    }
+  }
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
+}
+
+// One level of the backward pass, Eq.(4) read as
+//   delta(v) = sigma(v) * sum_{w: v in P(w)} psi(w),  psi(w) = (1 + delta(w)) / sigma(w),
+// so psi(v) = 1/sigma(v) + sum psi(w).  Successor w of v is on the DAG for
+// lane b iff w sits on level+1 for b, read from the level-tagged table the
+// previous (deeper) launch wrote.  Lanes whose nearest target lies at or
+// below this level are skipped (their psi here cannot reach a target), and
+// target vertices report delta on their lanes.  No atomics: every sum runs
+// in arc order, so results are bit-reproducible.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, int level, int ntgt,
+                                                     int full) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t GN = (uint64_t)S.G * n;
+  const uint64_t base = S.off[level];
+  const uint64_t count = S.cnt[level];
+  if (base + count > S.cap) return;
+  const int lane = lane_id();
+  const LevMask *bt_in = S.bt + (uint64_t)((level + 1) & 1) * GN;
+  LevMask *bt_out = S.bt + (uint64_t)(level & 1) * GN;
+  const uint32_t E = S.epoch;
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.items[base + i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    const ull mask = S.imask[base + i];
+    const int32_t tg = S.tgt_of[v];
+    const uint32_t tl = S.tlev[g * kLanes + lane];
+    const bool need = ((mask >> lane) & 1ull) && (full || (uint32_t)level > tl || tg >= 0);
+    const ull em = __ballot(need);
+    if (em == 0ull) continue;
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; e += 64) {
+      const int64_t my = e + lane;
+      uint32_t w = 0;
+      ull d = 0ull;
+      if (my < e1) {
+        w = (uint32_t)G.col[my];
+        const LevMask t = bt_in[gbase + w];
+        const ull mw = (t.lev == (uint32_t)(level + 1) && t.epoch == E) ? t.mask : 0ull;
+        d = em & mw;
+      }
+      c_d += (uint64_t)__popcll(d);
+      ull bits = __ballot(d != 0ull);
+      while (bits != 0ull) {
+        const int j = __ffsll((long long)bits) - 1;
+        bits &= bits - 1ull;
+        const uint32_t wj = read_lane(w, j);
+        const ull dj = read_lane64(d, j);
+        if ((dj >> lane) & 1ull) acc += S.psi[(gbase + wj) * kLanes + lane];
+      }
+    }
+    if (need) {
+      const double s = (double)S.sig[(uint64_t)it * kLanes + lane];
+      const double dl = s * acc;
+      S.psi[(uint64_t)it * kLanes + lane] = acc + 1.0 / s;
+      if (S.dout) S.dout[(uint64_t)it * kLanes + lane] = dl;
+      if (tg >= 0 && tg < ntgt)
+        S.res[((uint64_t)tg * S.G + g) * kLanes + lane] = (level > 0) ? dl : 0.0;
+    }
+    if (lane == 0) {
+      LevMask o;
+      o.mask = em;
+      o.lev = (uint32_t)level;
+      o.epoch = E;
+      bt_out[it] = o;
+      const uint64_t pc = (uint64_t)__popcll(em);
+      c_v += pc;
+      c_a += pc * (uint64_t)(e1 - e0);
+    }
+  }
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
+}
+
+// Reset what the batch touched: masks and sigma rows of every item.
+__global__ void k_batch_cleanup(BatchState S, uint64_t total) {
+  const uint64_t GN = (uint64_t)S.G * (uint64_t)S.n;
+  const int lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  if (total > S.cap) total = S.cap;
+  for (uint64_t i = wave; i < total; i += nwaves) {
+    const uint32_t it = S.items[i];
+    S.sig[(uint64_t)it * kLanes + lane] = 0ull;
+    if (lane == 0) S.vis[it] = 0ull;
+    if (lane < 3) S.fr[(uint64_t)lane * GN + it] = 0ull;
+  }
+}
+
+// Verification export of one level: per lane with a slot, distance = level,
+// sigma and delta from the state rows.
+__global__ void k_batch_export(BatchState S, int level, uint64_t begin, uint64_t count,
+                               const int32_t *lane_slot, uint64_t *dist, ull *sigma, double *delta,
+                               int64_t k) {
+  const uint64_t n = (uint64_t)S.n;
+  const int lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  if (begin + count > S.cap) return;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.items[begin + i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const ull mask = S.imask[begin + i];
+    if (!((mask >> lane) & 1ull)) continue;
+    const int32_t slot = lane_slot[g * kLanes + lane];
+    if (slot < 0 || slot >= k) continue;
+    const uint64_t o = (uint64_t)slot * n + v;
+    dist[o] = (uint64_t)level;
+    sigma[o] = S.sig[(uint64_t)it * kLanes + lane];
+    if (delta && S.dout) delta[o] = S.dout[(uint64_t)it * kLanes + lane];
+  }
+}
+
+// --------------------------------------------------------------- plain
+
+__global__ void k_plain_init(PlainState P, int32_t s) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    P.d[s] = 0;
+    P.sig[s] = 1ull;
+    P.queue[0] = s;
+    P.cnt[0] = 1u;
+    P.off[0] = 0ull;
+  }
+}
+
+// One BFS level from a single source: a wavefront per frontier vertex,
+// lanes over its out-arcs; the first lane to claim a vertex appends it
+// (ballot + mbcnt compaction, one queue atomic per wavefront).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_plain_fwd(DevGraph G, PlainState P, int level) {
+  const uint64_t base = P.off[level];
+  const uint64_t count = P.cnt[level];
+  const uint64_t nbase = base + count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.off[level + 1] = nbase;
+  if (nbase > (uint64_t)P.n) return;
+  const int lane = lane_id();
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  bool ovf = false;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const int32_t v = P.queue[base + i];
+    const ull sv = P.sig[v];
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    if (lane == 0) {
+      c_v += 1;
+      c_a += (uint64_t)(e1 - e0);
+    }
+    for (int64_t e = e0; e < e1; e += 64) {
+      const int64_t my = e + lane;
+      bool enq = false, dag = false;
+      int32_t w = 0;
+      if (my < e1) {
+        w = G.col[my];
+        int32_t dw = P.d[w];
+        if (dw < 0) {
+          const int32_t o = atomicCAS(&P.d[w], -1, level + 1);
+          if (o == -1) {
+            enq = true;
+            dw = level + 1;
+          } else {
+            dw = o;
+          }
+        }
+        dag = (dw == level + 1);
+        if (dag) {
+          const ull o = atomicAdd(&P.sig[w], sv);
+          if (o + sv < o) ovf = true;
+        }
+      }
+      c_d += dag ? 1 : 0;
+      const ull eb = __ballot(enq);
+      if (eb != 0ull) {
+        uint32_t p0 = 0;
+        if (lane == 0) p0 = atomicAdd(&P.cnt[level + 1], (uint32_t)__popcll(eb));
+        p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+        if (enq) {
+          const uint64_t p = nbase + p0 + (uint64_t)lanes_below(eb);
+          if (p < (uint64_t)P.n) P.queue[p] = w;
+        }
+      }
+    }
+  }
+  flush_counters<BLOCK>(P.ctr, P.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, P.flags);
+}
+
+// One backward level from a single source: lanes over out-arcs gather psi
+// of successors on level+1; the wavefront sum is a fixed shuffle tree.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_plain_bwd(DevGraph G, PlainState P, int level, int32_t target,
+                                                     int only_target) {
+  const uint64_t base = P.off[level];
+  const uint64_t count = P.cnt[level];
+  if (base + count > (uint64_t)P.n) return;
+  const int lane = lane_id();
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const int32_t v = P.queue[base + i];
+    if (only_target && v != target) continue;
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; e += 64) {
+      const int64_t my = e + lane;
+      if (my < e1) {
+        const int32_t w = G.col[my];
+        if (P.d[w] == level + 1) {
+          acc += P.psi[w];
+          c_d += 1;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      const double s = (double)P.sig[v];
+      P.psi[v] = acc + 1.0 / s;
+      P.dout[v] = s * acc;
+      c_v += 1;
+      c_a += (uint64_t)(e1 - e0);
+    }
+  }
+  flush_counters<BLOCK>(P.ctr, P.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, P.flags);
+}
+
+__global__ void k_plain_cleanup(PlainState P, uint64_t total) {
+  if (total > (uint64_t)P.n) total = (uint64_t)P.n;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t v = P.queue[i];
+    P.d[v] = -1;
+    P.sig[v] = 0ull;
+  }
+}
+
+__global__ void k_plain_export(PlainState P, uint64_t *dist, ull *sigma, double *delta) {
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < (uint64_t)P.n;
+       v += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t d = P.d[v];
+    if (dist) dist[v] = d < 0 ? ~0ull : (uint64_t)d;
+    if (sigma) sigma[v] = d < 0 ? 0ull : P.sig[v];
+    if (delta) delta[v] = d < 0 ? 0.0 : P.dout[v];
+  }
+}
+
+// --------------------------------------------------------- reachability
+
+__global__ void k_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t root) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    bitmap[root >> 5] |= 1u << (root & 31);
+    q[0] = root;
+    *qn = 1u;
+  }
+}
+
+// One BFS level on a CSR, weights ignored: a wavefront per frontier vertex,
+// lanes over arcs, first setter of a bit appends the vertex.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap,
+                                                       const int32_t *qin, const uint32_t *qin_n,
+                                                       int32_t *qout, uint32_t *qout_n) {
+  const int lane = lane_id();
+  const uint32_t count = *qin_n;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const int32_t v = qin[i];
+    const int64_t e0 = rp[v], e1 = rp[v + 1];
+    for (int64_t e = e0; e < e1; e += 64) {
+      const int64_t my = e + lane;
+      bool enq = false;
+      int32_t u = 0;
+      if (my < e1) {
+        u = col[my];
+        const uint32_t bit = 1u << (u & 31);
+        if (!(bitmap[u >> 5] & bit)) enq = !(atomicOr(&bitmap[u >> 5], bit) & bit);
+      }
+      const ull eb = __ballot(enq);
+      if (eb != 0ull) {
+        uint32_t p0 = 0;
+        if (lane == 0) p0 = atomicAdd(qout_n, (uint32_t)__popcll(eb));
+        p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+        if (enq) qout[p0 + lanes_below(eb)] = u;
+      }
+    }
+  }
+}
+
+__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------ launchers
+
+#define DISPATCH_BLOCK(L, KERNEL, ...)                                                     \
+  do {                                                                                     \
+    switch ((L).block) {                                                                   \
+      case 64: hipLaunchKernelGGL(KERNEL<64>, dim3((L).grid), dim3(64), 0, st, __VA_ARGS__); break;    \
+      case 128: hipLaunchKernelGGL(KERNEL<128>, dim3((L).grid), dim3(128), 0, st, __VA_ARGS__); break; \
+      case 512: hipLaunchKernelGGL(KERNEL<512>, dim3((L).grid), dim3(512), 0, st, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<256>, dim3((L).grid), dim3(256), 0, st, __VA_ARGS__); break;  \
+    }                                                                                      \
+  } while (0)
+
+hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const ull *masks0, int k,
+                             hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  const int grid = (k + 255) / 256;
+  hipLaunchKernelGGL(k_batch_init, dim3(grid), dim3(256), 0, st, S, items0, masks0, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_fwd_level, G, S, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_level(const DevGraph &G, const BatchState &S, int level, int ntgt, int full, Launch L,
+                            hipStream_t st) {
+  DISPATCH_BLOCK(L, k_bwd_level, G, S, level, ntgt, full);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_cleanup(const BatchState &S, uint64_t total, Launch L, hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_cleanup, dim3(L.grid), dim3(256), 0, st, S, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_export(const BatchState &S, int level, uint64_t begin, uint64_t count,
+                               const int32_t *lane_slot, uint64_t *dist, ull *sigma, double *delta, int64_t k,
+                               hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  uint64_t waves = count < 65536 ? count : 65536;
+  const int grid = (int)((waves * 64 + 255) / 256);
+  hipLaunchKernelGGL(k_batch_export, dim3(grid), dim3(256), 0, st, S, level, begin, count, lane_slot, dist,
+                     sigma, delta, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_init(const PlainState &P, int32_t s, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain_init, dim3(1), dim3(64), 0, st, P, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_fwd(const DevGraph &G, const PlainState &P, int level, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_plain_fwd, G, P, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_bwd(const DevGraph &G, const PlainState &P, int level, int32_t target, int only_target,
+                            Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_plain_bwd, G, P, level, target, only_target);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_cleanup(const PlainState &P, uint64_t total, hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  uint64_t g = (total + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_plain_cleanup, dim3((int)g), dim3(256), 0, st, P, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_export(const PlainState &P, uint64_t *dist, ull *sigma, double *delta,
+                               hipStream_t st) {
+  uint64_t g = ((uint64_t)P.n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_plain_export, dim3((int)g), dim3(256), 0, st, P, dist, sigma, delta);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_export(const PlainState &P, uint64_t total, uint64_t *dist, ull *sigma, double *delta,
+                               hipStream_t st) {
+  (void)total;
+  return launch_plain_export(P, dist, sigma, delta, st);
+}
+
+hipError_t launch_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t root, hipStream_t st) {
+  hipLaunchKernelGGL(k_reach_init, dim3(1), dim3(64), 0, st, bitmap, q, qn, root);
+  return hipGetLastError();
+}
+
+hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap, const int32_t *qin,
+                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_reach_level, rp, col, bitmap, qin, qin_n, qout, qout_n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_probe(const double *src, double *dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- targets
+
+__global__ void k_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
+    tgt_of[verts[i]] = set ? i : -1;
+}
+
+// Plain engine: distance and delta of each listed vertex.
+__global__ void k_plain_gather(PlainState P, const int32_t *verts, int k, int32_t *d_out, double *delta_out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const int32_t v = verts[i];
+    if (d_out) d_out[i] = P.d[v];
+    if (delta_out) delta_out[i] = P.d[v] < 0 ? 0.0 : P.dout[v];
+  }
+}
+
+hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set, hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_targets, dim3((k + 255) / 256), dim3(256), 0, st, tgt_of, verts, k, set);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_gather(const PlainState &P, const int32_t *verts, int k, int32_t *d_out,
+                               double *delta_out, hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plain_gather, dim3((k + 255) / 256), dim3(256), 0, st, P, verts, k, d_out, delta_out);
+  return hipGetLastError();
+}
+
+}  // namespace bcd

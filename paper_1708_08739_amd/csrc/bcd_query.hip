@@ -1,0 +1,857 @@
+// libbcd query layer: RV(r), batches of per-source passes, and the ABI
+// calls built on them (Alg.1, the set form of Section 4.2, Alg.2, and the
+// verification hooks).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bcd.h"
+#include "bcd_host_internal.h"
+
+namespace bcd {
+
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return hip_fail(_e, #expr); \
+  } while (0)
+
+#define STCHK(expr)              \
+  do {                           \
+    bcd_status _s = (expr);      \
+    if (_s != BCD_OK) return _s; \
+  } while (0)
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Neumaier-compensated sum in the order given (Alg.1 sums over RV(r) in
+// ascending vertex order; Alg.2 in draw order).
+static double compensated_sum(const double *x, size_t k, size_t stride) {
+  double s = 0.0, c = 0.0;
+  for (size_t i = 0; i < k; ++i) {
+    const double v = x[i * stride];
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+  }
+  return s + c;
+}
+
+// SplitMix64 output t for state `seed` (Steele, Lea and Flood 2014), and the
+// multiply-high map to [0, k).
+static inline uint64_t splitmix_at(uint64_t seed, uint64_t t) {
+  uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static inline uint64_t index_below(uint64_t x, uint64_t k) {
+  return (uint64_t)(((unsigned __int128)x * (unsigned __int128)k) >> 64);
+}
+
+// ------------------------------------------------------- reachability
+
+// Vertices reachable from `root` over the reverse graph (reverse = true,
+// Def.3: the vertices that reach root) or the graph itself.  Bit v of
+// `bits` is set for every vertex met, root included; *count excludes root.
+bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::vector<uint32_t> &bits,
+                     int64_t *count) {
+  STCHK(ws->ensure_reach());
+  const int64_t n = g->n;
+  const size_t words = (size_t)(n + 31) / 32;
+  hipStream_t st = ws->stream;
+  const int64_t *rp = reverse ? g->d_irp : g->d_rp;
+  const int32_t *col = reverse ? g->d_icol : g->d_col;
+  Launch L = g->launch();
+  HIPCHK(hipMemsetAsync(ws->bitmap, 0, words * sizeof(uint32_t), st));
+  HIPCHK(hipMemsetAsync(ws->rqn, 0, 2 * sizeof(uint32_t), st));
+  HIPCHK(launch_reach_init(ws->bitmap, ws->rq[0], &ws->rqn[0], root, st));
+  int cur = 0;
+  const int chunk = 8;
+  for (int64_t level = 0; level <= n;) {
+    for (int i = 0; i < chunk; ++i, ++level) {
+      HIPCHK(hipMemsetAsync(&ws->rqn[1 - cur], 0, sizeof(uint32_t), st));
+      HIPCHK(launch_reach_level(rp, col, ws->bitmap, ws->rq[cur], &ws->rqn[cur], ws->rq[1 - cur],
+                                &ws->rqn[1 - cur], L, st));
+      cur = 1 - cur;
+    }
+    uint32_t *h = reinterpret_cast<uint32_t *>(ws->h_misc);
+    HIPCHK(hipMemcpyAsync(h, &ws->rqn[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h[0] == 0) break;
+  }
+  HIPCHK(hipMemcpyAsync(ws->h_bitmap, ws->bitmap, words * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bits.assign(ws->h_bitmap, ws->h_bitmap + words);
+  int64_t c = 0;
+  for (size_t i = 0; i < words; ++i) c += __builtin_popcount(bits[i]);
+  *count = c - 1;
+  return BCD_OK;
+}
+
+static void bits_to_list(const std::vector<uint32_t> &bits, int64_t n, int32_t skip, std::vector<int32_t> &out) {
+  out.clear();
+  for (size_t wi = 0; wi < bits.size(); ++wi) {
+    uint32_t x = bits[wi];
+    while (x) {
+      const int b = __builtin_ctz(x);
+      x &= x - 1;
+      const int64_t v = (int64_t)wi * 32 + b;
+      if (v < n && v != skip) out.push_back((int32_t)v);
+    }
+  }
+}
+
+// --------------------------------------------------------- targets
+
+struct TargetMap {
+  Workspace *ws;
+  int32_t *d_verts = nullptr;
+  int k = 0;
+  bool set = false;
+  ~TargetMap() {
+    if (set) {
+      (void)launch_scatter_targets(ws->S.tgt_of, d_verts, k, 0, ws->stream);
+      (void)hipStreamSynchronize(ws->stream);
+    }
+    if (d_verts) (void)hipFree(d_verts);
+  }
+  bcd_status install(Workspace *w, const std::vector<int32_t> &tgt) {
+    ws = w;
+    k = (int)tgt.size();
+    if (k == 0) return BCD_OK;
+    if (hipMalloc((void **)&d_verts, (size_t)k * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      d_verts = nullptr;
+      return fail(BCD_ERR_OUT_OF_MEMORY, "target list allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(d_verts, tgt.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream));
+    HIPCHK(launch_scatter_targets(ws->S.tgt_of, d_verts, k, 1, ws->stream));
+    set = true;
+    return BCD_OK;
+  }
+};
+
+// -------------------------------------------------- batched engine
+
+struct BatchExport {
+  uint64_t *dist = nullptr;  // device [k][n]
+  unsigned long long *sigma = nullptr;
+  double *delta = nullptr;
+  int64_t k = 0;
+};
+
+struct ProfAcc {
+  int64_t launches[2] = {0, 0};
+  double ms[2] = {0, 0};
+};
+
+// One batch: `k` sources already staged in ws->h_items0 / h_masks0 (lane i
+// of the batch is group i/64, lane i%64).  Runs the forward levels until the
+// next level is empty, the backward levels down to the nearest target (or
+// level 0 when `full`), copies the per-lane target dependencies into
+// ws->h_res, and leaves the state clean for the next batch.
+static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool full, BatchExport *ex,
+                                ProfAcc *prof, bool *sigma_overflow) {
+  hipStream_t st = ws->stream;
+  const DevGraph D = g->dev();
+  const Launch L = g->launch();
+  const bool profiling = g->profiling.load();
+  const size_t G64 = (size_t)ws->G * kLanes;
+  HIPCHK(hipMemcpyAsync(ws->d_items0, ws->h_items0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ws->d_masks0, ws->h_masks0, (size_t)k * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                        st));
+  for (int attempt = 0;; ++attempt) {
+    ws->S.epoch += 1;
+    BatchState S = ws->S;  // kernel arguments: this batch's epoch and capacity
+    if (!ex) S.dout = nullptr;
+    uint32_t *hc = ws->h_cnt;
+    hc[kLevelChunkMax + 4] = (uint32_t)k;
+    HIPCHK(hipMemcpyAsync(&S.cnt[0], &hc[kLevelChunkMax + 4], sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    if (ntgt > 0) HIPCHK(hipMemsetAsync(S.res, 0, (size_t)ntgt * G64 * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
+    HIPCHK(launch_batch_init(S, ws->d_items0, ws->d_masks0, k, st));
+
+    // forward, in chunks of levels between host checks
+    std::vector<uint32_t> cnt;  // cnt[l] = items on level l
+    cnt.push_back((uint32_t)k);
+    int lmax = -1;
+    int level = 0;
+    int chunk = std::min(kLevelChunkMax, std::max(4, ws->last_depth + 2));
+    uint32_t flags_h[2] = {0, 0}, tmin_h = 0xFFFFFFFFu;
+    size_t ev = 0;
+    while (lmax < 0) {
+      const int first = level;
+      int launched = 0;
+      for (; launched < chunk && level <= g->n; ++launched, ++level) {
+        if (profiling) HIPCHK(hipEventRecord(ws->event_pair(ev).first, st));
+        HIPCHK(launch_fwd_level(D, S, level, L, st));
+        if (profiling) {
+          HIPCHK(hipEventRecord(ws->event_pair(ev).second, st));
+          ++ev;
+        }
+      }
+      HIPCHK(hipMemcpyAsync(hc, &S.cnt[first + 1], (size_t)launched * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      uint32_t *hm = reinterpret_cast<uint32_t *>(ws->h_misc);
+      HIPCHK(hipMemcpyAsync(hm, S.flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hm + 2, S.tmin, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      flags_h[0] = hm[0];
+      flags_h[1] = hm[1];
+      tmin_h = hm[2];
+      if (flags_h[1]) break;
+      for (int i = 0; i < launched; ++i) {
+        if (hc[i] == 0) {
+          lmax = first + i;
+          break;
+        }
+        cnt.push_back(hc[i]);
+      }
+      if (lmax < 0 && level > g->n) return fail(BCD_ERR_DEVICE, "forward pass did not terminate");
+      chunk = kLevelChunkMax;
+    }
+    if (flags_h[1]) {
+      // item list overflow: grow and redo this batch from a clean state
+      STCHK(ws->reset_batch_dense());
+      STCHK(ws->grow_items());
+      if (attempt > 8) return fail(BCD_ERR_OUT_OF_MEMORY, "frontier item list cannot grow further");
+      continue;
+    }
+    ws->last_depth = lmax;
+    if (flags_h[0]) *sigma_overflow = true;
+    const size_t fwd_events = ev;
+
+    // backward
+    int stop = -1;
+    if (full) stop = 0;
+    else if (ntgt > 0 && tmin_h != 0xFFFFFFFFu) stop = (int)tmin_h;
+    if (stop >= 0) {
+      for (int lv = lmax; lv >= stop; --lv) {
+        if (profiling) HIPCHK(hipEventRecord(ws->event_pair(ev).first, st));
+        HIPCHK(launch_bwd_level(D, S, lv, ntgt, full ? 1 : 0, L, st));
+        if (profiling) {
+          HIPCHK(hipEventRecord(ws->event_pair(ev).second, st));
+          ++ev;
+        }
+      }
+    }
+    uint64_t total = 0;
+    std::vector<uint64_t> off(cnt.size() + 1, 0);
+    for (size_t i = 0; i < cnt.size(); ++i) {
+      off[i + 1] = off[i] + cnt[i];
+      total += cnt[i];
+    }
+    if (ex) {
+      for (size_t lv = 0; lv < cnt.size(); ++lv)
+        HIPCHK(launch_batch_export(S, (int)lv, off[lv], cnt[lv], ws->d_lane_slot, ex->dist, ex->sigma, ex->delta,
+                                   ex->k, st));
+    }
+    if (ntgt > 0)
+      HIPCHK(hipMemcpyAsync(ws->h_res, S.res, (size_t)ntgt * G64 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_batch_cleanup(S, total, L, st));
+    HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (profiling && prof) {
+      for (size_t i = 0; i < ev; ++i) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ws->events[i].first, ws->events[i].second));
+        const int kind = i < fwd_events ? 0 : 1;
+        prof->ms[kind] += ms;
+        prof->launches[kind] += 1;
+      }
+    }
+    return BCD_OK;
+  }
+}
+
+static bcd_status collect_counters(Workspace *ws, uint64_t *ctr /*[C_COUNT]*/, uint64_t *dev_ctr) {
+  hipStream_t st = ws->stream;
+  HIPCHK(hipMemcpyAsync(ws->h_ctr, dev_ctr, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                        st));
+  HIPCHK(hipMemsetAsync(dev_ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < C_COUNT; ++k) ctr[k] = 0;
+  for (int s = 0; s < kCtrSlots; ++s)
+    for (int k = 0; k < C_COUNT; ++k) ctr[k] += ws->h_ctr[(size_t)s * C_COUNT + k];
+  return BCD_OK;
+}
+
+static void add_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr) {
+  // Algorithmic bytes (per (source, element) pair, independent of how the
+  // kernels share reads across sources):
+  //   forward : 32 per (source, vertex) + 8 per (source, arc) + 8 per (source, DAG arc)
+  //   backward: 32 per (source, vertex) + 8 per (source, arc) + 8 per (source, DAG arc)
+  const double fb = 32.0 * ctr[C_FWD_VPAIRS] + 8.0 * ctr[C_FWD_APAIRS] + 8.0 * ctr[C_FWD_DPAIRS];
+  const double bb = 32.0 * ctr[C_BWD_VPAIRS] + 8.0 * ctr[C_BWD_APAIRS] + 8.0 * ctr[C_BWD_DPAIRS];
+  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb);
+  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb);
+}
+
+static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
+                              const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out) {
+  const bcd_config cfg = g->config();
+  STCHK(ws->ensure_batch(cfg.groups));
+  const int ntgt = (int)tgt.size();
+  const size_t G64 = (size_t)ws->G * kLanes;
+  STCHK(ws->ensure_res((size_t)std::max(ntgt, 1) * G64));
+  TargetMap tm;
+  STCHK(tm.install(ws, tgt));
+  const size_t ns = src.size();
+  out.dep.assign(ns * (size_t)std::max(ntgt, 0), 0.0);
+  if (want_counters) out.counters.assign(ns * 3, 0);
+  out.width = want_counters ? 1 : (int32_t)G64;
+  ProfAcc prof;
+  bool ovf = false;
+  uint64_t tot[C_COUNT] = {0};
+  const size_t per = want_counters ? 1 : G64;  // counters per source need one source per batch
+  for (size_t b0 = 0; b0 < ns; b0 += per) {
+    const int k = (int)std::min(per, ns - b0);
+    for (int i = 0; i < k; ++i) {
+      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[b0 + i]);
+      ws->h_masks0[i] = 1ull << (i % kLanes);
+    }
+    STCHK(run_one_batch(g, ws, k, ntgt, false, nullptr, &prof, &ovf));
+    for (int i = 0; i < k; ++i)
+      for (int t = 0; t < ntgt; ++t) out.dep[(b0 + i) * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
+    if (want_counters) {
+      uint64_t c[C_COUNT];
+      STCHK(collect_counters(ws, c, ws->S.ctr));
+      out.counters[b0 * 3 + 0] = c[C_FWD_VPAIRS];
+      out.counters[b0 * 3 + 1] = c[C_FWD_APAIRS];
+      out.counters[b0 * 3 + 2] = c[C_FWD_DPAIRS];
+      for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
+    }
+  }
+  if (!want_counters) STCHK(collect_counters(ws, tot, ws->S.ctr));
+  out.te = tot[C_FWD_APAIRS];
+  out.reached = tot[C_FWD_VPAIRS];
+  out.dag = tot[C_FWD_DPAIRS];
+  if (g->profiling.load()) add_profile(g, prof, tot);
+  if (ovf) return fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+  return BCD_OK;
+}
+
+// ---------------------------------------------------- plain engine
+
+// One source through the plain kernels.  Targets' dependencies go to
+// dep[0..ntgt-1]; with `full`, the backward runs to level 0 and the whole
+// state can be exported before cleanup.
+static bcd_status run_plain_one(Graph *g, Workspace *ws, int32_t s, const int32_t *d_tgt, int ntgt,
+                                const std::vector<int32_t> &tgt, bool full, double *dep, uint64_t *dist,
+                                unsigned long long *sigma, double *delta, ProfAcc *prof, bool *ovf) {
+  PlainState &P = ws->P;
+  hipStream_t st = ws->stream;
+  const DevGraph D = g->dev();
+  const Launch L = g->launch();
+  const bool profiling = g->profiling.load();
+  HIPCHK(hipMemsetAsync(P.flags, 0, 4 * sizeof(uint32_t), st));
+  HIPCHK(launch_plain_init(P, s, st));
+  std::vector<uint32_t> cnt{1u};
+  int lmax = -1, level = 0;
+  int chunk = std::min(kLevelChunkMax, std::max(4, ws->last_depth + 2));
+  size_t ev = 0;
+  uint32_t *hc = ws->h_cnt;
+  while (lmax < 0) {
+    const int first = level;
+    int launched = 0;
+    for (; launched < chunk && level <= g->n; ++launched, ++level) {
+      if (profiling) HIPCHK(hipEventRecord(ws->event_pair(ev).first, st));
+      HIPCHK(launch_plain_fwd(D, P, level, L, st));
+      if (profiling) {
+        HIPCHK(hipEventRecord(ws->event_pair(ev).second, st));
+        ++ev;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(hc, &P.cnt[first + 1], (size_t)launched * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < launched; ++i) {
+      if (hc[i] == 0) {
+        lmax = first + i;
+        break;
+      }
+      cnt.push_back(hc[i]);
+    }
+    if (lmax < 0 && level > g->n) return fail(BCD_ERR_DEVICE, "forward pass did not terminate");
+    chunk = kLevelChunkMax;
+  }
+  ws->last_depth = lmax;
+  const size_t fwd_events = ev;
+  // distances of the targets decide where the backward may stop
+  int stop = full ? 0 : -1;
+  std::vector<int32_t> tdist(ntgt, -1);
+  if (!full && ntgt > 0) {
+    std::vector<int32_t> h(ntgt);
+    // gather distances through the export path of the plain state
+    int32_t *dbuf = nullptr;
+    if (hipMalloc((void **)&dbuf, (size_t)ntgt * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BCD_ERR_OUT_OF_MEMORY, "target distance buffer");
+    }
+    hipError_t e = launch_plain_gather(P, d_tgt, ntgt, dbuf, nullptr, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dbuf, (size_t)ntgt * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dbuf);
+    if (e != hipSuccess) return hip_fail(e, "target distances");
+    for (int t = 0; t < ntgt; ++t) {
+      tdist[t] = h[t];
+      if (h[t] > 0 && (stop < 0 || h[t] < stop)) stop = h[t];
+    }
+  }
+  if (stop >= 0) {
+    for (int lv = lmax; lv >= stop; --lv) {
+      if (profiling) HIPCHK(hipEventRecord(ws->event_pair(ev).first, st));
+      HIPCHK(launch_plain_bwd(D, P, lv, -1, 0, L, st));
+      if (profiling) {
+        HIPCHK(hipEventRecord(ws->event_pair(ev).second, st));
+        ++ev;
+      }
+    }
+  }
+  if (ntgt > 0 && dep) {
+    double *dbuf = nullptr;
+    if (hipMalloc((void **)&dbuf, (size_t)ntgt * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BCD_ERR_OUT_OF_MEMORY, "target dependency buffer");
+    }
+    std::vector<double> h(ntgt);
+    hipError_t e = launch_plain_gather(P, d_tgt, ntgt, nullptr, dbuf, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dbuf, (size_t)ntgt * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dbuf);
+    if (e != hipSuccess) return hip_fail(e, "target dependencies");
+    for (int t = 0; t < ntgt; ++t)
+      dep[t] = (tgt[t] == s || stop < 0 || (!full && tdist[t] <= 0)) ? 0.0 : h[t];
+  }
+  if (dist || sigma || delta) HIPCHK(launch_plain_export(P, 0, dist, sigma, delta, st));
+  uint64_t total = 0;
+  for (uint32_t c : cnt) total += c;
+  HIPCHK(launch_plain_cleanup(P, total, st));
+  HIPCHK(hipMemsetAsync(P.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
+  HIPCHK(hipMemcpyAsync(ws->h_misc, P.flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (reinterpret_cast<uint32_t *>(ws->h_misc)[0]) *ovf = true;
+  if (profiling && prof) {
+    for (size_t i = 0; i < ev; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ws->events[i].first, ws->events[i].second));
+      const int kind = i < fwd_events ? 0 : 1;
+      prof->ms[kind] += ms;
+      prof->launches[kind] += 1;
+    }
+  }
+  return BCD_OK;
+}
+
+static bcd_status run_plain(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
+                            const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out) {
+  STCHK(ws->ensure_plain());
+  const int ntgt = (int)tgt.size();
+  int32_t *d_tgt = nullptr;
+  if (ntgt > 0) {
+    if (hipMalloc((void **)&d_tgt, (size_t)ntgt * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BCD_ERR_OUT_OF_MEMORY, "target list");
+    }
+    hipError_t e = hipMemcpy(d_tgt, tgt.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d_tgt);
+      return hip_fail(e, "target upload");
+    }
+  }
+  const size_t ns = src.size();
+  out.dep.assign(ns * (size_t)ntgt, 0.0);
+  if (want_counters) out.counters.assign(ns * 3, 0);
+  out.width = 1;
+  ProfAcc prof;
+  bool ovf = false;
+  uint64_t tot[C_COUNT] = {0};
+  bcd_status rc = BCD_OK;
+  for (size_t i = 0; i < ns && rc == BCD_OK; ++i) {
+    rc = run_plain_one(g, ws, src[i], d_tgt, ntgt, tgt, false, out.dep.data() + i * ntgt, nullptr, nullptr, nullptr,
+                       &prof, &ovf);
+    if (rc == BCD_OK && want_counters) {
+      uint64_t c[C_COUNT];
+      rc = collect_counters(ws, c, ws->P.ctr);
+      out.counters[i * 3 + 0] = c[C_FWD_VPAIRS];
+      out.counters[i * 3 + 1] = c[C_FWD_APAIRS];
+      out.counters[i * 3 + 2] = c[C_FWD_DPAIRS];
+      for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
+    }
+  }
+  if (d_tgt) (void)hipFree(d_tgt);
+  if (rc != BCD_OK) return rc;
+  if (!want_counters) STCHK(collect_counters(ws, tot, ws->P.ctr));
+  out.te = tot[C_FWD_APAIRS];
+  out.reached = tot[C_FWD_VPAIRS];
+  out.dag = tot[C_FWD_DPAIRS];
+  if (g->profiling.load()) add_profile(g, prof, tot);
+  if (ovf) return fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+  return BCD_OK;
+}
+
+bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
+                       bool want_counters, SourceRun &out) {
+  if (g->weighted) return run_weighted(g, ws, src, tgt, want_counters, out);
+  if (g->config().engine == BCD_ENGINE_PLAIN) return run_plain(g, ws, src, tgt, want_counters, out);
+  return run_batched(g, ws, src, tgt, want_counters, out);
+}
+
+}  // namespace bcd
+
+using namespace bcd;
+
+// ------------------------------------------------------------------ ABI
+
+static bcd_status lease_ws(Graph *g, Lease &ls) {
+  if (!ls.ok()) return fail(BCD_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+  return ls->init_common(g);
+}
+
+extern "C" {
+
+bcd_status bcd_rv(const bcd_graph *gh, bcd_vid r, bcd_vid *out, int64_t cap, int64_t *count) {
+  if (!gh || !count) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
+  if (out && cap < 0) return fail(BCD_ERR_INVALID_ARG, "cap < 0");
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  std::vector<uint32_t> bits;
+  int64_t k = 0;
+  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+  if (out && k > cap) {
+    *count = k;
+    return fail(BCD_ERR_BUFFER_TOO_SMALL, "RV(r) has " + std::to_string(k) + " vertices");
+  }
+  if (out) {
+    std::vector<int32_t> list;
+    bits_to_list(bits, g->n, r, list);
+    std::copy(list.begin(), list.end(), out);
+  }
+  *count = k;
+  return BCD_OK;
+}
+
+bcd_status bcd_bc_exact(const bcd_graph *gh, bcd_vid r, double *bc, bcd_stats *st) {
+  if (!gh || !bc) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
+  bcd_stats s{};
+  s.fr_size = -1;
+  if (g->outdeg(r) == 0) {  // Prop.1
+    s.rv_size = -1;
+    *bc = 0.0;
+    if (st) *st = s;
+    return BCD_OK;
+  }
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  const double t0 = now_s();
+  std::vector<uint32_t> bits;
+  int64_t k = 0;
+  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+  std::vector<int32_t> rv;
+  bits_to_list(bits, g->n, r, rv);
+  const double t1 = now_s();
+  SourceRun run;
+  STCHK(run_sources(g, ls.w.get(), rv, std::vector<int32_t>{r}, false, run));
+  const double v = compensated_sum(run.dep.data(), rv.size(), 1);
+  const double t2 = now_s();
+  s.rv_size = k;
+  s.distinct_sources = (int64_t)rv.size();
+  s.traversed_edges = run.te;
+  s.reached = run.reached;
+  s.dag_arcs = run.dag;
+  s.t_rv_s = t1 - t0;
+  s.t_bc_s = t2 - t1;
+  s.batch_width = run.width;
+  *bc = v;
+  if (st) *st = s;
+  return BCD_OK;
+}
+
+bcd_status bcd_bc_set(const bcd_graph *gh, const bcd_vid *rs, int64_t l, double *bc, bcd_stats *st) {
+  if (!gh || !rs || !bc || l <= 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  for (int64_t i = 0; i < l; ++i)
+    if (rs[i] < 0 || rs[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "target out of range");
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  const double t0 = now_s();
+  // distinct targets, then D = union of RV(r_i) over targets with out-degree > 0
+  std::vector<int32_t> tg(rs, rs + l);
+  std::sort(tg.begin(), tg.end());
+  tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
+  std::vector<uint32_t> uni((size_t)(g->n + 31) / 32, 0u), bits;
+  for (int32_t r : tg) {
+    if (g->outdeg(r) == 0) continue;
+    int64_t k = 0;
+    STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+    bits[(size_t)r >> 5] &= ~(1u << (r & 31));
+    for (size_t i = 0; i < uni.size(); ++i) uni[i] |= bits[i];
+  }
+  std::vector<int32_t> D;
+  bits_to_list(uni, g->n, -1, D);
+  const double t1 = now_s();
+  SourceRun run;
+  STCHK(run_sources(g, ls.w.get(), D, tg, false, run));
+  std::vector<double> per(tg.size());
+  for (size_t t = 0; t < tg.size(); ++t)
+    per[t] = g->outdeg(tg[t]) == 0 ? 0.0 : compensated_sum(run.dep.data() + t, D.size(), tg.size());
+  for (int64_t i = 0; i < l; ++i) {
+    const size_t t = (size_t)(std::lower_bound(tg.begin(), tg.end(), rs[i]) - tg.begin());
+    bc[i] = per[t];
+  }
+  if (st) {
+    bcd_stats s{};
+    s.rv_size = (int64_t)D.size();
+    s.fr_size = -1;
+    s.distinct_sources = (int64_t)D.size();
+    s.traversed_edges = run.te;
+    s.reached = run.reached;
+    s.dag_arcs = run.dag;
+    s.t_rv_s = t1 - t0;
+    s.t_bc_s = now_s() - t1;
+    s.batch_width = run.width;
+    *st = s;
+  }
+  return BCD_OK;
+}
+
+bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_params *p, double *bc, bcd_stats *st) {
+  if (!gh || !p || !bc) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
+  if (p->T_override <= 0) {
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(BCD_ERR_INVALID_ARG, "eps must be > 0");
+    if (!(p->delta > 0.0 && p->delta < 1.0)) return fail(BCD_ERR_INVALID_ARG, "delta must be in (0,1)");
+  }
+  bcd_stats s{};
+  s.fr_size = -1;
+  if (g->outdeg(r) == 0) {  // Prop.1
+    s.rv_size = -1;
+    *bc = 0.0;
+    if (st) *st = s;
+    return BCD_OK;
+  }
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  const double t0 = now_s();
+  std::vector<uint32_t> bits;
+  int64_t k = 0;
+  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+  std::vector<int32_t> rv;
+  bits_to_list(bits, g->n, r, rv);
+  s.rv_size = k;
+  int64_t T = p->T_override;
+  if (T <= 0) {
+    double K = (double)(g->n - 2);
+    if (!(p->flags & BCD_K_TRIVIAL)) {
+      int64_t fr = 0;
+      std::vector<uint32_t> fb;
+      STCHK(reach_set(g, ls.w.get(), r, false, fb, &fr));
+      s.fr_size = fr;
+      K = (double)fr;
+    }
+    const double eps_abs = (p->flags & BCD_EPS_ABSOLUTE) ? p->eps : p->eps * (double)g->n * (double)(g->n - 1);
+    STCHK(bcd_sample_count(eps_abs, p->delta, K, k, &T));
+  }
+  s.samples = T;
+  const double t1 = now_s();
+  if (k == 0) {
+    *bc = 0.0;
+    s.t_rv_s = t1 - t0;
+    if (st) *st = s;
+    return BCD_OK;
+  }
+  if (T >= k && !(p->flags & BCD_NO_EXACT_FALLBACK)) {
+    SourceRun run;
+    STCHK(run_sources(g, ls.w.get(), rv, std::vector<int32_t>{r}, false, run));
+    *bc = compensated_sum(run.dep.data(), rv.size(), 1);
+    s.ran_exact = 1;
+    s.distinct_sources = (int64_t)rv.size();
+    s.traversed_edges = run.te;
+    s.reached = run.reached;
+    s.dag_arcs = run.dag;
+    s.batch_width = run.width;
+  } else {
+    if (T > (int64_t)1 << 40) return fail(BCD_ERR_UNSUPPORTED, "sample count too large to draw");
+    // draws in order; each distinct source computed once
+    std::vector<int64_t> slot((size_t)k, -1);
+    std::vector<int32_t> uniq;
+    std::vector<int64_t> draw((size_t)T);
+    for (int64_t t = 0; t < T; ++t) {
+      const uint64_t idx = index_below(splitmix_at(p->seed, (uint64_t)t), (uint64_t)k);
+      if (slot[idx] < 0) {
+        slot[idx] = (int64_t)uniq.size();
+        uniq.push_back(rv[idx]);
+      }
+      draw[(size_t)t] = slot[idx];
+    }
+    SourceRun run;
+    STCHK(run_sources(g, ls.w.get(), uniq, std::vector<int32_t>{r}, false, run));
+    std::vector<double> seq((size_t)T);
+    for (int64_t t = 0; t < T; ++t) seq[(size_t)t] = run.dep[(size_t)draw[(size_t)t]];
+    *bc = compensated_sum(seq.data(), (size_t)T, 1) * (double)k / (double)T;
+    s.distinct_sources = (int64_t)uniq.size();
+    s.traversed_edges = run.te;
+    s.reached = run.reached;
+    s.dag_arcs = run.dag;
+    s.batch_width = run.width;
+  }
+  s.t_rv_s = t1 - t0;
+  s.t_bc_s = now_s() - t1;
+  if (st) *st = s;
+  return BCD_OK;
+}
+
+bcd_status bcd_dependencies(const bcd_graph *gh, bcd_vid r, const bcd_vid *sources, int64_t k, double *dep,
+                            uint64_t *counters) {
+  if (!gh || (k > 0 && (!sources || !dep)) || k < 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
+  for (int64_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "source out of range");
+  if (k == 0) return BCD_OK;
+  // distinct sources, mapped back to positions
+  std::vector<int32_t> uniq(sources, sources + k);
+  std::sort(uniq.begin(), uniq.end());
+  uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  SourceRun run;
+  STCHK(run_sources(g, ls.w.get(), uniq, std::vector<int32_t>{r}, counters != nullptr, run));
+  for (int64_t i = 0; i < k; ++i) {
+    const size_t u = (size_t)(std::lower_bound(uniq.begin(), uniq.end(), sources[i]) - uniq.begin());
+    dep[i] = uniq[u] == r ? 0.0 : run.dep[u];
+    if (counters)
+      for (int j = 0; j < 3; ++j) counters[i * 3 + j] = run.counters[u * 3 + j];
+  }
+  return BCD_OK;
+}
+
+bcd_status bcd_multi_source_pass(const bcd_graph *gh, const bcd_vid *sources, int64_t k, uint64_t *dist,
+                                 uint64_t *sigma, double *delta) {
+  if (!gh || !sources || k <= 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (g->weighted) return multi_source_pass_weighted(g, sources, k, dist, sigma, delta);
+  const bcd_config cfg = g->config();
+  if (k > (int64_t)cfg.groups * kLanes) return fail(BCD_ERR_INVALID_ARG, "k exceeds the batch width");
+  for (int64_t i = 0; i < k; ++i) {
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "source out of range");
+    for (int64_t j = 0; j < i; ++j)
+      if (sources[j] == sources[i] && i / kLanes == j / kLanes) return fail(BCD_ERR_INVALID_ARG, "repeated source");
+  }
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  Workspace *ws = ls.w.get();
+  STCHK(ws->ensure_batch(cfg.groups));
+  STCHK(ws->ensure_dout());
+  const size_t G64 = (size_t)ws->G * kLanes;
+  const size_t kn = (size_t)k * (size_t)g->n;
+  BatchExport ex;
+  ex.k = k;
+  uint64_t *dd = nullptr;
+  unsigned long long *ds = nullptr;
+  double *dl = nullptr;
+  auto cleanup = [&]() {
+    if (dd) (void)hipFree(dd);
+    if (ds) (void)hipFree(ds);
+    if (dl) (void)hipFree(dl);
+  };
+  if (hipMalloc((void **)&dd, kn * 8) != hipSuccess || hipMalloc((void **)&ds, kn * 8) != hipSuccess ||
+      hipMalloc((void **)&dl, kn * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(BCD_ERR_OUT_OF_MEMORY, "export buffers");
+  }
+  hipStream_t st = ws->stream;
+  std::vector<int32_t> slot(G64, -1);
+  for (int64_t i = 0; i < k; ++i) slot[(size_t)i] = (int32_t)i;
+  hipError_t e = hipMemcpyAsync(ws->d_lane_slot, slot.data(), G64 * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(dd, 0xFF, kn * 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(ds, 0, kn * 8, st);
+  if (e == hipSuccess) e = hipMemsetAsync(dl, 0, kn * 8, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "export setup");
+  }
+  for (int64_t i = 0; i < k; ++i) {
+    ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)sources[i]);
+    ws->h_masks0[i] = 1ull << (i % kLanes);
+  }
+  ex.dist = dd;
+  ex.sigma = ds;
+  ex.delta = dl;
+  bool ovf = false;
+  ProfAcc prof;
+  bcd_status rc = run_one_batch(g, ws, (int)k, 0, true, &ex, &prof, &ovf);
+  if (rc == BCD_OK) {
+    e = hipSuccess;
+    if (dist) e = hipMemcpy(dist, dd, kn * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sigma) e = hipMemcpy(sigma, ds, kn * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && delta) e = hipMemcpy(delta, dl, kn * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "export copy");
+  }
+  cleanup();
+  uint64_t c[C_COUNT];
+  if (rc == BCD_OK) rc = collect_counters(ws, c, ws->S.ctr);
+  if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+  return rc;
+}
+
+bcd_status bcd_source_pass(const bcd_graph *gh, bcd_vid s, uint64_t *dist, uint64_t *sigma, double *delta) {
+  if (!gh) return fail(BCD_ERR_INVALID_ARG, "graph is NULL");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (s < 0 || s >= g->n) return fail(BCD_ERR_INVALID_ARG, "s out of range");
+  if (g->weighted || g->config().engine != BCD_ENGINE_PLAIN) return bcd_multi_source_pass(gh, &s, 1, dist, sigma, delta);
+  Lease ls(g);
+  STCHK(lease_ws(g, ls));
+  Workspace *ws = ls.w.get();
+  STCHK(ws->ensure_plain());
+  const size_t n = (size_t)g->n;
+  uint64_t *dd = nullptr;
+  unsigned long long *ds = nullptr;
+  double *dl = nullptr;
+  auto cleanup = [&]() {
+    if (dd) (void)hipFree(dd);
+    if (ds) (void)hipFree(ds);
+    if (dl) (void)hipFree(dl);
+  };
+  if (hipMalloc((void **)&dd, n * 8) != hipSuccess || hipMalloc((void **)&ds, n * 8) != hipSuccess ||
+      hipMalloc((void **)&dl, n * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(BCD_ERR_OUT_OF_MEMORY, "export buffers");
+  }
+  bool ovf = false;
+  ProfAcc prof;
+  std::vector<int32_t> none;
+  bcd_status rc = run_plain_one(g, ws, s, nullptr, 0, none, true, nullptr, dd, ds, dl, &prof, &ovf);
+  if (rc == BCD_OK) {
+    hipError_t e = hipSuccess;
+    if (dist) e = hipMemcpy(dist, dd, n * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sigma) e = hipMemcpy(sigma, ds, n * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && delta) e = hipMemcpy(delta, dl, n * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "export copy");
+  }
+  cleanup();
+  uint64_t c[C_COUNT];
+  if (rc == BCD_OK) rc = collect_counters(ws, c, ws->P.ctr);
+  if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/bcd.h declares, and every check that happens before the
+device is touched behaves as documented."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1708_08739_amd import bcd
+from paper_1708_08739_amd import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(bcd_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return bcd.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "bcd_bc_exact" in names and "bcd_rv" in names and "bcd_bc_sampled" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    for name in bcd.SIGNATURES:
+        assert name in names, name
+
+
+def test_status_strings(lib):
+    for code in range(10):
+        s = lib.bcd_status_string(code).decode()
+        assert s and s != "unknown status"
+    assert lib.bcd_status_string(99).decode() == "unknown status"
+
+
+def test_sample_count_eq8(lib):
+    # Eq.(8) values worked by hand in tests/golden/sample_count_eq8.txt
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "sample_count_eq8.txt"))
+            if l.strip() and not l.startswith("#")]
+    for eps, delta, K, rv, T in rows:
+        assert bcd.bcd_sample_count(float(eps), float(delta), float(K), int(rv)) == int(T)
+    assert bcd.bcd_sample_count(1e-9, 0.1, 1e6, 10 ** 7) == 2 ** 63 - 1
+    for bad in [(0.0, 0.1, 1, 1), (1.0, 0.0, 1, 1), (1.0, 1.0, 1, 1), (1.0, 0.5, -1, 1), (1.0, 0.5, 1, -1)]:
+        with pytest.raises(bcd.BcdError) as e:
+            bcd.bcd_sample_count(*bad)
+        assert e.value.code == bcd.BCD_ERR_INVALID_ARG
+
+
+def _load(n, m, rp, col, w=None):
+    L = bcd.load()
+    h = C.c_void_p()
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    w = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
+    rc = L.bcd_graph_load_csr(n, m, rp.ctypes.data, col.ctypes.data if col.size else None,
+                              None if w is None else w.ctypes.data, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("rp0", bcd.BCD_ERR_BAD_GRAPH), ("rpn", bcd.BCD_ERR_BAD_GRAPH), ("decreasing", bcd.BCD_ERR_BAD_GRAPH),
+    ("col_range", bcd.BCD_ERR_BAD_GRAPH), ("self_loop", bcd.BCD_ERR_BAD_GRAPH),
+    ("repeat", bcd.BCD_ERR_BAD_GRAPH), ("unsorted", bcd.BCD_ERR_BAD_GRAPH),
+    ("zero_weight", bcd.BCD_ERR_BAD_GRAPH), ("n0", bcd.BCD_ERR_INVALID_ARG),
+    ("neg_m", bcd.BCD_ERR_INVALID_ARG),
+])
+def test_graph_validation_before_device(case, expect):
+    """Malformed CSR is rejected on the host, before any device call."""
+    n, rp, col, w = 3, [0, 2, 3, 3], [1, 2, 0], None
+    m = 3
+    if case == "rp0":
+        rp = [1, 2, 3, 3]
+    elif case == "rpn":
+        rp = [0, 2, 3, 2]
+    elif case == "decreasing":
+        rp = [0, 2, 1, 3]
+    elif case == "col_range":
+        col = [1, 3, 0]
+    elif case == "self_loop":
+        col = [0, 2, 0]
+    elif case == "repeat":
+        col = [2, 2, 0]
+    elif case == "unsorted":
+        col = [2, 1, 0]
+    elif case == "zero_weight":
+        w = [1, 0, 1]
+    elif case == "n0":
+        n = 0
+    elif case == "neg_m":
+        m = -1
+    rc, h = _load(n, m, rp, col, w)
+    assert rc == expect, (case, rc, bcd.last_error())
+    assert h.value is None
+
+
+def test_null_arguments(lib):
+    assert lib.bcd_graph_load_csr(3, 0, None, None, None, None) == bcd.BCD_ERR_INVALID_ARG
+    assert lib.bcd_bc_exact(None, 0, None, None) == bcd.BCD_ERR_INVALID_ARG
+    assert lib.bcd_rv(None, 0, None, 0, None) == bcd.BCD_ERR_INVALID_ARG
+    assert lib.bcd_graph_free(None) == bcd.BCD_OK
+    assert lib.bcd_sample_count(1.0, 0.5, 1.0, 1, None) == bcd.BCD_ERR_INVALID_ARG
+    assert bcd.last_error()
+
+
+def test_valid_graph_without_device_reports_device_error():
+    """With no GPU, a well-formed graph fails with BCD_ERR_DEVICE (never a
+    silent CPU path)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    g = gg.directed_path(5)
+    rc, h = _load(g.n, g.m, g.row_ptr, g.col)
+    assert rc == bcd.BCD_ERR_DEVICE

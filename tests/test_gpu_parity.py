@@ -1,0 +1,262 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Bars: distances and path counts bit-exact; dependencies and BC within
+1e-10 relative of the oracle (exactly 0.0 where the oracle gives 0.0);
+RV(r) as a set (and ascending list) bit-exact.  Sizes span several
+64-source column groups and ragged last groups; the largest cases use the
+launch configuration the bench times, compared on sampled sources.
+"""
+import numpy as np
+import pytest
+
+from paper_1708_08739_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+
+
+def close(a, b, rel=REL):
+    """|a - b| <= rel |b| elementwise, and a == 0 exactly where b == 0."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return bool(np.array_equal(a == 0, b == 0) and np.all(np.abs(a - b) <= rel * np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1708_08739_amd import bcd
+    bcd.load()
+    return bcd
+
+
+def dev(B, g, **cfg):
+    G = B.Graph.from_digraph(g)
+    if cfg:
+        G.set_config(**cfg)
+    return G
+
+
+# ------------------------------------------------------------ RV(r)
+
+def test_rv_matches_oracle(B, oracle):
+    g, q = gg.rmat16()
+    G = dev(B, g)
+    for r in q + gg.uniform_vertices(g.n, 6, seed=11, exclude=q):
+        print("rv r", r, flush=True)
+        got = G.rv(r)
+        want = oracle.rv(g, r)
+        assert np.array_equal(got, want), r
+
+
+def test_rv_buffer_too_small(B):
+    import ctypes as C
+    g = gg.directed_path(10)
+    G = dev(B, g)
+    out = np.empty(3, dtype=np.int32)
+    cnt = C.c_int64()
+    rc = B.load().bcd_rv(G.h, 9, out.ctypes.data, 3, C.byref(cnt))
+    assert rc == B.BCD_ERR_BUFFER_TOO_SMALL and cnt.value == 9
+
+
+# ------------------------------------------------- per-source passes
+
+SMALL = [
+    ("diamond9", lambda: gg.diamond_chain(9)[0]),
+    ("grid12", lambda: gg.grid_right_down(12, 12)),
+    ("cycle9", lambda: gg.directed_cycle(9)),
+    ("rand40", lambda: gg.random_small(40, 0.08, seed=3)),
+    ("er300", lambda: gg.erdos_renyi(300, 1500, seed=9)),
+    ("rmat10", lambda: gg.rmat(10, 8, seed=21)),
+]
+
+
+@pytest.mark.parametrize("name,make", SMALL)
+@pytest.mark.parametrize("engine", ["batched", "plain"])
+def test_source_pass_bitexact(B, oracle, name, make, engine):
+    g = make()
+    G = dev(B, g, engine=B.BCD_ENGINE_PLAIN if engine == "plain" else B.BCD_ENGINE_BATCHED)
+    for s in sorted(set([0, g.n - 1] + gg.uniform_vertices(g.n, min(6, g.n - 2), seed=4, exclude=[0, g.n - 1]))):
+        print(name, engine, "s", s, flush=True)
+        d, sg, dl = G.source_pass(s)
+        od, osg, odl, ovf, _ = oracle.source_pass(g, s)
+        assert not ovf
+        assert np.array_equal(d, od), (name, s)
+        assert np.array_equal(sg, osg), (name, s)
+        assert close(dl, odl), (name, s, np.max(np.abs(dl - odl)))
+
+
+@pytest.mark.parametrize("k", [1, 63, 64, 65, 130])
+def test_multi_source_pass_groups(B, oracle, k):
+    """k sources in one batch: spans 1..3 column groups with a ragged last one."""
+    g = gg.rmat(11, 8, seed=5)
+    G = dev(B, g, groups=3)
+    src = gg.uniform_vertices(g.n, k, seed=k)
+    print("multi k", k, flush=True)
+    d, sg, dl = G.multi_source_pass(src)
+    for i, s in enumerate(src):
+        od, osg, odl, ovf, _ = oracle.source_pass(g, s)
+        assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (k, i, s)
+        assert close(dl[i], odl), (k, i, s)
+
+
+def test_counters_match_oracle(B, oracle):
+    g = gg.rmat(10, 8, seed=3)
+    r = gg.top_out_degree(g, 1)[0]
+    src = oracle.rv(g, r)[:20]
+    for engine in (B.BCD_ENGINE_BATCHED, B.BCD_ENGINE_PLAIN):
+        G = dev(B, g, engine=engine)
+        dep, cnt = G.dependencies(r, src, counters=True)
+        odep, ocnt = oracle.dependencies(g, r, src)
+        assert np.array_equal(cnt, ocnt)
+        assert close(dep, odep)
+
+
+# -------------------------------------------------------------- BC(r)
+
+def test_bc_exact_er2000_both_engines(B, oracle):
+    g, (r,) = gg.er_2000()
+    want, ost = oracle.bc_exact(g, r)
+    vals = []
+    for cfg in [dict(engine=B.BCD_ENGINE_BATCHED, groups=1), dict(engine=B.BCD_ENGINE_BATCHED, groups=5),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=16, block=512),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=2, block=64, grid_mult=1),
+                dict(engine=B.BCD_ENGINE_PLAIN)]:
+        print("er2000", cfg, flush=True)
+        G = dev(B, g, **cfg)
+        got, st = G.bc_exact(r)
+        assert close(got, want), (cfg, got, want)
+        assert st["rv_size"] == ost["rv_size"]
+        assert st["traversed_edges"] == ost["te"]
+        assert st["reached"] == ost["reached"] and st["dag_arcs"] == ost["dag_arcs"]
+        vals.append(got)
+    # batched results do not depend on the batch width
+    assert vals[0] == vals[1] == vals[2] == vals[3]
+
+
+def test_bc_exact_repeatable(B):
+    g = gg.rmat(12, 8, seed=8)
+    G = dev(B, g)
+    r = gg.top_out_degree(g, 1)[0]
+    a = G.bc_exact(r)[0]
+    b = G.bc_exact(r)[0]
+    assert a == b
+
+
+def test_closed_forms(B):
+    n = 40
+    G = dev(B, gg.directed_path(n))
+    for i in range(0, n, 7):
+        assert G.bc_exact(i)[0] == i * (n - 1 - i)
+    G = dev(B, gg.directed_cycle(17))
+    assert G.bc_exact(5)[0] == 16 * 15 / 2
+    g, c = gg.in_out_star(7, 5)
+    assert dev(B, g).bc_exact(c)[0] == 35.0
+    k = 9
+    g, ids = gg.diamond_chain(k)
+    G = dev(B, g)
+    for i in range(1, k):
+        assert G.bc_exact(ids["x"][i])[0] == 9 * i * (k - i)
+        assert G.bc_exact(ids["a"][i])[0] == (3 * i - 2) * (3 * k - 3 * i + 1) / 2
+    G = dev(B, gg.complete_digraph(9))
+    v, st = G.bc_exact(3)
+    assert v == 0.0 and st["rv_size"] == 8
+    G = dev(B, gg.transitive_tournament(12))
+    v, st = G.bc_exact(11)
+    assert v == 0.0 and st["rv_size"] == -1
+
+
+def test_degenerate_graphs(B):
+    one = gg.Digraph(1, np.array([0, 0]), np.zeros(0, dtype=np.int32))
+    G = dev(B, one)
+    assert G.bc_exact(0)[0] == 0.0
+    assert G.rv(0).size == 0
+    empty = gg.Digraph(5, np.zeros(6, dtype=np.int64), np.zeros(0, dtype=np.int32))
+    G = dev(B, empty)
+    assert G.bc_exact(2)[0] == 0.0 and G.bc_exact(2)[1]["rv_size"] == -1
+    # in-degree 0 but out-degree > 0: RV empty
+    g = gg.directed_path(6)
+    v, st = dev(B, g).bc_exact(0)
+    assert v == 0.0 and st["rv_size"] == 0
+
+
+def test_sigma_overflow(B):
+    g, ids = gg.diamond_chain(63)
+    G = dev(B, g)
+    assert G.bc_exact(ids["x"][31])[0] == 9 * 31 * 32
+    d, sg, _ = G.source_pass(0)
+    assert int(sg[ids["x"][63]]) == 1 << 63
+    g64, ids64 = gg.diamond_chain(64)
+    for engine in (B.BCD_ENGINE_BATCHED, B.BCD_ENGINE_PLAIN):
+        G = dev(B, g64, engine=engine)
+        with pytest.raises(B.BcdError) as e:
+            G.bc_exact(ids64["x"][40])
+        assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW
+    G = dev(B, gg.grid_right_down(35, 35))
+    with pytest.raises(B.BcdError) as e:
+        G.source_pass(0)
+    assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW
+    G = dev(B, gg.grid_right_down(34, 34))
+    d, sg, _ = G.source_pass(0)
+    import math
+    assert int(sg[33 * 34 + 33]) == math.comb(66, 33)
+
+
+def test_bc_set_and_identity(B, oracle):
+    g = gg.rmat(10, 8, seed=23)
+    rs = gg.queries_top_and_random(g, seed=9, top=3, rnd=4)
+    rs = rs + [rs[1]]
+    G = dev(B, g)
+    got, st = G.bc_set(rs)
+    want, ost = oracle.bc_set(g, rs)
+    assert close(got, want)
+    assert st["distinct_sources"] == ost["distinct_sources"] and st["traversed_edges"] == ost["te"]
+    # sum of BC over all vertices = sum over reachable pairs of (d - 1)
+    g2 = gg.erdos_renyi(120, 400, seed=12)
+    G2 = dev(B, g2, groups=1)
+    allbc, _ = G2.bc_set(list(range(g2.n)))
+    obc, _ = oracle.bc_set(g2, list(range(g2.n)))
+    assert close(allbc, obc)
+
+
+def test_bc_sampled_matches_oracle(B, oracle):
+    g = gg.rmat(12, 8, seed=7)
+    r = gg.top_out_degree(g, 1)[0]
+    G = dev(B, g)
+    for T, seed in [(50, 1), (333, 77), (1, 5)]:
+        got, st = G.bc_sampled(r, T=T, seed=seed, flags=B.BCD_NO_EXACT_FALLBACK)
+        want, ost = oracle.bc_sampled(g, r, T, seed)
+        assert close(got, want), (T, seed)
+        assert st["samples"] == T and st["distinct_sources"] == ost["distinct_sources"]
+    # Eq.(8) with K = #FR, normalised eps; T >= |RV| falls back to the exact sum
+    got, st = G.bc_sampled(r, eps=0.01, delta=0.1, seed=3)
+    K = oracle.fr_count(g, r)
+    T = oracle.sample_count(0.01 * g.n * (g.n - 1), 0.1, K, st["rv_size"])
+    assert st["samples"] == T and st["fr_size"] == K
+    if T >= st["rv_size"]:
+        assert st["ran_exact"] == 1 and close(got, oracle.bc_exact(g, r)[0])
+
+
+# ------------------------------------------- full-size R-MAT scale 16
+
+def test_rmat16_sampled_sources_bench_config(B, oracle):
+    """R-MAT scale 16, edge factor 8, in the bench's launch configuration:
+    per-source dependencies on 96 seeded sources of each query's RV(r)
+    (spanning two column groups), and one whole query end to end."""
+    g, q = gg.rmat16()
+    G = dev(B, g)
+    for r in q:
+        rv = oracle.rv(g, r)
+        if rv.size == 0:
+            got, st = G.bc_exact(r)
+            assert got == 0.0
+            continue
+        pick = rv[np.sort(np.unique(gg.below(gg.stream(r, 0, 96), rv.size).astype(np.int64)))]
+        print("rmat16 r", r, "sources", pick.size, flush=True)
+        dep = G.dependencies(r, pick)
+        odep, _ = oracle.dependencies(g, r, pick)
+        assert close(dep, odep), r
+    r = q[0]
+    got, st = G.bc_exact(r)
+    want, ost = oracle.bc_exact(g, r)
+    assert close(got, want) and st["traversed_edges"] == ost["te"]
