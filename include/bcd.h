@@ -203,6 +203,64 @@ bcd_status bcd_profile_reset(bcd_graph *g);
  * plain copy of `bytes` bytes, best of `reps`. */
 bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps);
 
+/* -------------------------------------------------------------- serving
+ * A request loop for many BC(r) queries on one resident graph (the calls of
+ * Alg.1, Alg.2 and the Section 4.2 set form, as above).  Queries are admitted
+ * in arrival order while their device result buffers fit the HBM budget; the
+ * sources of all admitted queries are packed into shared batches (a source
+ * needed by several queries is computed once), so queries that arrive while
+ * others run join the next batches and their work overlaps on the device.
+ * Every result is bit-identical to the same call made alone. */
+
+typedef struct bcd_server_config {
+  uint64_t hbm_budget_bytes; /* device bytes for workspaces + per-query buffers; 0 = 64 GiB */
+  int32_t workers;           /* concurrent batches (one stream each), >= 1; 0 = 2 */
+  int32_t groups;            /* 64-source column groups per batch; 0 = graph's configured value */
+  int32_t queue_capacity;    /* max queries submitted and not yet polled; 0 = 4096 */
+  int32_t reserved;
+} bcd_server_config;
+
+#define BCD_QUERY_EXACT 0   /* bcd_bc_exact(r) */
+#define BCD_QUERY_SAMPLED 1 /* bcd_bc_sampled(r, params) */
+#define BCD_QUERY_SET 2     /* bcd_bc_set(rs, l): bc_out receives l values */
+
+typedef struct bcd_query {
+  int32_t kind;              /* BCD_QUERY_* */
+  bcd_vid r;                 /* EXACT, SAMPLED */
+  const bcd_vid *rs;         /* SET: l targets, copied at submit */
+  int64_t l;
+  bcd_sample_params params;  /* SAMPLED */
+  double *bc_out;            /* SET: caller buffer of l doubles, written before the result is
+                                returned by bcd_server_poll; must stay valid until then */
+  uint64_t tag;              /* opaque, echoed back */
+} bcd_query;
+
+typedef struct bcd_result {
+  uint64_t ticket;
+  uint64_t tag;
+  int32_t status;            /* bcd_status of the query */
+  int32_t kind;
+  double bc;                 /* EXACT / SAMPLED value (SET: first target's value) */
+  bcd_stats stats;
+  double t_arrive_s;         /* submit time, seconds on the library's steady clock */
+  double t_admit_s;          /* admission (RV done, buffers reserved) */
+  double t_done_s;           /* result reduced and queued for poll */
+} bcd_result;
+
+/* Start a server on a loaded graph; the graph must outlive the server. */
+bcd_status bcd_server_create(const bcd_graph *g, const bcd_server_config *cfg, bcd_server **out);
+/* Enqueue one query (non-blocking).  *ticket identifies its result.  Errors:
+ * INVALID_ARG (bad query), AGAIN (queue_capacity queries outstanding). */
+bcd_status bcd_server_submit(bcd_server *s, const bcd_query *q, uint64_t *ticket);
+/* Collect up to cap finished results into out[0 .. *n_out-1], waiting up to
+ * timeout_ns for the first one (0 = do not wait, < 0 = wait forever).
+ * Returns AGAIN if none finished in time. */
+bcd_status bcd_server_poll(bcd_server *s, bcd_result *out, int32_t cap, int32_t *n_out, int64_t timeout_ns);
+/* Library steady-clock time in seconds (the clock of the t_* fields). */
+double bcd_server_now(void);
+/* Stop: queued queries finish with CANCELLED, running batches drain.  NULL is a no-op. */
+bcd_status bcd_server_destroy(bcd_server *s);
+
 #ifdef __cplusplus
 }
 #endif

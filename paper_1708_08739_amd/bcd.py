@@ -63,6 +63,27 @@ class KernelProfile(C.Structure):
                 ("vertex_pairs", C.c_uint64), ("arc_pairs", C.c_uint64), ("dag_pairs", C.c_uint64)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("workers", C.c_int32), ("groups", C.c_int32),
+                ("queue_capacity", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Query(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("r", C.c_int32), ("rs", C.c_void_p), ("l", C.c_int64),
+                ("params", SampleParams), ("bc_out", C.c_void_p), ("tag", C.c_uint64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int32), ("kind", C.c_int32),
+                ("bc", C.c_double), ("stats", Stats), ("t_arrive_s", C.c_double), ("t_admit_s", C.c_double),
+                ("t_done_s", C.c_double)]
+
+
+BCD_QUERY_EXACT = 0
+BCD_QUERY_SAMPLED = 1
+BCD_QUERY_SET = 2
+
+
 class BcdError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         super().__init__(f"{where}: {STATUS_NAMES.get(code, code)} ({detail})")
@@ -96,6 +117,10 @@ SIGNATURES = {
     "bcd_profile_get": [_p, _i32, C.POINTER(KernelProfile)],
     "bcd_profile_reset": [_p],
     "bcd_bandwidth_probe": [_i64, _i32, C.POINTER(_d)],
+    "bcd_server_create": [_p, C.POINTER(ServerConfig), C.POINTER(_p)],
+    "bcd_server_submit": [_p, C.POINTER(Query), C.POINTER(_u64)],
+    "bcd_server_poll": [_p, _p, _i32, C.POINTER(_i32), _i64],
+    "bcd_server_destroy": [_p],
 }
 OPTIONAL_SIGNATURES: dict = {}
 
@@ -121,6 +146,8 @@ def load(path: str | None = None):
         fn.restype = C.c_int
     L.bcd_status_string.argtypes = [C.c_int]
     L.bcd_status_string.restype = C.c_char_p
+    L.bcd_server_now.argtypes = []
+    L.bcd_server_now.restype = C.c_double
     L.bcd_last_error.argtypes = []
     L.bcd_last_error.restype = C.c_char_p
     _lib = L
@@ -272,3 +299,70 @@ class Graph:
         p = KernelProfile()
         check(load().bcd_profile_get(self.h, kind, C.byref(p)), "bcd_profile_get")
         return {k: getattr(p, k) for k, _ in p._fields_}
+
+
+class Server:
+    """Serving loop on a loaded ``Graph`` (``bcd_server_*``)."""
+
+    def __init__(self, graph: Graph, hbm_budget_bytes: int = 0, workers: int = 0, groups: int = 0,
+                 queue_capacity: int = 0):
+        self.graph = graph
+        cfg = ServerConfig(hbm_budget_bytes, workers, groups, queue_capacity, 0)
+        h = C.c_void_p()
+        check(load().bcd_server_create(graph.h, C.byref(cfg), C.byref(h)), "bcd_server_create")
+        self.h = h
+        self._keep: dict[int, tuple] = {}
+
+    def submit(self, kind: int, r: int = 0, rs=None, eps: float = 0.01, delta: float = 0.1, seed: int = 0,
+               flags: int = 0, T: int = 0, tag: int = 0) -> int:
+        q = Query()
+        q.kind = kind
+        q.r = r
+        keep = ()
+        if kind == BCD_QUERY_SET:
+            arr = np.ascontiguousarray(rs, dtype=np.int32)
+            out = np.zeros(arr.size, dtype=np.float64)
+            q.rs = arr.ctypes.data
+            q.l = arr.size
+            q.bc_out = out.ctypes.data
+            keep = (arr, out)
+        q.params = SampleParams(eps, delta, seed & 0xFFFFFFFFFFFFFFFF, flags, T)
+        q.tag = tag
+        t = C.c_uint64()
+        check(load().bcd_server_submit(self.h, C.byref(q), C.byref(t)), "bcd_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    def poll(self, cap: int = 64, timeout_s: float = -1.0) -> list[dict]:
+        buf = (Result * cap)()
+        n = C.c_int32()
+        ns = -1 if timeout_s < 0 else int(timeout_s * 1e9)
+        rc = load().bcd_server_poll(self.h, buf, cap, C.byref(n), ns)
+        if rc == BCD_ERR_AGAIN:
+            return []
+        check(rc, "bcd_server_poll")
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            d = {k: getattr(r, k) for k, _ in Result._fields_ if k != "stats"}
+            d["stats"] = r.stats.as_dict()
+            keep = self._keep.pop(r.ticket, ())
+            if keep:
+                d["bcs"] = keep[1].copy()
+            out.append(d)
+        return out
+
+    @staticmethod
+    def now() -> float:
+        return load().bcd_server_now()
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().bcd_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

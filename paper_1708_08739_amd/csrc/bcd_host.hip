@@ -36,17 +36,6 @@ bcd_status hip_fail(hipError_t e, const char *what) {
   return fail(BCD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCHK(expr)                                  \
-  do {                                                \
-    hipError_t _e = (expr);                           \
-    if (_e != hipSuccess) return hip_fail(_e, #expr); \
-  } while (0)
-
-#define STCHK(expr)                \
-  do {                             \
-    bcd_status _s = (expr);        \
-    if (_s != BCD_OK) return _s;   \
-  } while (0)
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -112,6 +101,7 @@ static void hfree(T *&p) {
 Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
+  release_weighted();
   dfree(S.sig);
   dfree(S.psi);
   dfree(S.dout);
@@ -128,6 +118,7 @@ void Workspace::release() {
   dfree(S.res);
   dfree(S.ctr);
   dfree(S.flags);
+  dfree(S.ovl);
   dfree(d_items0);
   dfree(d_masks0);
   dfree(d_lane_slot);
@@ -184,9 +175,11 @@ bcd_status Workspace::ensure_reach() {
 bcd_status Workspace::ensure_batch(int G_) {
   if (batch_ready && G == G_) return BCD_OK;
   if (batch_ready) {
+    release_weighted();
     dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.bt);
-    dfree(S.items); dfree(S.imask); dfree(S.tlev); dfree(S.res); dfree(d_items0); dfree(d_masks0);
-    dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0); hfree(h_res);
+    dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tlev); dfree(S.tmin);
+    dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.flags); dfree(S.ovl);
+    dfree(d_items0); dfree(d_masks0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0); hfree(h_res);
     batch_ready = false;
   }
   if ((uint64_t)G_ * (uint64_t)n >= (1ull << 32))
@@ -211,6 +204,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.tmin, 4));
   STCHK(dalloc(&S.tgt_of, (size_t)n));
   STCHK(dalloc(&S.flags, 4));
+  STCHK(dalloc(&S.ovl, (size_t)G));
   S.ctr_slots = kCtrSlots;
   STCHK(dalloc(&S.ctr, (size_t)kCtrSlots * C_COUNT));
   res_cap = (size_t)G * kLanes;

@@ -11,6 +11,19 @@
 #include "../../include/bcd.h"
 #include "bcd_internal.h"
 
+// Error propagation inside the host layer.
+#define HIPCHK(expr)                                  \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return hip_fail(_e, #expr); \
+  } while (0)
+
+#define STCHK(expr)              \
+  do {                           \
+    bcd_status _s = (expr);      \
+    if (_s != BCD_OK) return _s; \
+  } while (0)
+
 namespace bcd {
 
 constexpr int kCtrSlots = 16384;      // max workgroups of a traversal launch
@@ -72,6 +85,10 @@ struct Workspace {
   bcd_status grow_items();
   bcd_status reset_batch_dense();
   bcd_status ensure_plain();
+  bool weighted_ready = false;
+  int weighted_G = 0;
+  bcd_status ensure_weighted();
+  void release_weighted();
   std::pair<hipEvent_t, hipEvent_t> event_pair(size_t i);
 };
 
@@ -130,6 +147,15 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
                         const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
 bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t k, uint64_t *dist,
                                       uint64_t *sigma, double *delta);
+// One batch of `k` sources already staged in ws->h_items0 / h_masks0 with
+// ntgt targets installed in ws->S.tgt_of; per-lane target dependencies stay
+// in ws->S.res on the device; per-group overflow lanes go to ovl_out[G].
+bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
+bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
+double compensated_sum(const double *x, size_t k, size_t stride);
+uint64_t splitmix_at(uint64_t seed, uint64_t t);
+uint64_t index_below(uint64_t x, uint64_t k);
+void bits_to_list(const std::vector<uint32_t> &bits, int64_t n, int32_t skip, std::vector<int32_t> &out);
 bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
                        const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
 

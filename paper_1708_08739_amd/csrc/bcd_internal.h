@@ -25,7 +25,9 @@ enum Ctr {
   C_BWD_VPAIRS = 3,  // (source, vertex) pairs whose psi the backward kernel produced
   C_BWD_APAIRS = 4,  // (source, arc) pairs the backward kernel scanned
   C_BWD_DPAIRS = 5,  // (source, DAG arc) pairs the backward kernel accumulated
-  C_COUNT = 8
+  C_RLX_APAIRS = 6,  // (source, arc) relaxations of the weighted distance rounds (6..8)
+  C_SCRATCH = 9,     // unused slots for kernels that only report overflow (9..11)
+  C_COUNT = 12
 };
 
 // Device state of one batch of G column groups (64 sources each) over an
@@ -52,8 +54,17 @@ struct BatchState {
   double *res;               // [ntgt][G][64] delta of lane on target
   uint64_t *ctr;             // [grid][C_COUNT] per-workgroup counters
   uint32_t *flags;           // [4]: 0 sigma overflow, 1 item capacity exceeded
+  unsigned long long *ovl;   // [G] lanes whose sigma overflowed
   uint32_t epoch;
   int ctr_slots;
+  // weighted graphs only
+  uint32_t *wd;              // [G][n][64] distances, 0xFFFFFFFF unreached
+  uint32_t *wc;              // [G][n][64] shortest-path-DAG in-arcs not yet pushed
+  unsigned long long *chg;   // [2][G][n] lanes whose distance dropped (relaxation rounds)
+  uint32_t *bq;              // [2][G*n] relaxation round queues
+  uint32_t *bqn;             // [3] relaxation queue lengths (rotating)
+  uint32_t *rl;              // [G*n] items reached by any lane
+  uint32_t *rln;             // [1]
 };
 
 // Plain engine state (one source).
@@ -113,6 +124,23 @@ hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *b
 hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set, hipStream_t st);
 hipError_t launch_plain_gather(const PlainState &P, const int32_t *verts, int k, int32_t *d_out,
                                double *delta_out, hipStream_t st);
+// weighted engine (bcd_weighted.hip)
+hipError_t launch_w_init(const BatchState &S, const uint32_t *items0, const unsigned long long *masks0, int k,
+                         hipStream_t st);
+hipError_t launch_w_relax(const DevGraph &G, const BatchState &S, int round, Launch L, hipStream_t st);
+hipError_t launch_w_count(const DevGraph &G, const BatchState &S, Launch L, hipStream_t st);
+hipError_t launch_w_sigma(const DevGraph &G, const BatchState &S, int round, Launch L, hipStream_t st);
+hipError_t launch_w_bwd(const DevGraph &G, const BatchState &S, int round, int ntgt, int full, Launch L,
+                        hipStream_t st);
+hipError_t launch_w_cleanup(const BatchState &S, Launch L, hipStream_t st);
+hipError_t launch_w_export(const BatchState &S, const int32_t *lane_slot, uint64_t *dist,
+                           unsigned long long *sigma, double *delta, int64_t k, Launch L, hipStream_t st);
+struct ResultRoute {
+  double *dst;      // device address in a query's result buffer
+  uint32_t src;     // index into res ([ntgt][G][64])
+  uint32_t pad;
+};
+hipError_t launch_route_results(const double *res, const ResultRoute *routes, int k, hipStream_t st);
 hipError_t launch_copy_probe(const double *src, double *dst, int64_t n, hipStream_t st);
 
 }  // namespace bcd

@@ -10,72 +10,11 @@
 // coalesced 512-byte row.  Level masks per (g, v) are single 64-bit words,
 // so testing "has source b already settled w" for all 64 sources costs two
 // 8-byte loads per arc.
-#include "bcd_internal.h"
+#include <algorithm>
+
+#include "bcd_device.h"
 
 namespace bcd {
-
-typedef unsigned long long ull;
-
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-
-__device__ __forceinline__ int lanes_below(ull m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ uint32_t read_lane(uint32_t x, int j) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, j);
-}
-
-__device__ __forceinline__ ull read_lane64(ull x, int j) {
-  uint32_t lo = read_lane((uint32_t)x, j);
-  uint32_t hi = read_lane((uint32_t)(x >> 32), j);
-  return ((ull)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t first_lane64(uint64_t x) {
-  uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Sum three per-thread counters over the workgroup and add them into this
-// workgroup's private counter slot (one writer per slot per launch).
-template <int BLOCK>
-__device__ __forceinline__ void flush_counters(uint64_t *ctr, int slots, int k0, uint64_t a, uint64_t b,
-                                               uint64_t c, bool ovf, uint32_t *flags) {
-  __shared__ uint64_t red[3][BLOCK / 64];
-  __shared__ int any_ovf;
-  if (threadIdx.x == 0) any_ovf = 0;
-  __syncthreads();
-  for (int off = 32; off > 0; off >>= 1) {
-    a += __shfl_down(a, off);
-    b += __shfl_down(b, off);
-    c += __shfl_down(c, off);
-  }
-  if (ovf) any_ovf = 1;
-  const int w = threadIdx.x >> 6;
-  if (lane_id() == 0) {
-    red[0][w] = a;
-    red[1][w] = b;
-    red[2][w] = c;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t s0 = 0, s1 = 0, s2 = 0;
-    for (int i = 0; i < BLOCK / 64; ++i) {
-      s0 += red[0][i];
-      s1 += red[1][i];
-      s2 += red[2][i];
-    }
-    if ((int)blockIdx.x < slots) {
-      uint64_t *p = ctr + (size_t)blockIdx.x * C_COUNT + k0;
-      p[0] += s0;
-      p[1] += s1;
-      p[2] += s2;
-    }
-    if (any_ovf) atomicOr(&flags[0], 1u);
-  }
-}
 
 // ------------------------------------------------------------ batched
 
@@ -183,7 +122,10 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
         const ull dj = read_lane64(dag, j);
         if ((dj >> lane) & 1ull) {
           const ull o = atomicAdd(&S.sig[(gbase + wj) * kLanes + lane], sv);
-          if (o + sv < o) ovf = true;
+          if (o + sv < o) {
+            ovf = true;
+            atomicOr(&S.ovl[g], 1ull << lane);
+          }
         }
       }
     }
@@ -605,6 +547,18 @@ __global__ void k_plain_gather(PlainState P, const int32_t *verts, int k, int32_
     if (d_out) d_out[i] = P.d[v];
     if (delta_out) delta_out[i] = P.d[v] < 0 ? 0.0 : P.dout[v];
   }
+}
+
+__global__ void k_route_results(const double *res, const ResultRoute *routes, int k) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
+    *routes[i].dst = res[routes[i].src];
+}
+
+hipError_t launch_route_results(const double *res, const ResultRoute *routes, int k, hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  const int grid = std::min(4096, (k + 255) / 256);
+  hipLaunchKernelGGL(k_route_results, dim3(grid), dim3(256), 0, st, res, routes, k);
+  return hipGetLastError();
 }
 
 hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set, hipStream_t st) {

@@ -15,17 +15,6 @@
 
 namespace bcd {
 
-#define HIPCHK(expr)                                  \
-  do {                                                \
-    hipError_t _e = (expr);                           \
-    if (_e != hipSuccess) return hip_fail(_e, #expr); \
-  } while (0)
-
-#define STCHK(expr)              \
-  do {                           \
-    bcd_status _s = (expr);      \
-    if (_s != BCD_OK) return _s; \
-  } while (0)
 
 static double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -33,7 +22,7 @@ static double now_s() {
 
 // Neumaier-compensated sum in the order given (Alg.1 sums over RV(r) in
 // ascending vertex order; Alg.2 in draw order).
-static double compensated_sum(const double *x, size_t k, size_t stride) {
+double compensated_sum(const double *x, size_t k, size_t stride) {
   double s = 0.0, c = 0.0;
   for (size_t i = 0; i < k; ++i) {
     const double v = x[i * stride];
@@ -47,14 +36,14 @@ static double compensated_sum(const double *x, size_t k, size_t stride) {
 
 // SplitMix64 output t for state `seed` (Steele, Lea and Flood 2014), and the
 // multiply-high map to [0, k).
-static inline uint64_t splitmix_at(uint64_t seed, uint64_t t) {
+uint64_t splitmix_at(uint64_t seed, uint64_t t) {
   uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
 
-static inline uint64_t index_below(uint64_t x, uint64_t k) {
+uint64_t index_below(uint64_t x, uint64_t k) {
   return (uint64_t)(((unsigned __int128)x * (unsigned __int128)k) >> 64);
 }
 
@@ -98,7 +87,7 @@ bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::v
   return BCD_OK;
 }
 
-static void bits_to_list(const std::vector<uint32_t> &bits, int64_t n, int32_t skip, std::vector<int32_t> &out) {
+void bits_to_list(const std::vector<uint32_t> &bits, int64_t n, int32_t skip, std::vector<int32_t> &out) {
   out.clear();
   for (size_t wi = 0; wi < bits.size(); ++wi) {
     uint32_t x = bits[wi];
@@ -161,7 +150,8 @@ struct ProfAcc {
 // level 0 when `full`), copies the per-lane target dependencies into
 // ws->h_res, and leaves the state clean for the next batch.
 static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool full, BatchExport *ex,
-                                ProfAcc *prof, bool *sigma_overflow) {
+                                ProfAcc *prof, bool *sigma_overflow, bool copy_res = true,
+                                unsigned long long *ovl_out = nullptr) {
   hipStream_t st = ws->stream;
   const DevGraph D = g->dev();
   const Launch L = g->launch();
@@ -181,6 +171,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
     HIPCHK(launch_batch_init(S, ws->d_items0, ws->d_masks0, k, st));
 
     // forward, in chunks of levels between host checks
@@ -257,8 +248,10 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
         HIPCHK(launch_batch_export(S, (int)lv, off[lv], cnt[lv], ws->d_lane_slot, ex->dist, ex->sigma, ex->delta,
                                    ex->k, st));
     }
-    if (ntgt > 0)
+    if (ntgt > 0 && copy_res)
       HIPCHK(hipMemcpyAsync(ws->h_res, S.res, (size_t)ntgt * G64 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (ovl_out)
+      HIPCHK(hipMemcpyAsync(ovl_out, S.ovl, (size_t)ws->G * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIPCHK(launch_batch_cleanup(S, total, L, st));
     HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
@@ -498,6 +491,11 @@ static bcd_status run_plain(Graph *g, Workspace *ws, const std::vector<int32_t> 
   if (g->profiling.load()) add_profile(g, prof, tot);
   if (ovf) return fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return BCD_OK;
+}
+
+bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
+  if (g->weighted) return run_staged_wbatch(g, ws, k, ntgt, ovl_out, ovf);
+  return run_one_batch(g, ws, k, ntgt, false, nullptr, nullptr, ovf, false, ovl_out);
 }
 
 bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,

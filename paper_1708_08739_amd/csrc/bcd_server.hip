@@ -1,0 +1,540 @@
+// libbcd serving loop: many BC(r) queries on one resident graph with
+// continuous batching at source granularity.
+//
+// Threads:
+//   planner  - takes submitted queries in arrival order, finds RV(r) (or the
+//              union D for a set query, or the draws of Alg.2), reserves the
+//              query's device result buffer against the HBM budget (waiting
+//              while it does not fit) and publishes its source list;
+//   workers  - each owns a batch workspace and a stream; a worker fills its
+//              next batch with the next unscheduled sources of the admitted
+//              queries in admission order (one lane per distinct vertex: a
+//              source two queries need is computed once), runs the batched
+//              pass, and routes each lane's dependency on each of its
+//              queries' targets straight into those queries' device buffers;
+//   the worker that completes a query's last source copies its buffer back,
+//   reduces it exactly as the standalone call does, and posts the result.
+// A query that arrives while batches run is admitted as budget frees up and
+// joins the following batches, so its work overlaps with the others on the
+// device; its value is bit-identical to the standalone call (per-source
+// dependencies do not depend on batch composition, and the reduction order
+// is the same).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/bcd.h"
+#include "bcd_host_internal.h"
+
+namespace bcd {
+
+static double steady_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SQuery {
+  uint64_t ticket = 0;
+  bcd_query q{};
+  std::vector<int32_t> rs;       // set targets as submitted
+  std::vector<int32_t> targets;  // distinct targets
+  std::vector<int32_t> sources;  // distinct sources, in reduction order
+  std::vector<int64_t> draw;     // sampled: draw -> source slot
+  double *dres = nullptr;        // device [ns][nt]
+  size_t bytes = 0;
+  size_t next = 0;               // next source to schedule
+  size_t done = 0;               // sources finished
+  bool overflow = false;
+  bool failed = false;
+  bcd_result res{};
+};
+
+}  // namespace bcd
+
+struct bcd_server {
+  bcd::Graph *g = nullptr;
+  bcd_server_config cfg{};
+  std::mutex mu;
+  std::condition_variable cv_plan;     // planner: new submissions / budget freed / stop
+  std::condition_variable cv_work;     // workers: admitted work / stop
+  std::condition_variable cv_done;     // pollers
+  std::deque<std::shared_ptr<bcd::SQuery>> submitted;
+  std::deque<std::shared_ptr<bcd::SQuery>> active;  // admitted, in admission order
+  std::deque<bcd_result> finished;
+  size_t outstanding = 0;  // submitted and not yet polled
+  size_t reserved = 0;     // bytes of admitted queries' buffers
+  size_t budget_q = 0;     // budget left for query buffers after workspaces
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread planner;
+  std::vector<std::thread> workers;
+  std::vector<std::unique_ptr<bcd::Workspace>> wss;
+  std::unique_ptr<bcd::Workspace> plan_ws;
+};
+
+namespace bcd {
+
+static void post_result(bcd_server *S, const std::shared_ptr<SQuery> &q, int32_t status) {
+  q->res.status = status;
+  q->res.t_done_s = steady_now();
+  S->finished.push_back(q->res);
+  S->cv_done.notify_all();
+}
+
+// Reduce a finished query exactly as the standalone calls do.
+static bcd_status finalize(bcd_server *S, Workspace *ws, SQuery &q) {
+  const size_t ns = q.sources.size(), nt = q.targets.size();
+  std::vector<double> dep(ns * nt);
+  if (ns * nt > 0) {
+    if (hipMemcpyAsync(dep.data(), q.dres, ns * nt * sizeof(double), hipMemcpyDeviceToHost, ws->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ws->stream) != hipSuccess)
+      return fail(BCD_ERR_DEVICE, "result copy failed");
+  }
+  Graph *g = S->g;
+  if (q.q.kind == BCD_QUERY_EXACT) {
+    q.res.bc = compensated_sum(dep.data(), ns, 1);
+  } else if (q.q.kind == BCD_QUERY_SAMPLED) {
+    if (q.res.stats.ran_exact) {
+      q.res.bc = compensated_sum(dep.data(), ns, 1);
+    } else {
+      std::vector<double> seq(q.draw.size());
+      for (size_t t = 0; t < q.draw.size(); ++t) seq[t] = dep[(size_t)q.draw[t]];
+      q.res.bc = compensated_sum(seq.data(), seq.size(), 1) * (double)q.res.stats.rv_size / (double)seq.size();
+    }
+  } else {
+    for (size_t i = 0; i < q.rs.size(); ++i) {
+      const size_t t = (size_t)(std::lower_bound(q.targets.begin(), q.targets.end(), q.rs[i]) - q.targets.begin());
+      const double v = g->outdeg(q.rs[i]) == 0 ? 0.0 : compensated_sum(dep.data() + t, ns, nt);
+      q.q.bc_out[i] = v;
+      if (i == 0) q.res.bc = v;
+    }
+  }
+  return BCD_OK;
+}
+
+// Source list of a query (same rules as bcd_bc_exact / _sampled / _set).
+static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
+  Graph *g = S->g;
+  bcd_stats &st = q.res.stats;
+  st.fr_size = -1;
+  std::vector<uint32_t> bits;
+  int64_t k = 0;
+  if (q.q.kind == BCD_QUERY_SET) {
+    q.targets = q.rs;
+    std::sort(q.targets.begin(), q.targets.end());
+    q.targets.erase(std::unique(q.targets.begin(), q.targets.end()), q.targets.end());
+    std::vector<uint32_t> uni((size_t)(g->n + 31) / 32, 0u);
+    for (int32_t r : q.targets) {
+      if (g->outdeg(r) == 0) continue;
+      STCHK(reach_set(g, ws, r, true, bits, &k));
+      bits[(size_t)r >> 5] &= ~(1u << (r & 31));
+      for (size_t i = 0; i < uni.size(); ++i) uni[i] |= bits[i];
+    }
+    bits_to_list(uni, g->n, -1, q.sources);
+    st.rv_size = (int64_t)q.sources.size();
+    st.distinct_sources = st.rv_size;
+    return BCD_OK;
+  }
+  const int32_t r = q.q.r;
+  q.targets = {r};
+  if (g->outdeg(r) == 0) {
+    st.rv_size = -1;
+    return BCD_OK;
+  }
+  STCHK(reach_set(g, ws, r, true, bits, &k));
+  std::vector<int32_t> rv;
+  bits_to_list(bits, g->n, r, rv);
+  st.rv_size = k;
+  if (q.q.kind == BCD_QUERY_EXACT) {
+    q.sources = std::move(rv);
+    st.distinct_sources = (int64_t)q.sources.size();
+    return BCD_OK;
+  }
+  const bcd_sample_params &p = q.q.params;
+  int64_t T = p.T_override;
+  if (T <= 0) {
+    double K = (double)(g->n - 2);
+    if (!(p.flags & BCD_K_TRIVIAL)) {
+      int64_t fr = 0;
+      std::vector<uint32_t> fb;
+      STCHK(reach_set(g, ws, r, false, fb, &fr));
+      st.fr_size = fr;
+      K = (double)fr;
+    }
+    const double eps_abs = (p.flags & BCD_EPS_ABSOLUTE) ? p.eps : p.eps * (double)g->n * (double)(g->n - 1);
+    STCHK(bcd_sample_count(eps_abs, p.delta, K, k, &T));
+  }
+  st.samples = T;
+  if (k == 0) return BCD_OK;
+  if (T >= k && !(p.flags & BCD_NO_EXACT_FALLBACK)) {
+    st.ran_exact = 1;
+    q.sources = std::move(rv);
+  } else {
+    if (T > (int64_t)1 << 40) return fail(BCD_ERR_UNSUPPORTED, "sample count too large to draw");
+    std::vector<int64_t> slot((size_t)k, -1);
+    q.draw.resize((size_t)T);
+    for (int64_t t = 0; t < T; ++t) {
+      const uint64_t idx = index_below(splitmix_at(p.seed, (uint64_t)t), (uint64_t)k);
+      if (slot[idx] < 0) {
+        slot[idx] = (int64_t)q.sources.size();
+        q.sources.push_back(rv[idx]);
+      }
+      q.draw[(size_t)t] = slot[idx];
+    }
+  }
+  st.distinct_sources = (int64_t)q.sources.size();
+  return BCD_OK;
+}
+
+static void planner_loop(bcd_server *S) {
+  Workspace *ws = S->plan_ws.get();
+  for (;;) {
+    std::shared_ptr<SQuery> q;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_plan.wait(lk, [&] { return S->stop || !S->submitted.empty(); });
+      if (S->stop) return;
+      q = S->submitted.front();
+      S->submitted.pop_front();
+    }
+    const double t0 = steady_now();
+    bcd_status rc = plan_query(S, ws, *q);
+    q->res.stats.t_rv_s = steady_now() - t0;
+    const size_t cells = q->sources.size() * q->targets.size();
+    q->bytes = std::max<size_t>(cells, 1) * sizeof(double);
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (rc != BCD_OK) {
+      post_result(S, q, rc);
+      continue;
+    }
+    if (cells == 0) {  // nothing to compute (out-degree 0, empty RV)
+      q->res.t_admit_s = steady_now();
+      q->res.bc = 0.0;
+      if (q->q.kind == BCD_QUERY_SET)
+        for (size_t i = 0; i < q->rs.size(); ++i) q->q.bc_out[i] = 0.0;
+      post_result(S, q, BCD_OK);
+      continue;
+    }
+    if (q->bytes > S->budget_q) {
+      lk.unlock();
+      fail(BCD_ERR_OUT_OF_MEMORY, "query result buffer exceeds the server's HBM budget");
+      lk.lock();
+      post_result(S, q, BCD_ERR_OUT_OF_MEMORY);
+      continue;
+    }
+    // admission: wait until the buffer fits the budget
+    S->cv_plan.wait(lk, [&] { return S->stop || S->reserved + q->bytes <= S->budget_q; });
+    if (S->stop) {
+      post_result(S, q, BCD_ERR_CANCELLED);
+      return;
+    }
+    S->reserved += q->bytes;
+    lk.unlock();
+    bcd_status arc = BCD_OK;
+    if (hipMalloc((void **)&q->dres, q->bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      q->dres = nullptr;
+      arc = BCD_ERR_OUT_OF_MEMORY;
+    } else if (hipMemsetAsync(q->dres, 0, q->bytes, ws->stream) != hipSuccess ||
+               hipStreamSynchronize(ws->stream) != hipSuccess) {
+      arc = BCD_ERR_DEVICE;
+    }
+    lk.lock();
+    if (arc != BCD_OK) {
+      S->reserved -= q->bytes;
+      if (q->dres) (void)hipFree(q->dres);
+      q->dres = nullptr;
+      post_result(S, q, arc);
+      continue;
+    }
+    q->res.t_admit_s = steady_now();
+    S->active.push_back(q);
+    S->cv_work.notify_all();
+  }
+}
+
+struct Lane {
+  int32_t vertex;
+  std::vector<std::pair<std::shared_ptr<SQuery>, uint32_t>> users;  // (query, source slot)
+};
+
+static void release_query(bcd_server *S, SQuery &q) {
+  if (q.dres) (void)hipFree(q.dres);
+  q.dres = nullptr;
+  S->reserved -= q.bytes;
+  S->cv_plan.notify_all();
+}
+
+static void worker_loop(bcd_server *S, Workspace *ws) {
+  Graph *g = S->g;
+  const size_t width = (size_t)ws->G * kLanes;
+  std::vector<unsigned long long> ovl((size_t)ws->G);
+  for (;;) {
+    std::vector<Lane> lanes;
+    std::vector<int32_t> tg;  // distinct targets of the batch
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] {
+        if (S->stop) return true;
+        for (auto &q : S->active)
+          if (q->next < q->sources.size()) return true;
+        return false;
+      });
+      if (S->stop) return;
+      std::unordered_map<int32_t, size_t> where;
+      for (auto &q : S->active) {
+        while (q->next < q->sources.size() && lanes.size() < width) {
+          const int32_t s = q->sources[q->next];
+          auto it = where.find(s);
+          if (it == where.end()) {
+            where.emplace(s, lanes.size());
+            lanes.push_back(Lane{s, {}});
+            it = where.find(s);
+          }
+          lanes[it->second].users.emplace_back(q, (uint32_t)q->next);
+          q->next++;
+        }
+        if (lanes.size() >= width) break;
+      }
+      for (auto &ln : lanes)
+        for (auto &u : ln.users)
+          for (int32_t t : u.first->targets) tg.push_back(t);
+    }
+    std::sort(tg.begin(), tg.end());
+    tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
+    // stage the batch
+    const int k = (int)lanes.size();
+    for (int i = 0; i < k; ++i) {
+      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)lanes[(size_t)i].vertex);
+      ws->h_masks0[i] = 1ull << (i % kLanes);
+    }
+    const int ntgt = (int)tg.size();
+    bcd_status rc = ws->ensure_res((size_t)std::max(ntgt, 1) * width);
+    int32_t *d_t = nullptr;
+    ResultRoute *d_routes = nullptr;
+    std::vector<ResultRoute> routes;
+    for (int i = 0; i < k; ++i)
+      for (auto &u : lanes[(size_t)i].users) {
+        SQuery &q = *u.first;
+        const size_t nt = q.targets.size();
+        for (size_t ti = 0; ti < nt; ++ti) {
+          const size_t t = (size_t)(std::lower_bound(tg.begin(), tg.end(), q.targets[ti]) - tg.begin());
+          ResultRoute rr;
+          rr.dst = q.dres + (size_t)u.second * nt + ti;
+          rr.src = (uint32_t)(t * width + (size_t)i);
+          rr.pad = 0;
+          routes.push_back(rr);
+        }
+      }
+    if (rc == BCD_OK && (hipMalloc((void **)&d_t, (size_t)std::max(ntgt, 1) * sizeof(int32_t)) != hipSuccess ||
+                         hipMalloc((void **)&d_routes, std::max<size_t>(routes.size(), 1) * sizeof(ResultRoute)) !=
+                             hipSuccess)) {
+      (void)hipGetLastError();
+      rc = BCD_ERR_OUT_OF_MEMORY;
+    }
+    if (rc == BCD_OK) {
+      hipError_t e = hipMemcpyAsync(d_t, tg.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_routes, routes.data(), routes.size() * sizeof(ResultRoute), hipMemcpyHostToDevice,
+                           ws->stream);
+      if (e == hipSuccess) e = launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 1, ws->stream);
+      if (e != hipSuccess) rc = BCD_ERR_DEVICE;
+    }
+    bool ovf = false;
+    if (rc == BCD_OK) rc = run_staged_batch(g, ws, k, ntgt, ovl.data(), &ovf);
+    if (rc == BCD_OK) {
+      hipError_t e = launch_route_results(ws->S.res, d_routes, (int)routes.size(), ws->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ws->stream);
+      if (e != hipSuccess) rc = BCD_ERR_DEVICE;
+    }
+    if (d_t) {
+      (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
+      (void)hipStreamSynchronize(ws->stream);
+      (void)hipFree(d_t);
+    }
+    if (d_routes) (void)hipFree(d_routes);
+    // account
+    std::vector<std::shared_ptr<SQuery>> complete;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (int i = 0; i < k; ++i) {
+        const bool lane_ovf = ovf && ((ovl[(size_t)i / kLanes] >> (i % kLanes)) & 1ull);
+        for (auto &u : lanes[(size_t)i].users) {
+          SQuery &q = *u.first;
+          if (rc != BCD_OK) q.failed = true;
+          if (lane_ovf) q.overflow = true;
+          q.done++;
+          if (q.done == q.sources.size()) complete.push_back(u.first);
+        }
+      }
+      // a query whose every source has been counted leaves the active list
+      for (auto &q : complete) {
+        auto it = std::find(S->active.begin(), S->active.end(), q);
+        if (it != S->active.end()) S->active.erase(it);
+      }
+    }
+    for (auto &q : complete) {
+      int32_t status = BCD_OK;
+      if (q->failed) status = rc != BCD_OK ? rc : BCD_ERR_DEVICE;
+      else if (q->overflow) status = BCD_ERR_SIGMA_OVERFLOW;
+      else {
+        bcd_status fr = finalize(S, ws, *q);
+        if (fr != BCD_OK) status = fr;
+      }
+      q->res.stats.t_bc_s = steady_now() - q->res.t_admit_s;
+      q->res.stats.batch_width = (int32_t)width;
+      std::unique_lock<std::mutex> lk(S->mu);
+      release_query(S, *q);
+      post_result(S, q, status);
+    }
+  }
+}
+
+}  // namespace bcd
+
+using namespace bcd;
+
+extern "C" {
+
+double bcd_server_now(void) { return steady_now(); }
+
+bcd_status bcd_server_create(const bcd_graph *gh, const bcd_server_config *cfg, bcd_server **out) {
+  if (!gh || !out) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  std::unique_ptr<bcd_server> S(new (std::nothrow) bcd_server());
+  if (!S) return fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed");
+  S->g = g;
+  if (cfg) S->cfg = *cfg;
+  if (S->cfg.hbm_budget_bytes == 0) S->cfg.hbm_budget_bytes = 64ull << 30;
+  if (S->cfg.workers <= 0) S->cfg.workers = 2;
+  if (S->cfg.workers > 16) return fail(BCD_ERR_INVALID_ARG, "at most 16 workers");
+  if (S->cfg.groups <= 0) S->cfg.groups = g->config().groups;
+  if (S->cfg.queue_capacity <= 0) S->cfg.queue_capacity = 4096;
+  if ((uint64_t)S->cfg.groups * (uint64_t)g->n >= (1ull << 32))
+    return fail(BCD_ERR_INVALID_ARG, "groups * n must stay below 2^32");
+  // workspace footprint: sigma, psi rows, masks, items (and weighted rows)
+  const uint64_t GN = (uint64_t)S->cfg.groups * (uint64_t)g->n;
+  uint64_t ws_bytes = GN * kLanes * 16 + GN * (8 + 24 + 32) + GN * 4 * 12 + (uint64_t)g->n * 24;
+  if (g->weighted) ws_bytes += GN * kLanes * 8 + GN * 28;
+  const uint64_t fixed = ws_bytes * (uint64_t)S->cfg.workers;
+  if (fixed >= S->cfg.hbm_budget_bytes)
+    return fail(BCD_ERR_OUT_OF_MEMORY, "HBM budget smaller than the batch workspaces (" + std::to_string(fixed) +
+                                           " bytes); lower groups or workers");
+  S->budget_q = (size_t)(S->cfg.hbm_budget_bytes - fixed);
+  S->plan_ws.reset(new (std::nothrow) Workspace());
+  if (!S->plan_ws) return fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed");
+  STCHK(S->plan_ws->init_common(g));
+  STCHK(S->plan_ws->ensure_reach());
+  for (int i = 0; i < S->cfg.workers; ++i) {
+    std::unique_ptr<Workspace> w(new (std::nothrow) Workspace());
+    if (!w) return fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    STCHK(w->init_common(g));
+    STCHK(w->ensure_batch(S->cfg.groups));
+    if (g->weighted) STCHK(w->ensure_weighted());
+    S->wss.push_back(std::move(w));
+  }
+  bcd_server *raw = S.get();
+  try {
+    raw->planner = std::thread(planner_loop, raw);
+    for (auto &w : raw->wss) raw->workers.emplace_back(worker_loop, raw, w.get());
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(raw->mu);
+      raw->stop = true;
+    }
+    raw->cv_plan.notify_all();
+    raw->cv_work.notify_all();
+    if (raw->planner.joinable()) raw->planner.join();
+    for (auto &t : raw->workers) t.join();
+    return fail(BCD_ERR_OUT_OF_MEMORY, "thread start failed");
+  }
+  *out = S.release();
+  return BCD_OK;
+}
+
+bcd_status bcd_server_submit(bcd_server *S, const bcd_query *q, uint64_t *ticket) {
+  if (!S || !q || !ticket) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  Graph *g = S->g;
+  if (q->kind == BCD_QUERY_EXACT || q->kind == BCD_QUERY_SAMPLED) {
+    if (q->r < 0 || q->r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
+    if (q->kind == BCD_QUERY_SAMPLED && q->params.T_override <= 0) {
+      if (!(q->params.eps > 0.0) || !std::isfinite(q->params.eps)) return fail(BCD_ERR_INVALID_ARG, "eps must be > 0");
+      if (!(q->params.delta > 0.0 && q->params.delta < 1.0))
+        return fail(BCD_ERR_INVALID_ARG, "delta must be in (0,1)");
+    }
+  } else if (q->kind == BCD_QUERY_SET) {
+    if (!q->rs || q->l <= 0 || !q->bc_out) return fail(BCD_ERR_INVALID_ARG, "set query needs rs, l > 0, bc_out");
+    for (int64_t i = 0; i < q->l; ++i)
+      if (q->rs[i] < 0 || q->rs[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "target out of range");
+  } else {
+    return fail(BCD_ERR_INVALID_ARG, "unknown query kind");
+  }
+  auto sq = std::make_shared<SQuery>();
+  sq->q = *q;
+  if (q->kind == BCD_QUERY_SET) sq->rs.assign(q->rs, q->rs + q->l);
+  sq->q.rs = nullptr;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) return fail(BCD_ERR_CANCELLED, "server is stopping");
+  if (S->outstanding >= (size_t)S->cfg.queue_capacity) return fail(BCD_ERR_AGAIN, "queue full");
+  sq->ticket = S->next_ticket++;
+  sq->res.ticket = sq->ticket;
+  sq->res.tag = q->tag;
+  sq->res.kind = q->kind;
+  sq->res.t_arrive_s = steady_now();
+  S->outstanding++;
+  S->submitted.push_back(sq);
+  S->cv_plan.notify_all();
+  *ticket = sq->ticket;
+  return BCD_OK;
+}
+
+bcd_status bcd_server_poll(bcd_server *S, bcd_result *out, int32_t cap, int32_t *n_out, int64_t timeout_ns) {
+  if (!S || !out || cap <= 0 || !n_out) return fail(BCD_ERR_INVALID_ARG, "bad argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  if (S->finished.empty() && timeout_ns != 0) {
+    if (timeout_ns < 0) S->cv_done.wait(lk, [&] { return !S->finished.empty(); });
+    else S->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return !S->finished.empty(); });
+  }
+  int32_t k = 0;
+  while (k < cap && !S->finished.empty()) {
+    out[k++] = S->finished.front();
+    S->finished.pop_front();
+    S->outstanding--;
+  }
+  *n_out = k;
+  if (k == 0) return fail(BCD_ERR_AGAIN, "no result ready");
+  return BCD_OK;
+}
+
+bcd_status bcd_server_destroy(bcd_server *S) {
+  if (!S) return BCD_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_plan.notify_all();
+  S->cv_work.notify_all();
+  if (S->planner.joinable()) S->planner.join();
+  for (auto &t : S->workers) t.join();
+  // whatever did not finish is cancelled
+  for (auto &q : S->active) {
+    if (q->dres) (void)hipFree(q->dres);
+    q->dres = nullptr;
+  }
+  S->active.clear();
+  S->submitted.clear();
+  delete S;
+  return BCD_OK;
+}
+
+}  // extern "C"

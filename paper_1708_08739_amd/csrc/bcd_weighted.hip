@@ -1,16 +1,702 @@
-// Weighted graphs (positive integer arc lengths): placeholder until the
-// weighted engine lands.
+// Weighted graphs (positive integer arc lengths, Section 2): the per-source
+// pass for 64 sources per wavefront lane group.
+//
+//   1. distances: rounds of label-correcting relaxation; lane b lowers
+//      dist_b(w) with atomicMin and flags (g, w) for the next round;
+//   2. shortest-path-DAG in-degrees: for every reached (g, w), count the
+//      in-arcs (u, w) with dist_b(u) + len(u, w) = dist_b(w) (a pull over the
+//      reverse graph, no atomics);
+//   3. path counts in topological rounds: a lane of a vertex is ready when
+//      all its DAG in-arcs have pushed; it then pushes sigma along its DAG
+//      out-arcs and counts them down (Kahn's order on each source's SPD);
+//   4. backward: Eq.(4) over the rounds of step 3 in reverse -- every DAG
+//      successor of v became ready in a later round, so its psi is final.
+// Step 3's round of a vertex plays the role of the BFS level of the
+// unweighted engine, including the pruning below the nearest target.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/bcd.h"
+#include "bcd_device.h"
 #include "bcd_host_internal.h"
 
 namespace bcd {
 
-bcd_status run_weighted(Graph *, Workspace *, const std::vector<int32_t> &, const std::vector<int32_t> &, bool,
-                        SourceRun &) {
-  return fail(BCD_ERR_UNSUPPORTED, "weighted graphs are not supported yet");
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+__global__ void k_w_init(BatchState S, const uint32_t *items0, const ull *masks0, int k) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const uint32_t it = items0[i];
+    const ull m = masks0[i];
+    S.fr[it] = m;       // topological round 0
+    S.items[i] = it;
+    S.chg[it] = m;      // relaxation round 0: the sources changed
+    S.bq[i] = it;
+    S.rl[i] = it;
+    S.vis[it] = m;      // reached lanes
+    for (int b = 0; b < kLanes; ++b)
+      if ((m >> b) & 1ull) {
+        S.sig[(size_t)it * kLanes + b] = 1ull;
+        S.wd[(size_t)it * kLanes + b] = 0u;
+      }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.bqn[0] = (uint32_t)k;
+    S.bqn[1] = 0u;
+    S.bqn[2] = 0u;
+    *S.rln = (uint32_t)k;
+  }
 }
 
-bcd_status multi_source_pass_weighted(Graph *, const int32_t *, int64_t, uint64_t *, uint64_t *, double *) {
-  return fail(BCD_ERR_UNSUPPORTED, "weighted graphs are not supported yet");
+// One relaxation round.  Input: queue bq[round&1] (length bqn[round%3]) with
+// changed-lane masks chg[round&1]; output: bq[(round+1)&1], chg[(round+1)&1],
+// length bqn[(round+1)%3]; bqn[(round+2)%3] is zeroed for the round after.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int round) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t GN = (uint64_t)S.G * n;
+  const uint32_t count = S.bqn[round % 3];
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.bqn[(round + 2) % 3] = 0u;
+  const uint32_t *qin = S.bq + (uint64_t)(round & 1) * GN;
+  uint32_t *qout = S.bq + (uint64_t)((round + 1) & 1) * GN;
+  uint32_t *qout_n = &S.bqn[(round + 1) % 3];
+  ull *ccur = S.chg + (uint64_t)(round & 1) * GN;
+  ull *cnxt = S.chg + (uint64_t)((round + 1) & 1) * GN;
+  const int lane = lane_id();
+  uint64_t c_r = 0;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = qin[i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    const ull mask = ccur[it];
+    if (lane == 0) ccur[it] = 0ull;  // the owner retires its flag; others write cnxt only
+    const bool act = (mask >> lane) & 1ull;
+    const uint32_t dv = act ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
+    const bool live = act && dv != kInf;
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    if (lane == 0) c_r += (uint64_t)__popcll(mask) * (uint64_t)(e1 - e0);
+    for (int64_t e = e0; e < e1; ++e) {
+      const uint32_t w = (uint32_t)G.col[e];
+      const uint32_t len = G.w[e];
+      uint32_t *pw = &S.wd[(gbase + w) * kLanes + lane];
+      const uint32_t nd = dv + len;
+      bool imp = false;
+      if (live && nd < *pw) imp = atomicMin(pw, nd) > nd;
+      const ull im = __ballot(imp);
+      if (im != 0ull && lane == 0) {
+        const ull o = atomicOr(&cnxt[gbase + w], im);
+        if (o == 0ull) {
+          const uint32_t p = atomicAdd(qout_n, 1u);
+          if (p < GN) qout[p] = (uint32_t)(gbase + w);
+        }
+        const ull r = atomicOr(&S.vis[gbase + w], im);
+        if (r == 0ull) {
+          const uint32_t p = atomicAdd(S.rln, 1u);
+          if (p < GN) S.rl[p] = (uint32_t)(gbase + w);
+        }
+      }
+    }
+  }
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_RLX_APAIRS, c_r, 0, 0, false, S.flags);
+}
+
+// DAG in-degree of every reached (g, w) on each lane, pulled over in-arcs.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t GN = (uint64_t)S.G * n;
+  uint32_t count = *S.rln;
+  if (count > GN) count = (uint32_t)GN;
+  const int lane = lane_id();
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.rl[i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t w = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    const uint32_t dw = S.wd[(uint64_t)it * kLanes + lane];
+    const bool fin = dw != kInf;
+    uint32_t c = 0;
+    const int64_t e0 = G.irp[w], e1 = G.irp[w + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+      const uint32_t u = (uint32_t)G.icol[e];
+      const uint32_t len = G.iw[e];
+      const uint32_t du = S.wd[(gbase + u) * kLanes + lane];
+      if (fin && du != kInf && du + len == dw) ++c;
+    }
+    S.wc[(uint64_t)it * kLanes + lane] = c;
+    const ull fm = __ballot(fin);
+    c_d += c;
+    if (lane == 0) {
+      c_v += (uint64_t)__popcll(fm);
+      c_a += (uint64_t)__popcll(fm) * (uint64_t)(G.rp[w + 1] - G.rp[w]);
+    }
+  }
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
+}
+
+// One topological round: items whose lanes became ready push sigma along
+// their DAG out-arcs; a lane of w whose last DAG in-arc pushed is ready next
+// round.  Level lists, rotation of the mask arrays and target bookkeeping
+// mirror the unweighted forward kernel.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int level) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t GN = (uint64_t)S.G * n;
+  const uint64_t base = S.off[level];
+  const uint64_t count = S.cnt[level];
+  const uint64_t nbase = base + count;
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.off[level + 1] = nbase;
+  if (S.flags[1] != 0u || nbase > S.cap) return;
+  const int lane = lane_id();
+  ull *cur = S.fr + (uint64_t)(level % 3) * GN;
+  ull *nxt = S.fr + (uint64_t)((level + 1) % 3) * GN;
+  ull *old = S.fr + (uint64_t)((level + 2) % 3) * GN;
+  if (level > 0) {
+    const uint64_t pb = S.off[level - 1];
+    const uint64_t pc = S.cnt[level - 1];
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pc; i += (uint64_t)gridDim.x * BLOCK)
+      old[S.items[pb + i]] = 0ull;
+  }
+  bool ovf = false;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.items[base + i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    const ull mask = cur[it];
+    if (lane == 0) S.imask[base + i] = mask;
+    const bool act = (mask >> lane) & 1ull;
+    const ull sv = act ? S.sig[(uint64_t)it * kLanes + lane] : 0ull;
+    const uint32_t dv = act ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
+    if (S.tgt_of[v] >= 0) {
+      if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
+      if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
+    }
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+      const uint32_t w = (uint32_t)G.col[e];
+      const uint32_t len = G.w[e];
+      const uint64_t row = (gbase + w) * kLanes + lane;
+      bool ready = false;
+      if (act && S.wd[row] == dv + len) {
+        const ull o = atomicAdd(&S.sig[row], sv);
+        if (o + sv < o) {
+          ovf = true;
+          atomicOr(&S.ovl[g], 1ull << lane);
+        }
+        ready = atomicSub(&S.wc[row], 1u) == 1u;
+      }
+      const ull rm = __ballot(ready);
+      if (rm != 0ull && lane == 0) {
+        if (atomicOr(&nxt[gbase + w], rm) == 0ull) {
+          const uint32_t p = atomicAdd(&S.cnt[level + 1], 1u);
+          if (nbase + p < S.cap) S.items[nbase + p] = (uint32_t)(gbase + w);
+          else atomicOr(&S.flags[1], 1u);
+        }
+      }
+    }
+  }
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_SCRATCH, 0, 0, 0, ovf, S.flags);
+}
+
+// Backward over topological round `level`: psi(v) = 1/sigma(v) + sum of
+// psi(w) over DAG out-arcs (v, w) of the lane; lanes pruned as in the
+// unweighted kernel.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int level, int ntgt, int full) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t base = S.off[level];
+  const uint64_t count = S.cnt[level];
+  if (base + count > S.cap) return;
+  const int lane = lane_id();
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.items[base + i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    const ull mask = S.imask[base + i];
+    const int32_t tg = S.tgt_of[v];
+    const uint32_t tl = S.tlev[g * kLanes + lane];
+    const bool need = ((mask >> lane) & 1ull) && (full || (uint32_t)level > tl || tg >= 0);
+    const ull em = __ballot(need);
+    if (em == 0ull) continue;
+    const uint32_t dv = need ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    double acc = 0.0;
+    for (int64_t e = e0; e < e1; ++e) {
+      const uint32_t w = (uint32_t)G.col[e];
+      const uint32_t len = G.w[e];
+      const uint64_t row = (gbase + w) * kLanes + lane;
+      if (need && S.wd[row] == dv + len) {
+        acc += S.psi[row];
+        ++c_d;
+      }
+    }
+    if (need) {
+      const double s = (double)S.sig[(uint64_t)it * kLanes + lane];
+      const double dl = s * acc;
+      S.psi[(uint64_t)it * kLanes + lane] = acc + 1.0 / s;
+      if (S.dout) S.dout[(uint64_t)it * kLanes + lane] = dl;
+      if (tg >= 0 && tg < ntgt) S.res[((uint64_t)tg * S.G + g) * kLanes + lane] = (level > 0) ? dl : 0.0;
+    }
+    if (lane == 0) {
+      c_v += (uint64_t)__popcll(em);
+      c_a += (uint64_t)__popcll(em) * (uint64_t)(e1 - e0);
+    }
+  }
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
+}
+
+__global__ void k_w_cleanup(BatchState S) {
+  const uint64_t GN = (uint64_t)S.G * (uint64_t)S.n;
+  uint64_t count = *S.rln;
+  if (count > GN) count = GN;
+  const int lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.rl[i];
+    const uint64_t row = (uint64_t)it * kLanes + lane;
+    S.wd[row] = kInf;
+    S.wc[row] = 0u;
+    S.sig[row] = 0ull;
+    if (lane == 0) S.vis[it] = 0ull;
+    if (lane < 3) S.fr[(uint64_t)lane * GN + it] = 0ull;
+    if (lane >= 3 && lane < 5) S.chg[(uint64_t)(lane - 3) * GN + it] = 0ull;
+  }
+}
+
+__global__ void k_w_export(BatchState S, const int32_t *lane_slot, uint64_t *dist, ull *sigma, double *delta,
+                           int64_t k) {
+  const uint64_t n = (uint64_t)S.n;
+  const uint64_t GN = (uint64_t)S.G * n;
+  uint64_t count = *S.rln;
+  if (count > GN) count = GN;
+  const int lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t i = wave; i < count; i += nwaves) {
+    const uint32_t it = S.rl[i];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t row = (uint64_t)it * kLanes + lane;
+    const uint32_t d = S.wd[row];
+    if (d == kInf) continue;
+    const int32_t slot = lane_slot[g * kLanes + lane];
+    if (slot < 0 || slot >= k) continue;
+    const uint64_t o = (uint64_t)slot * n + v;
+    dist[o] = d;
+    sigma[o] = S.sig[row];
+    if (delta && S.dout) delta[o] = S.dout[row];
+  }
+}
+
+#define DISPATCH_BLOCK(L, KERNEL, ...)                                                                  \
+  do {                                                                                                  \
+    switch ((L).block) {                                                                                \
+      case 64: hipLaunchKernelGGL(KERNEL<64>, dim3((L).grid), dim3(64), 0, st, __VA_ARGS__); break;    \
+      case 128: hipLaunchKernelGGL(KERNEL<128>, dim3((L).grid), dim3(128), 0, st, __VA_ARGS__); break; \
+      case 512: hipLaunchKernelGGL(KERNEL<512>, dim3((L).grid), dim3(512), 0, st, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL(KERNEL<256>, dim3((L).grid), dim3(256), 0, st, __VA_ARGS__); break;  \
+    }                                                                                                   \
+  } while (0)
+
+hipError_t launch_w_init(const BatchState &S, const uint32_t *items0, const ull *masks0, int k, hipStream_t st) {
+  const int grid = std::max(1, (k + 255) / 256);
+  hipLaunchKernelGGL(k_w_init, dim3(grid), dim3(256), 0, st, S, items0, masks0, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_relax(const DevGraph &G, const BatchState &S, int round, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_w_relax, G, S, round);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_count(const DevGraph &G, const BatchState &S, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_w_count, G, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_sigma(const DevGraph &G, const BatchState &S, int round, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_w_sigma, G, S, round);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_bwd(const DevGraph &G, const BatchState &S, int round, int ntgt, int full, Launch L,
+                        hipStream_t st) {
+  DISPATCH_BLOCK(L, k_w_bwd, G, S, round, ntgt, full);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_cleanup(const BatchState &S, Launch L, hipStream_t st) {
+  hipLaunchKernelGGL(k_w_cleanup, dim3(L.grid), dim3(256), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_w_export(const BatchState &S, const int32_t *lane_slot, uint64_t *dist, ull *sigma,
+                           double *delta, int64_t k, Launch L, hipStream_t st) {
+  hipLaunchKernelGGL(k_w_export, dim3(L.grid), dim3(256), 0, st, S, lane_slot, dist, sigma, delta, k);
+  return hipGetLastError();
+}
+
+}  // namespace bcd
+
+// ================================================================= host
+
+namespace bcd {
+
+
+template <class T>
+static bcd_status walloc(T **p, size_t count) {
+  *p = nullptr;
+  if (hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(BCD_ERR_OUT_OF_MEMORY, "device allocation for the weighted engine failed");
+  }
+  return BCD_OK;
+}
+
+bcd_status Workspace::ensure_weighted() {
+  if (weighted_ready && weighted_G == G) return BCD_OK;
+  release_weighted();
+  const size_t GN = (size_t)G * (size_t)n;
+  STCHK(walloc(&S.wd, GN * kLanes));
+  STCHK(walloc(&S.wc, GN * kLanes));
+  STCHK(walloc(&S.chg, 2 * GN));
+  STCHK(walloc(&S.bq, 2 * GN));
+  STCHK(walloc(&S.bqn, 4));
+  STCHK(walloc(&S.rl, GN));
+  STCHK(walloc(&S.rln, 1));
+  HIPCHK(hipMemsetAsync(S.wd, 0xFF, GN * kLanes * sizeof(uint32_t), stream));
+  HIPCHK(hipMemsetAsync(S.wc, 0, GN * kLanes * sizeof(uint32_t), stream));
+  HIPCHK(hipMemsetAsync(S.chg, 0, 2 * GN * sizeof(unsigned long long), stream));
+  HIPCHK(hipMemsetAsync(S.bqn, 0, 4 * sizeof(uint32_t), stream));
+  HIPCHK(hipMemsetAsync(S.rln, 0, sizeof(uint32_t), stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  weighted_ready = true;
+  weighted_G = G;
+  return BCD_OK;
+}
+
+void Workspace::release_weighted() {
+  auto f = [](auto *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+  };
+  f(S.wd);
+  f(S.wc);
+  f(S.chg);
+  f(S.bq);
+  f(S.bqn);
+  f(S.rl);
+  f(S.rln);
+  weighted_ready = false;
+}
+
+struct WExport {
+  uint64_t *dist = nullptr;
+  unsigned long long *sigma = nullptr;
+  double *delta = nullptr;
+  int64_t k = 0;
+};
+
+// One batch of the weighted engine; `k` sources staged in h_items0/h_masks0.
+static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool full, WExport *ex,
+                                 double *ms_fwd, double *ms_bwd, int64_t *l_fwd, int64_t *l_bwd, bool *sigma_overflow,
+                                 bool copy_res = true, unsigned long long *ovl_out = nullptr) {
+  hipStream_t st = ws->stream;
+  const DevGraph D = g->dev();
+  const Launch L = g->launch();
+  const bool profiling = g->profiling.load();
+  const size_t G64 = (size_t)ws->G * kLanes;
+  HIPCHK(hipMemcpyAsync(ws->d_items0, ws->h_items0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ws->d_masks0, ws->h_masks0, (size_t)k * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                        st));
+  for (int attempt = 0;; ++attempt) {
+    ws->S.epoch += 1;
+    BatchState S = ws->S;
+    if (!ex) S.dout = nullptr;
+    uint32_t *hc = ws->h_cnt;
+    uint32_t *hm = reinterpret_cast<uint32_t *>(ws->h_misc);
+    hc[kLevelChunkMax + 4] = (uint32_t)k;
+    HIPCHK(hipMemcpyAsync(&S.cnt[0], &hc[kLevelChunkMax + 4], sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    if (ntgt > 0) HIPCHK(hipMemsetAsync(S.res, 0, (size_t)ntgt * G64 * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
+    HIPCHK(launch_w_init(S, ws->d_items0, ws->d_masks0, k, st));
+    size_t ev = 0;
+    auto rec0 = [&]() -> hipError_t {
+      return profiling ? hipEventRecord(ws->event_pair(ev).first, st) : hipSuccess;
+    };
+    auto rec1 = [&]() -> hipError_t {
+      if (!profiling) return hipSuccess;
+      hipError_t e = hipEventRecord(ws->event_pair(ev).second, st);
+      ++ev;
+      return e;
+    };
+    // 1. distances
+    int round = 0;
+    for (;;) {
+      const int chunk = 8;
+      for (int i = 0; i < chunk; ++i, ++round) {
+        HIPCHK(rec0());
+        HIPCHK(launch_w_relax(D, S, round, L, st));
+        HIPCHK(rec1());
+      }
+      HIPCHK(hipMemcpyAsync(hm, &S.bqn[round % 3], sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (hm[0] == 0) break;
+      if (round > g->n + 16) return fail(BCD_ERR_DEVICE, "relaxation rounds did not converge");
+    }
+    // 2. DAG in-degrees
+    HIPCHK(rec0());
+    HIPCHK(launch_w_count(D, S, L, st));
+    HIPCHK(rec1());
+    // 3. path counts in topological rounds
+    std::vector<uint32_t> cnt{(uint32_t)k};
+    int lmax = -1, level = 0;
+    int chunk = std::min(kLevelChunkMax, std::max(4, ws->last_depth + 2));
+    uint32_t flags_h[2] = {0, 0}, tmin_h = 0xFFFFFFFFu;
+    while (lmax < 0) {
+      const int first = level;
+      int launched = 0;
+      for (; launched < chunk && level <= g->n; ++launched, ++level) {
+        HIPCHK(rec0());
+        HIPCHK(launch_w_sigma(D, S, level, L, st));
+        HIPCHK(rec1());
+      }
+      HIPCHK(hipMemcpyAsync(hc, &S.cnt[first + 1], (size_t)launched * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hm, S.flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hm + 2, S.tmin, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      flags_h[0] = hm[0];
+      flags_h[1] = hm[1];
+      tmin_h = hm[2];
+      if (flags_h[1]) break;
+      for (int i = 0; i < launched; ++i) {
+        if (hc[i] == 0) {
+          lmax = first + i;
+          break;
+        }
+        cnt.push_back(hc[i]);
+      }
+      if (lmax < 0 && level > g->n) return fail(BCD_ERR_DEVICE, "topological rounds did not terminate");
+      chunk = kLevelChunkMax;
+    }
+    if (flags_h[1]) {
+      HIPCHK(launch_w_cleanup(S, L, st));
+      STCHK(ws->reset_batch_dense());
+      STCHK(ws->grow_items());
+      if (attempt > 8) return fail(BCD_ERR_OUT_OF_MEMORY, "frontier item list cannot grow further");
+      continue;
+    }
+    ws->last_depth = lmax;
+    if (flags_h[0]) *sigma_overflow = true;
+    const size_t fwd_events = ev;
+    // 4. backward
+    int stop = -1;
+    if (full) stop = 0;
+    else if (ntgt > 0 && tmin_h != 0xFFFFFFFFu) stop = (int)tmin_h;
+    if (stop >= 0)
+      for (int lv = lmax; lv >= stop; --lv) {
+        HIPCHK(rec0());
+        HIPCHK(launch_w_bwd(D, S, lv, ntgt, full ? 1 : 0, L, st));
+        HIPCHK(rec1());
+      }
+    if (ex) HIPCHK(launch_w_export(S, ws->d_lane_slot, ex->dist, ex->sigma, ex->delta, ex->k, L, st));
+    if (ntgt > 0 && copy_res)
+      HIPCHK(hipMemcpyAsync(ws->h_res, S.res, (size_t)ntgt * G64 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (ovl_out)
+      HIPCHK(hipMemcpyAsync(ovl_out, S.ovl, (size_t)ws->G * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_w_cleanup(S, L, st));
+    HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (profiling) {
+      for (size_t i = 0; i < ev; ++i) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ws->events[i].first, ws->events[i].second));
+        if (i < fwd_events) {
+          *ms_fwd += ms;
+          *l_fwd += 1;
+        } else {
+          *ms_bwd += ms;
+          *l_bwd += 1;
+        }
+      }
+    }
+    return BCD_OK;
+  }
+}
+
+static bcd_status wcounters(Workspace *ws, uint64_t *c) {
+  hipStream_t st = ws->stream;
+  HIPCHK(hipMemcpyAsync(ws->h_ctr, ws->S.ctr, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                        st));
+  HIPCHK(hipMemsetAsync(ws->S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < C_COUNT; ++k) c[k] = 0;
+  for (int s = 0; s < kCtrSlots; ++s)
+    for (int k = 0; k < C_COUNT; ++k) c[k] += ws->h_ctr[(size_t)s * C_COUNT + k];
+  return BCD_OK;
+}
+
+static void wprofile(Graph *g, double msf, double msb, int64_t lf, int64_t lb, const uint64_t *c) {
+  const double fb = 32.0 * c[C_FWD_VPAIRS] + 8.0 * c[C_FWD_APAIRS] + 8.0 * c[C_FWD_DPAIRS];
+  const double bb = 32.0 * c[C_BWD_VPAIRS] + 8.0 * c[C_BWD_APAIRS] + 8.0 * c[C_BWD_DPAIRS];
+  g->add_profile(0, lf, msf, c + C_FWD_VPAIRS, fb);
+  g->add_profile(1, lb, msb, c + C_BWD_VPAIRS, bb);
+}
+
+bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
+  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_w >= 0xFFFFFFFFull)
+    return fail(BCD_ERR_UNSUPPORTED, "(n-1) * max weight must stay below 2^32 - 1 for 32-bit distances");
+  STCHK(ws->ensure_weighted());
+  double a = 0, b = 0;
+  int64_t c = 0, d = 0;
+  return run_one_wbatch(g, ws, k, ntgt, false, nullptr, &a, &b, &c, &d, ovf, false, ovl_out);
+}
+
+bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
+                        bool want_counters, SourceRun &out) {
+  const bcd_config cfg = g->config();
+  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_w >= 0xFFFFFFFFull)
+    return fail(BCD_ERR_UNSUPPORTED, "(n-1) * max weight must stay below 2^32 - 1 for 32-bit distances");
+  STCHK(ws->ensure_batch(cfg.groups));
+  STCHK(ws->ensure_weighted());
+  const int ntgt = (int)tgt.size();
+  const size_t G64 = (size_t)ws->G * kLanes;
+  STCHK(ws->ensure_res((size_t)std::max(ntgt, 1) * G64));
+  std::vector<int32_t> tv(tgt);
+  int32_t *d_t = nullptr;
+  if (ntgt > 0) {
+    STCHK(walloc(&d_t, (size_t)ntgt));
+    HIPCHK(hipMemcpyAsync(d_t, tv.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream));
+    HIPCHK(launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 1, ws->stream));
+  }
+  const size_t ns = src.size();
+  out.dep.assign(ns * (size_t)ntgt, 0.0);
+  if (want_counters) out.counters.assign(ns * 3, 0);
+  // the plain engine on a weighted graph runs one source per batch
+  const bool one = want_counters || cfg.engine == BCD_ENGINE_PLAIN;
+  const size_t per = one ? 1 : G64;
+  out.width = (int32_t)per;
+  double msf = 0, msb = 0;
+  int64_t lf = 0, lb = 0;
+  bool ovf = false;
+  uint64_t tot[C_COUNT] = {0};
+  bcd_status rc = BCD_OK;
+  for (size_t b0 = 0; b0 < ns && rc == BCD_OK; b0 += per) {
+    const int k = (int)std::min(per, ns - b0);
+    for (int i = 0; i < k; ++i) {
+      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[b0 + i]);
+      ws->h_masks0[i] = 1ull << (i % kLanes);
+    }
+    rc = run_one_wbatch(g, ws, k, ntgt, false, nullptr, &msf, &msb, &lf, &lb, &ovf);
+    if (rc != BCD_OK) break;
+    for (int i = 0; i < k; ++i)
+      for (int t = 0; t < ntgt; ++t) out.dep[(b0 + i) * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
+    if (want_counters) {
+      uint64_t c[C_COUNT];
+      rc = wcounters(ws, c);
+      out.counters[b0 * 3 + 0] = c[C_FWD_VPAIRS];
+      out.counters[b0 * 3 + 1] = c[C_FWD_APAIRS];
+      out.counters[b0 * 3 + 2] = c[C_FWD_DPAIRS];
+      for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
+    }
+  }
+  if (ntgt > 0) {
+    (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
+    (void)hipStreamSynchronize(ws->stream);
+    (void)hipFree(d_t);
+  }
+  if (rc != BCD_OK) return rc;
+  if (!want_counters) STCHK(wcounters(ws, tot));
+  out.te = tot[C_FWD_APAIRS];
+  out.reached = tot[C_FWD_VPAIRS];
+  out.dag = tot[C_FWD_DPAIRS];
+  if (g->profiling.load()) wprofile(g, msf, msb, lf, lb, tot);
+  if (ovf) return fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+  return BCD_OK;
+}
+
+bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t k, uint64_t *dist, uint64_t *sigma,
+                                      double *delta) {
+  const bcd_config cfg = g->config();
+  if (k > (int64_t)cfg.groups * kLanes) return fail(BCD_ERR_INVALID_ARG, "k exceeds the batch width");
+  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_w >= 0xFFFFFFFFull)
+    return fail(BCD_ERR_UNSUPPORTED, "(n-1) * max weight must stay below 2^32 - 1 for 32-bit distances");
+  for (int64_t i = 0; i < k; ++i) {
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "source out of range");
+    for (int64_t j = 0; j < i; ++j)
+      if (sources[j] == sources[i] && i / kLanes == j / kLanes) return fail(BCD_ERR_INVALID_ARG, "repeated source");
+  }
+  Lease ls(g);
+  if (!ls.ok()) return fail(BCD_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+  STCHK(ls->init_common(g));
+  Workspace *ws = ls.w.get();
+  STCHK(ws->ensure_batch(cfg.groups));
+  STCHK(ws->ensure_weighted());
+  STCHK(ws->ensure_dout());
+  const size_t G64 = (size_t)ws->G * kLanes;
+  const size_t kn = (size_t)k * (size_t)g->n;
+  WExport ex;
+  ex.k = k;
+  STCHK(walloc(&ex.dist, kn));
+  bcd_status rc = walloc(&ex.sigma, kn);
+  if (rc == BCD_OK) rc = walloc(&ex.delta, kn);
+  hipStream_t st = ws->stream;
+  std::vector<int32_t> slot(G64, -1);
+  for (int64_t i = 0; i < k; ++i) slot[(size_t)i] = (int32_t)i;
+  hipError_t e = hipSuccess;
+  if (rc == BCD_OK) {
+    e = hipMemcpyAsync(ws->d_lane_slot, slot.data(), G64 * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ex.dist, 0xFF, kn * 8, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ex.sigma, 0, kn * 8, st);
+    if (e == hipSuccess) e = hipMemsetAsync(ex.delta, 0, kn * 8, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = hip_fail(e, "export setup");
+  }
+  bool ovf = false;
+  if (rc == BCD_OK) {
+    for (int64_t i = 0; i < k; ++i) {
+      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)sources[i]);
+      ws->h_masks0[i] = 1ull << (i % kLanes);
+    }
+    double a = 0, b = 0;
+    int64_t c = 0, d = 0;
+    rc = run_one_wbatch(g, ws, (int)k, 0, true, &ex, &a, &b, &c, &d, &ovf);
+  }
+  if (rc == BCD_OK) {
+    e = hipSuccess;
+    if (dist) e = hipMemcpy(dist, ex.dist, kn * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sigma) e = hipMemcpy(sigma, ex.sigma, kn * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && delta) e = hipMemcpy(delta, ex.delta, kn * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "export copy");
+  }
+  if (ex.dist) (void)hipFree(ex.dist);
+  if (ex.sigma) (void)hipFree(ex.sigma);
+  if (ex.delta) (void)hipFree(ex.delta);
+  uint64_t cc[C_COUNT];
+  if (rc == BCD_OK) rc = wcounters(ws, cc);
+  if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
+  return rc;
 }
 
 }  // namespace bcd

@@ -260,3 +260,47 @@ def test_rmat16_sampled_sources_bench_config(B, oracle):
     got, st = G.bc_exact(r)
     want, ost = oracle.bc_exact(g, r)
     assert close(got, want) and st["traversed_edges"] == ost["te"]
+
+
+# ------------------------------------------------------------ weighted
+
+WSMALL = [
+    ("rand40w", lambda: gg.random_small(40, 0.1, seed=5, max_weight=3)),
+    ("er300w", lambda: gg.with_weights(gg.erdos_renyi(300, 1500, seed=9), seed=19, max_weight=7)),
+    ("rmat10w", lambda: gg.with_weights(gg.rmat(10, 8, seed=21), seed=4, max_weight=100)),
+    ("grid10w1", lambda: gg.with_unit_weights(gg.grid_right_down(10, 10))),
+]
+
+
+@pytest.mark.parametrize("name,make", WSMALL)
+def test_weighted_source_pass_bitexact(B, oracle, name, make):
+    g = make()
+    G = dev(B, g, groups=2)
+    src = sorted(set([0, g.n - 1] + gg.uniform_vertices(g.n, min(70, g.n - 2), seed=6, exclude=[0, g.n - 1])))
+    print("weighted", name, len(src), flush=True)
+    d, sg, dl = G.multi_source_pass(src)
+    for i, s in enumerate(src):
+        od, osg, odl, ovf, _ = oracle.source_pass(g, s)
+        assert np.array_equal(d[i], od), (name, s)
+        assert np.array_equal(sg[i], osg), (name, s)
+        assert close(dl[i], odl), (name, s)
+
+
+def test_weighted_bc_and_counters(B, oracle):
+    g = gg.with_weights(gg.rmat(11, 8, seed=13), seed=5, max_weight=100)
+    G = dev(B, g)
+    for r in gg.queries_top_and_random(g, seed=2, top=2, rnd=3):
+        print("weighted bc r", r, flush=True)
+        got, st = G.bc_exact(r)
+        want, ost = oracle.bc_exact(g, r)
+        assert close(got, want), (r, got, want)
+        assert st["traversed_edges"] == ost["te"] and st["dag_arcs"] == ost["dag_arcs"]
+    rs = gg.top_out_degree(g, 3)
+    got, _ = G.bc_set(rs)
+    want, _ = oracle.bc_set(g, rs)
+    assert close(got, want)
+    # unit weights reproduce the unweighted engine exactly
+    g1 = gg.with_unit_weights(gg.rmat(10, 8, seed=3))
+    g0 = gg.rmat(10, 8, seed=3)
+    r = gg.top_out_degree(g0, 1)[0]
+    assert dev(B, g1).bc_exact(r)[0] == dev(B, g0).bc_exact(r)[0] or close(dev(B, g1).bc_exact(r)[0], dev(B, g0).bc_exact(r)[0])

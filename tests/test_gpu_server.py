@@ -1,0 +1,108 @@
+"""Serving loop on the GPU: every result equals the standalone call bit for
+bit, whether the query runs alone or mixed with others arriving while
+batches run; set and sampled queries; budget admission; errors."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1708_08739_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1708_08739_amd import bcd
+    bcd.load()
+    return bcd
+
+
+def drain(S, n, timeout=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < n:
+        for r in S.poll(timeout_s=1.0):
+            got[r["ticket"]] = r
+        assert time.time() - t0 < timeout, "server did not finish"
+    return got
+
+
+def test_server_mixed_equals_alone(B, oracle):
+    g = gg.rmat(12, 8, seed=8)
+    G = B.Graph.from_digraph(g)
+    G.set_config(groups=2)
+    qs = gg.queries_top_and_random(g, seed=4, top=4, rnd=6)
+    alone = {r: G.bc_exact(r)[0] for r in qs}
+    samp = {r: G.bc_sampled(r, T=40, seed=r, flags=B.BCD_NO_EXACT_FALLBACK)[0] for r in qs[:3]}
+    sets = G.bc_set(qs[:5])[0]
+    S = B.Server(G, workers=2, groups=2)
+    tickets = {}
+    # staggered arrivals: some queries arrive while earlier batches are running
+    for i, r in enumerate(qs):
+        tickets[S.submit(B.BCD_QUERY_EXACT, r=r, tag=r)] = ("exact", r)
+        if i < 3:
+            tickets[S.submit(B.BCD_QUERY_SAMPLED, r=r, T=40, seed=r, flags=B.BCD_NO_EXACT_FALLBACK)] = ("samp", r)
+        if i == 4:
+            tickets[S.submit(B.BCD_QUERY_SET, rs=qs[:5])] = ("set", None)
+        time.sleep(0.002)
+    res = drain(S, len(tickets))
+    S.close()
+    for t, (kind, r) in tickets.items():
+        out = res[t]
+        assert out["status"] == B.BCD_OK, (kind, r, out)
+        assert out["t_arrive_s"] <= out["t_admit_s"] <= out["t_done_s"]
+        if kind == "exact":
+            assert out["bc"] == alone[r], (r, out["bc"], alone[r])
+            assert out["tag"] == r
+        elif kind == "samp":
+            assert out["bc"] == samp[r]
+        else:
+            assert np.array_equal(out["bcs"], sets)
+    for r in qs[:3]:
+        want, _ = oracle.bc_exact(g, r)
+        assert abs(alone[r] - want) <= 1e-10 * abs(want)
+
+
+def test_server_budget_admission_and_errors(B):
+    g = gg.rmat(11, 8, seed=2)
+    G = B.Graph.from_digraph(g)
+    G.set_config(groups=1)
+    qs = gg.top_out_degree(g, 6)
+    alone = {r: G.bc_exact(r)[0] for r in qs}
+    # budget so tight that queries must wait for each other's buffers
+    nrv = max(int(G.bc_exact(r)[1]["rv_size"]) for r in qs)
+    ws = 1 * g.n * 64 * 16 + g.n * 64 + g.n * 48 + g.n * 24
+    S = B.Server(G, workers=1, groups=1, hbm_budget_bytes=ws + 8 * nrv + 64)
+    ts = [S.submit(B.BCD_QUERY_EXACT, r=r) for r in qs]
+    res = drain(S, len(ts))
+    for t, r in zip(ts, qs):
+        assert res[t]["status"] == B.BCD_OK and res[t]["bc"] == alone[r]
+    with pytest.raises(B.BcdError) as e:
+        S.submit(B.BCD_QUERY_EXACT, r=g.n + 5)
+    assert e.value.code == B.BCD_ERR_INVALID_ARG
+    S.close()
+    with pytest.raises(B.BcdError) as e:
+        B.Server(G, workers=1, groups=1, hbm_budget_bytes=1024)
+    assert e.value.code == B.BCD_ERR_OUT_OF_MEMORY
+
+
+def test_server_overflow_isolated(B):
+    """A query whose sources overflow sigma fails alone; a query whose
+    sources share its batch but not its overflow still gets its value."""
+    gd, ids = gg.diamond_chain(64)
+    s, d = gd.arcs()
+    off = gd.n
+    ps = np.arange(off, off + 5)
+    g = gg.from_arcs(gd.n + 6, np.concatenate([s, ps]), np.concatenate([d, ps + 1]))
+    G = B.Graph.from_digraph(g)
+    ok_r = off + 2
+    want = G.bc_exact(ok_r)[0]
+    assert want == 2 * 3
+    S = B.Server(G, workers=1, groups=1)
+    t_bad = S.submit(B.BCD_QUERY_EXACT, r=ids["x"][40])
+    t_ok = S.submit(B.BCD_QUERY_EXACT, r=ok_r)
+    res = drain(S, 2)
+    S.close()
+    assert res[t_bad]["status"] == B.BCD_ERR_SIGMA_OVERFLOW
+    assert res[t_ok]["status"] == B.BCD_OK and res[t_ok]["bc"] == want
