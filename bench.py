@@ -43,7 +43,100 @@ def workload(name: str):
     if name == "er2000":
         g, q = gg.er_2000()
         return g, q, "er_n2000_m10000_maxindeg_exact"
+    if name == "rmat18w":
+        g, q = gg.rmat18_weighted()
+        return g, q, "rmat18_ef16_w1-100_8queries_exact"
+    if name == "rmat20set":
+        return gg.rmat20(), None, "rmat20_ef16_set64_exact"
+    if name == "rmat22serve":
+        return gg.rmat22(), None, "rmat22_ef16_serving_sampled"
     raise SystemExit(f"unknown workload {name}")
+
+
+def run_weighted(G, g, queries, args):
+    """R-MAT scale 18, edge factor 16, weights in [1,100]: the four top
+    out-degree vertices through one set call (they share RV), the others
+    one exact call each."""
+    from paper_1708_08739_amd import bcd
+    if args.autotune:
+        cfg, rate = G.autotune(queries[0], max_groups=8, max_sources=2048)
+        log(f"[bench] autotune: groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult} ({rate:.2f} GTEPS)")
+    t0 = time.perf_counter()
+    bcs, st = G.bc_set(queries[:4])
+    te = st["traversed_edges"]
+    lat = [time.perf_counter() - t0]
+    for r in queries[4:]:
+        t = time.perf_counter()
+        bc, s2 = G.bc_exact(r)
+        lat.append(time.perf_counter() - t)
+        te += s2["traversed_edges"]
+    wall = time.perf_counter() - t0
+    return te, wall, lat
+
+
+def select_uneven(G, g, k: int, seed: int, lo=10, hi=100000):
+    """k query vertices whose |RV(r)| is closest to k log-spaced targets in
+    [lo, hi], from a seeded pool of vertices with in- and out-degree > 0."""
+    from paper_1708_08739_amd import graphgen as gg
+    ind, outd = g.in_degree(), g.out_degree()
+    cand = [v for v in gg.uniform_vertices(g.n, 4000, seed=seed) if ind[v] > 0 and outd[v] > 0][:1500]
+    sizes = {}
+    for v in cand:
+        sizes[v] = len(G.rv(v))
+    targets = np.logspace(np.log10(lo), np.log10(hi), k)
+    chosen = []
+    for t in targets:
+        best = min((v for v in cand if v not in chosen), key=lambda v: (abs(np.log(max(sizes[v], 1)) - np.log(t)), v))
+        chosen.append(best)
+    return chosen, [sizes[v] for v in chosen]
+
+
+def serve(G, g, args):
+    """Serving: sampled BC(r) queries (eps = 0.01 normalised, delta = 0.1,
+    K = reach of r, seeded) on R-MAT; first all at t = 0 to find the
+    saturation throughput, then Poisson arrivals at a fraction of it."""
+    from paper_1708_08739_amd import bcd, graphgen as gg
+    ind, outd = g.in_degree(), g.out_degree()
+    pool = [v for v in gg.uniform_vertices(g.n, 20 * args.queries, seed=105) if ind[v] > 0 and outd[v] > 0]
+    qs = pool[: args.queries]
+
+    def run(rate):
+        S = bcd.Server(G, workers=args.workers, groups=G.config().groups, hbm_budget_bytes=args.hbm_budget << 30)
+        gaps = [0.0] * len(qs)
+        if rate > 0:
+            u = gg.unit(gg.stream(205, 0, len(qs)))
+            gaps = list(-np.log1p(-u) / rate)
+        t0 = time.perf_counter()
+        arrive = 0.0
+        tickets = {}
+        for i, r in enumerate(qs):
+            arrive += gaps[i]
+            while time.perf_counter() - t0 < arrive:
+                time.sleep(min(0.001, arrive - (time.perf_counter() - t0)))
+            tickets[S.submit(bcd.BCD_QUERY_SAMPLED, r=r, eps=0.01, delta=0.1, seed=305 + i)] = r
+        res = []
+        while len(res) < len(qs):
+            res += S.poll(timeout_s=1.0)
+        wall = time.perf_counter() - t0
+        S.close()
+        bad = [x for x in res if x["status"] != bcd.BCD_OK]
+        if bad:
+            raise SystemExit(f"serving: {len(bad)} queries failed: {bad[0]}")
+        lat = np.array([x["t_done_s"] - x["t_arrive_s"] for x in res])
+        te = sum(x["stats"]["traversed_edges"] for x in res)
+        return {"queries": len(qs), "wall_s": round(wall, 3), "qps": round(len(qs) / wall, 3),
+                "gteps": round(te / wall / 1e9, 3), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                "samples_mean": float(np.mean([x["stats"]["samples"] for x in res])),
+                "distinct_sources_mean": float(np.mean([x["stats"]["distinct_sources"] for x in res]))}, te
+    sat, te = run(0.0)
+    log(f"[bench] serving saturation: {sat}")
+    out = {"saturation": sat}
+    for frac in (0.5, 0.9):
+        r, _ = run(frac * sat["qps"])
+        log(f"[bench] serving at {frac} x saturation: {r}")
+        out[f"poisson_{frac}"] = r
+    return out
 
 
 def cpu_baseline(g, r, budget_s: float, threads: int):
@@ -83,6 +176,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--queries", type=int, default=64, help="serving: number of sampled queries")
+    ap.add_argument("--workers", type=int, default=2, help="serving: concurrent batches")
+    ap.add_argument("--hbm-budget", type=int, default=64, help="serving: HBM budget in GiB")
+    ap.add_argument("--set-size", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
@@ -104,6 +202,35 @@ def main():
         kw["grid_mult"] = args.grid_mult
     cfg = G.set_config(engine=bcd.BCD_ENGINE_BATCHED, **kw)
     log(f"[bench] config groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult}")
+
+    if args.workload in ("rmat18w", "rmat20set", "rmat22serve"):
+        extra = {}
+        if args.workload == "rmat18w":
+            te, wall, lat = run_weighted(G, g, queries, args)
+        elif args.workload == "rmat20set":
+            qs, sizes = select_uneven(G, g, args.set_size, seed=104)
+            log(f"[bench] set of {len(qs)}: |RV| from {min(sizes)} to {max(sizes)}")
+            if args.autotune:
+                c2, rate = G.autotune(qs[int(np.argmax(sizes))], max_groups=8, max_sources=2048)
+                log(f"[bench] autotune: groups={c2.groups} ({rate:.2f} GTEPS)")
+            t0 = time.perf_counter()
+            bcs, st = G.bc_set(qs)
+            wall = time.perf_counter() - t0
+            te, lat = st["traversed_edges"], [wall]
+            extra = {"set_size": len(qs), "rv_sizes": sizes, "distinct_sources": st["distinct_sources"]}
+        else:
+            srv = serve(G, g, args)
+            te, wall, lat = srv["saturation"]["gteps"] * 1e9 * srv["saturation"]["wall_s"], srv["saturation"]["wall_s"], [0]
+            extra = {"serving": srv}
+        cfg = G.config()
+        print(json.dumps({"metric": "GTEPS for RV(r)-pruned BC(r) on one MI355X; p50/p99 query latency",
+                          "value": round(te / wall / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
+                          "workload": wname, "wall_s": round(wall, 3), "traversed_edges": int(te),
+                          "latencies_s": [round(x, 4) for x in lat][:16],
+                          "config": {"workload": wname, "n": g.n, "m": g.m, "groups": cfg.groups,
+                                     "block": cfg.block, "grid_mult": cfg.grid_mult},
+                          **extra}), flush=True)
+        return
 
     def step(lat=None):
         te = 0

@@ -126,6 +126,17 @@ bcd_status bcd_graph_info(const bcd_graph *g, int64_t *n, int64_t *m, int32_t *w
 bcd_status bcd_set_config(bcd_graph *g, const bcd_config *cfg);
 bcd_status bcd_get_config(const bcd_graph *g, bcd_config *cfg);
 
+/* Autotuner for the batched engine: times the per-source passes of a fixed
+ * seeded sample of RV(r) (at most max_sources sources) under each candidate
+ * (groups in {1,2,4,...,max_groups}, block in {256,512}, grid_mult in
+ * {4,8,16}), keeps the configuration with the highest traversed arcs per
+ * second, installs it on the graph and returns it in *best (and its rate in
+ * *gteps, may be NULL).  Results of later calls do not depend on the choice
+ * (batch composition never changes a per-source value).  Errors:
+ * INVALID_ARG (r out of range, RV(r) empty, max_groups < 1). */
+bcd_status bcd_autotune(bcd_graph *g, bcd_vid r, int32_t max_groups, int64_t max_sources, bcd_config *best,
+                        double *gteps);
+
 /* RV(r) of Def.1, found as Def.3 / Prop.2 prescribe: a breadth-first
  * traversal from r on the resident reverse graph, weights ignored, r left
  * out.  Writes the ids ascending into out[0 .. *count-1] if cap suffices;

@@ -117,6 +117,7 @@ SIGNATURES = {
     "bcd_profile_get": [_p, _i32, C.POINTER(KernelProfile)],
     "bcd_profile_reset": [_p],
     "bcd_bandwidth_probe": [_i64, _i32, C.POINTER(_d)],
+    "bcd_autotune": [_p, _i32, _i32, _i64, C.POINTER(Config), C.POINTER(_d)],
     "bcd_server_create": [_p, C.POINTER(ServerConfig), C.POINTER(_p)],
     "bcd_server_submit": [_p, C.POINTER(Query), C.POINTER(_u64)],
     "bcd_server_poll": [_p, _p, _i32, C.POINTER(_i32), _i64],
@@ -287,6 +288,12 @@ class Graph:
         check(load().bcd_dependencies(self.h, r, _ptr(src), src.size, _ptr(dep), _ptr(cnt)),
               "bcd_dependencies")
         return (dep, cnt) if counters else dep
+
+    def autotune(self, r: int, max_groups: int = 16, max_sources: int = 4096):
+        c = Config()
+        rate = C.c_double()
+        check(load().bcd_autotune(self.h, r, max_groups, max_sources, C.byref(c), C.byref(rate)), "bcd_autotune")
+        return c, rate.value
 
     # -- profiling
     def profile_enable(self, on: bool = True):

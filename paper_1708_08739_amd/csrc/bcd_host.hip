@@ -117,6 +117,7 @@ void Workspace::release() {
   dfree(S.tgt_of);
   dfree(S.res);
   dfree(S.ctr);
+  dfree(S.acc);
   dfree(S.flags);
   dfree(S.ovl);
   dfree(d_items0);
@@ -130,6 +131,7 @@ void Workspace::release() {
   dfree(P.cnt);
   dfree(P.off);
   dfree(P.ctr);
+  dfree(P.acc);
   dfree(P.flags);
   dfree(bitmap);
   dfree(rq[0]);
@@ -178,7 +180,7 @@ bcd_status Workspace::ensure_batch(int G_) {
     release_weighted();
     dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.bt);
     dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tlev); dfree(S.tmin);
-    dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.flags); dfree(S.ovl);
+    dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
     dfree(d_items0); dfree(d_masks0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0); hfree(h_res);
     batch_ready = false;
   }
@@ -194,7 +196,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.vis, GN));
   STCHK(dalloc(&S.fr, 3 * GN));
   STCHK(dalloc(&S.bt, 2 * GN));
-  S.cap = std::min<uint64_t>((uint64_t)GN * 4, (uint64_t)GN * kLanes);
+  S.cap = (uint64_t)GN * 16;
   STCHK(dalloc(&S.items, S.cap));
   STCHK(dalloc(&S.imask, S.cap));
   const size_t levels = (size_t)n + kLevelChunkMax + 4;
@@ -207,6 +209,8 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.ovl, (size_t)G));
   S.ctr_slots = kCtrSlots;
   STCHK(dalloc(&S.ctr, (size_t)kCtrSlots * C_COUNT));
+  STCHK(dalloc(&S.acc, (size_t)C_COUNT));
+  HIPCHK(hipMemsetAsync(S.acc, 0, (size_t)C_COUNT * sizeof(uint64_t), stream));
   res_cap = (size_t)G * kLanes;
   STCHK(dalloc(&S.res, res_cap));
   STCHK(dalloc(&d_items0, (size_t)G * kLanes));
@@ -250,7 +254,7 @@ bcd_status Workspace::ensure_dout() {
 
 bcd_status Workspace::grow_items() {
   const uint64_t GN = (uint64_t)G * (uint64_t)n;
-  const uint64_t ncap = std::min<uint64_t>(S.cap * 2, GN * kLanes + 1);
+  const uint64_t ncap = std::min<uint64_t>(S.cap * 2, GN * kLanes + (uint64_t)kLanes * G);
   dfree(S.items);
   dfree(S.imask);
   S.cap = ncap;
@@ -268,6 +272,7 @@ bcd_status Workspace::reset_batch_dense() {
   HIPCHK(hipMemsetAsync(S.fr, 0, 3 * GN * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)n + kLevelChunkMax + 4) * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), stream));
+  HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));
   HIPCHK(hipStreamSynchronize(stream));
   return BCD_OK;
 }
@@ -287,6 +292,8 @@ bcd_status Workspace::ensure_plain() {
   STCHK(dalloc(&P.flags, 4));
   P.ctr_slots = kCtrSlots;
   STCHK(dalloc(&P.ctr, (size_t)kCtrSlots * C_COUNT));
+  STCHK(dalloc(&P.acc, (size_t)C_COUNT));
+  HIPCHK(hipMemsetAsync(P.acc, 0, (size_t)C_COUNT * sizeof(uint64_t), stream));
   if (!h_cnt) STCHK(halloc(&h_cnt, kLevelChunkMax + 8));
   if (!h_misc) STCHK(halloc(&h_misc, 64));
   if (!h_ctr) STCHK(halloc(&h_ctr, (size_t)kCtrSlots * C_COUNT));
@@ -523,7 +530,7 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
     return fail(BCD_ERR_INVALID_ARG, "groups must be >= 1 with groups * n < 2^32");
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256 && cfg->block != 512)
     return fail(BCD_ERR_INVALID_ARG, "block must be 64, 128, 256 or 512");
-  if (cfg->grid_mult < 1 || cfg->grid_mult > 64) return fail(BCD_ERR_INVALID_ARG, "grid_mult must be in [1, 64]");
+  if (cfg->grid_mult < 1 || cfg->grid_mult > 32) return fail(BCD_ERR_INVALID_ARG, "grid_mult must be in [1, 32]");
   std::lock_guard<std::mutex> lk(g->cfg_mu);
   g->cfg = *cfg;
   return BCD_OK;

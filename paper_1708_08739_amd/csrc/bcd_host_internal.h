@@ -26,7 +26,7 @@
 
 namespace bcd {
 
-constexpr int kCtrSlots = 16384;      // max workgroups of a traversal launch
+constexpr int kCtrSlots = 8192;       // max workgroups of a traversal launch
 constexpr int kLevelChunkMax = 64;    // level launches enqueued between host checks
 
 bcd_status fail(bcd_status s, const std::string &msg);
@@ -153,6 +153,7 @@ bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t 
 bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
 bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
 double compensated_sum(const double *x, size_t k, size_t stride);
+bcd_status collect_counters(Workspace *ws, uint64_t *ctr, uint64_t *dev_acc);
 uint64_t splitmix_at(uint64_t seed, uint64_t t);
 uint64_t index_below(uint64_t x, uint64_t k);
 void bits_to_list(const std::vector<uint32_t> &bits, int64_t n, int32_t skip, std::vector<int32_t> &out);

@@ -53,6 +53,7 @@ struct BatchState {
   int32_t *tgt_of;           // [n] target index of a vertex, -1 if none
   double *res;               // [ntgt][G][64] delta of lane on target
   uint64_t *ctr;             // [grid][C_COUNT] per-workgroup counters
+  uint64_t *acc;             // [C_COUNT] counters of completed batches
   uint32_t *flags;           // [4]: 0 sigma overflow, 1 item capacity exceeded
   unsigned long long *ovl;   // [G] lanes whose sigma overflowed
   uint32_t epoch;
@@ -78,6 +79,7 @@ struct PlainState {
   uint32_t *cnt;             // [n + 2]
   uint64_t *off;             // [n + 2]
   uint64_t *ctr;             // [grid][C_COUNT]
+  uint64_t *acc;             // [C_COUNT]
   uint32_t *flags;           // [4]
   int ctr_slots;
 };
@@ -141,6 +143,9 @@ struct ResultRoute {
   uint32_t pad;
 };
 hipError_t launch_route_results(const double *res, const ResultRoute *routes, int k, hipStream_t st);
+// Add the per-workgroup counter slots into acc[C_COUNT] and zero them (one
+// launch after every completed batch; an aborted batch just zeroes them).
+hipError_t launch_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc, hipStream_t st);
 hipError_t launch_copy_probe(const double *src, double *dst, int64_t n, hipStream_t st);
 
 }  // namespace bcd

@@ -549,6 +549,30 @@ __global__ void k_plain_gather(PlainState P, const int32_t *verts, int k, int32_
   }
 }
 
+__global__ void k_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc) {
+  __shared__ uint64_t part[256];
+  for (int k = 0; k < C_COUNT; ++k) {
+    uint64_t s = 0;
+    for (int i = threadIdx.x; i < slots; i += blockDim.x) {
+      s += ctr[(size_t)i * C_COUNT + k];
+      ctr[(size_t)i * C_COUNT + k] = 0;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[k] += part[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctr_fold, dim3(1), dim3(256), 0, st, ctr, slots, acc);
+  return hipGetLastError();
+}
+
 __global__ void k_route_results(const double *res, const ResultRoute *routes, int k) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
     *routes[i].dst = res[routes[i].src];

@@ -253,6 +253,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     if (ovl_out)
       HIPCHK(hipMemcpyAsync(ovl_out, S.ovl, (size_t)ws->G * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIPCHK(launch_batch_cleanup(S, total, L, st));
+    HIPCHK(launch_ctr_fold(S.ctr, kCtrSlots, S.acc, st));
     HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
     if (profiling && prof) {
@@ -268,15 +269,14 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
   }
 }
 
-static bcd_status collect_counters(Workspace *ws, uint64_t *ctr /*[C_COUNT]*/, uint64_t *dev_ctr) {
+// Counters of the batches completed since the last collection (folded on the
+// device after each batch), then reset.
+bcd_status collect_counters(Workspace *ws, uint64_t *ctr /*[C_COUNT]*/, uint64_t *dev_acc) {
   hipStream_t st = ws->stream;
-  HIPCHK(hipMemcpyAsync(ws->h_ctr, dev_ctr, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                        st));
-  HIPCHK(hipMemsetAsync(dev_ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), st));
+  HIPCHK(hipMemcpyAsync(ws->h_ctr, dev_acc, (size_t)C_COUNT * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemsetAsync(dev_acc, 0, (size_t)C_COUNT * sizeof(uint64_t), st));
   HIPCHK(hipStreamSynchronize(st));
-  for (int k = 0; k < C_COUNT; ++k) ctr[k] = 0;
-  for (int s = 0; s < kCtrSlots; ++s)
-    for (int k = 0; k < C_COUNT; ++k) ctr[k] += ws->h_ctr[(size_t)s * C_COUNT + k];
+  for (int k = 0; k < C_COUNT; ++k) ctr[k] = ws->h_ctr[k];
   return BCD_OK;
 }
 
@@ -319,14 +319,14 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
       for (int t = 0; t < ntgt; ++t) out.dep[(b0 + i) * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
     if (want_counters) {
       uint64_t c[C_COUNT];
-      STCHK(collect_counters(ws, c, ws->S.ctr));
+      STCHK(collect_counters(ws, c, ws->S.acc));
       out.counters[b0 * 3 + 0] = c[C_FWD_VPAIRS];
       out.counters[b0 * 3 + 1] = c[C_FWD_APAIRS];
       out.counters[b0 * 3 + 2] = c[C_FWD_DPAIRS];
       for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
     }
   }
-  if (!want_counters) STCHK(collect_counters(ws, tot, ws->S.ctr));
+  if (!want_counters) STCHK(collect_counters(ws, tot, ws->S.acc));
   out.te = tot[C_FWD_APAIRS];
   out.reached = tot[C_FWD_VPAIRS];
   out.dag = tot[C_FWD_DPAIRS];
@@ -430,6 +430,7 @@ static bcd_status run_plain_one(Graph *g, Workspace *ws, int32_t s, const int32_
   uint64_t total = 0;
   for (uint32_t c : cnt) total += c;
   HIPCHK(launch_plain_cleanup(P, total, st));
+  HIPCHK(launch_ctr_fold(P.ctr, kCtrSlots, P.acc, st));
   HIPCHK(hipMemsetAsync(P.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
   HIPCHK(hipMemcpyAsync(ws->h_misc, P.flags, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -475,7 +476,7 @@ static bcd_status run_plain(Graph *g, Workspace *ws, const std::vector<int32_t> 
                        &prof, &ovf);
     if (rc == BCD_OK && want_counters) {
       uint64_t c[C_COUNT];
-      rc = collect_counters(ws, c, ws->P.ctr);
+      rc = collect_counters(ws, c, ws->P.acc);
       out.counters[i * 3 + 0] = c[C_FWD_VPAIRS];
       out.counters[i * 3 + 1] = c[C_FWD_APAIRS];
       out.counters[i * 3 + 2] = c[C_FWD_DPAIRS];
@@ -484,7 +485,7 @@ static bcd_status run_plain(Graph *g, Workspace *ws, const std::vector<int32_t> 
   }
   if (d_tgt) (void)hipFree(d_tgt);
   if (rc != BCD_OK) return rc;
-  if (!want_counters) STCHK(collect_counters(ws, tot, ws->P.ctr));
+  if (!want_counters) STCHK(collect_counters(ws, tot, ws->P.acc));
   out.te = tot[C_FWD_APAIRS];
   out.reached = tot[C_FWD_VPAIRS];
   out.dag = tot[C_FWD_DPAIRS];
@@ -805,7 +806,7 @@ bcd_status bcd_multi_source_pass(const bcd_graph *gh, const bcd_vid *sources, in
   }
   cleanup();
   uint64_t c[C_COUNT];
-  if (rc == BCD_OK) rc = collect_counters(ws, c, ws->S.ctr);
+  if (rc == BCD_OK) rc = collect_counters(ws, c, ws->S.acc);
   if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return rc;
 }
@@ -847,7 +848,7 @@ bcd_status bcd_source_pass(const bcd_graph *gh, bcd_vid s, uint64_t *dist, uint6
   }
   cleanup();
   uint64_t c[C_COUNT];
-  if (rc == BCD_OK) rc = collect_counters(ws, c, ws->P.ctr);
+  if (rc == BCD_OK) rc = collect_counters(ws, c, ws->P.acc);
   if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return rc;
 }

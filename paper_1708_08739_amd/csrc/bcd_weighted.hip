@@ -526,6 +526,7 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     if (ovl_out)
       HIPCHK(hipMemcpyAsync(ovl_out, S.ovl, (size_t)ws->G * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIPCHK(launch_w_cleanup(S, L, st));
+    HIPCHK(launch_ctr_fold(S.ctr, kCtrSlots, S.acc, st));
     HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
     if (profiling) {
@@ -545,17 +546,7 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
   }
 }
 
-static bcd_status wcounters(Workspace *ws, uint64_t *c) {
-  hipStream_t st = ws->stream;
-  HIPCHK(hipMemcpyAsync(ws->h_ctr, ws->S.ctr, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                        st));
-  HIPCHK(hipMemsetAsync(ws->S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), st));
-  HIPCHK(hipStreamSynchronize(st));
-  for (int k = 0; k < C_COUNT; ++k) c[k] = 0;
-  for (int s = 0; s < kCtrSlots; ++s)
-    for (int k = 0; k < C_COUNT; ++k) c[k] += ws->h_ctr[(size_t)s * C_COUNT + k];
-  return BCD_OK;
-}
+static bcd_status wcounters(Workspace *ws, uint64_t *c) { return collect_counters(ws, c, ws->S.acc); }
 
 static void wprofile(Graph *g, double msf, double msb, int64_t lf, int64_t lb, const uint64_t *c) {
   const double fb = 32.0 * c[C_FWD_VPAIRS] + 8.0 * c[C_FWD_APAIRS] + 8.0 * c[C_FWD_DPAIRS];
