@@ -194,7 +194,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.sig, GN * kLanes));
   STCHK(dalloc(&S.psi, GN * kLanes));
   STCHK(dalloc(&S.vis, GN));
-  STCHK(dalloc(&S.fr, 3 * GN));
+  STCHK(dalloc(&S.fr, 4 * GN));
   STCHK(dalloc(&S.bt, 2 * GN));
   S.cap = (uint64_t)GN * 16;
   STCHK(dalloc(&S.items, S.cap));
@@ -224,7 +224,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   if (!h_ctr) STCHK(halloc(&h_ctr, (size_t)kCtrSlots * C_COUNT));
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.fr, 0, 3 * GN * sizeof(uint64_t), stream));
+  HIPCHK(hipMemsetAsync(S.fr, 0, 4 * GN * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.bt, 0, 2 * GN * sizeof(LevMask), stream));
   HIPCHK(hipMemsetAsync(S.cnt, 0, levels * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.off, 0, levels * sizeof(uint64_t), stream));
@@ -269,7 +269,7 @@ bcd_status Workspace::reset_batch_dense() {
   const size_t GN = (size_t)G * (size_t)n;
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.fr, 0, 3 * GN * sizeof(uint64_t), stream));
+  HIPCHK(hipMemsetAsync(S.fr, 0, 4 * GN * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)n + kLevelChunkMax + 4) * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));

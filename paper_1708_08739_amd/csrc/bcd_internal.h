@@ -41,7 +41,7 @@ struct BatchState {
   double *psi;               // [G][n][64] (1 + delta) / sigma
   double *dout;              // [G][n][64] delta, verification hook only (may be null)
   unsigned long long *vis;   // [G][n] lanes settled on a level < current (lagging, see kernel)
-  unsigned long long *fr;    // [3][G][n] rotating level masks: current, next, retiring
+  unsigned long long *fr;    // [4][G][n] rotating level masks: current, next, previous, retiring
   LevMask *bt;               // [2][G][n] backward level masks, by level parity
   uint32_t *items;           // [cap] g * n + v, grouped by level
   unsigned long long *imask; // [cap] lanes of the item on its level

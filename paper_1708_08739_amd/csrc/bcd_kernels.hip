@@ -33,14 +33,18 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
   (void)GN;
 }
 
-// One BFS level of the batched forward pass (unweighted graphs).
-//   For every item (g, v, mask) on `level`: for every out-arc (v, w), the
-//   lanes b in mask for which w is not settled on a level <= `level` are
-//   exactly the lanes where (v, w) is a shortest-path-DAG arc; those lanes
-//   add sigma(v) to sigma(w) (the forward half of the pass that Eq.(4)
-//   then walks backwards).  The first wavefront to flag (g, w) for level+1
-//   appends it to the next level's item list.
-// Visibility: masks of `level` (cur) were completed by the previous launch.
+// One BFS level of the batched forward pass (unweighted graphs).  For every
+// item (g, v, mask) on `level`:
+//   1. sigma pull: sigma_b(v) = sum of sigma_b(u) over in-arcs (u, v) with u
+//      on level-1 for lane b (the shortest-path-DAG predecessors of v), an
+//      exact uint64 sum with a carry check on every add; no atomics, and the
+//      row loads of four predecessors are issued together;
+//   2. discovery: for every out-arc (v, w), lanes b in mask for which w is
+//      not settled on a level <= `level` are DAG arcs; they are flagged on
+//      (g, w) for level+1 with one atomicOr per arc, lanes over arcs, and
+//      the first flagger appends (g, w) to the next level's item list.
+// Level masks rotate over four arrays: cur (level), nxt (level+1, being
+// built), prv (level-1, read by the pull) and old (level-2, retired here).
 // vis lags: the owner of (g, v) ORs cur into vis during this launch, so a
 // reader sees vis | cur, which is the same union either way.
 template <int BLOCK>
@@ -48,19 +52,20 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
   const uint64_t n = (uint64_t)S.n;
   const uint64_t GN = (uint64_t)S.G * n;
   const uint64_t base = S.off[level];
-  uint64_t count = S.cnt[level];
+  const uint64_t count = S.cnt[level];
   const uint64_t nbase = base + count;
   if (blockIdx.x == 0 && threadIdx.x == 0) S.off[level + 1] = nbase;
   if (S.flags[1] != 0u || nbase > S.cap) return;  // capacity exceeded earlier: batch is redone
   const int lane = lane_id();
-  ull *cur = S.fr + (uint64_t)(level % 3) * GN;
-  ull *nxt = S.fr + (uint64_t)((level + 1) % 3) * GN;
-  ull *old = S.fr + (uint64_t)((level + 2) % 3) * GN;
+  ull *cur = S.fr + (uint64_t)(level & 3) * GN;
+  ull *nxt = S.fr + (uint64_t)((level + 1) & 3) * GN;
+  ull *old = S.fr + (uint64_t)((level + 2) & 3) * GN;
+  const ull *prv = S.fr + (uint64_t)((level + 3) & 3) * GN;
 
-  // retire the masks of level-1 so that array can collect level+2
-  if (level > 0) {
-    const uint64_t pb = S.off[level - 1];
-    const uint64_t pc = S.cnt[level - 1];
+  // retire the masks of level-2 so that array can collect level+2
+  if (level >= 2) {
+    const uint64_t pb = S.off[level - 2];
+    const uint64_t pc = S.cnt[level - 2];
     for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pc; i += (uint64_t)gridDim.x * BLOCK)
       old[S.items[pb + i]] = 0ull;
   }
@@ -80,11 +85,58 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
       S.vis[it] = S.vis[it] | mask;
     }
     const bool act = (mask >> lane) & 1ull;
-    const ull sv = act ? S.sig[(uint64_t)it * kLanes + lane] : 0ull;
     if (S.tgt_of[v] >= 0) {
       if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
       if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
     }
+
+    // 1. path counts of this level's lanes, pulled from level-1
+    if (level > 0) {
+      ull acc = 0ull;
+      bool lov = false;
+      const int64_t f0 = G.irp[v], f1 = G.irp[v + 1];
+      for (int64_t e = f0; e < f1; e += 64) {
+        const int64_t my = e + lane;
+        uint32_t u = 0;
+        ull pm = 0ull;
+        if (my < f1) {
+          u = (uint32_t)G.icol[my];
+          pm = prv[gbase + u] & mask;
+        }
+        c_d += (uint64_t)__popcll(pm);
+        ull bits = __ballot(pm != 0ull);
+        while (bits != 0ull) {
+          int j[4];
+          int c = 0;
+          for (; c < 4 && bits != 0ull; ++c) {
+            j[c] = __ffsll((long long)bits) - 1;
+            bits &= bits - 1ull;
+          }
+          ull x[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (q < c) {
+              const uint32_t uq = read_lane(u, j[q]);
+              const ull dq = read_lane64(pm, j[q]);
+              if ((dq >> lane) & 1ull) x[q] = S.sig[(gbase + uq) * kLanes + lane];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const ull t = acc + x[q];
+            if (t < acc) lov = true;
+            acc = t;
+          }
+        }
+      }
+      if (act) S.sig[(uint64_t)it * kLanes + lane] = acc;
+      if (lov) {
+        ovf = true;
+        atomicOr(&S.ovl[g], 1ull << lane);
+      }
+    }
+
+    // 2. discovery of level+1
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
     const uint64_t pc = (uint64_t)__popcll(mask);
     if (lane == 0) {
@@ -94,14 +146,12 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
     for (int64_t e = e0; e < e1; e += 64) {
       const int64_t my = e + lane;
       uint32_t w = 0;
-      ull dag = 0ull;
+      bool enq = false;
       if (my < e1) {
         w = (uint32_t)G.col[my];
-        const ull vm = S.vis[gbase + w] | cur[gbase + w];
-        dag = mask & ~vm;
+        const ull dag = mask & ~(S.vis[gbase + w] | cur[gbase + w]);
+        if (dag != 0ull) enq = (atomicOr(&nxt[gbase + w], dag) == 0ull);
       }
-      bool enq = false;
-      if (dag != 0ull) enq = (atomicOr(&nxt[gbase + w], dag) == 0ull);
       const ull eb = __ballot(enq);
       if (eb != 0ull) {
         uint32_t p0 = 0;
@@ -111,21 +161,6 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
           const uint64_t p = nbase + p0 + (uint64_t)lanes_below(eb);
           if (p < S.cap) S.items[p] = (uint32_t)(gbase + w);
           else atomicOr(&S.flags[1], 1u);
-        }
-      }
-      c_d += (uint64_t)__popcll(dag);
-      ull bits = __ballot(dag != 0ull);
-      while (bits != 0ull) {
-        const int j = __ffsll((long long)bits) - 1;
-        bits &= bits - 1ull;
-        const uint32_t wj = read_lane(w, j);
-        const ull dj = read_lane64(dag, j);
-        if ((dj >> lane) & 1ull) {
-          const ull o = atomicAdd(&S.sig[(gbase + wj) * kLanes + lane], sv);
-          if (o + sv < o) {
-            ovf = true;
-            atomicOr(&S.ovl[g], 1ull << lane);
-          }
         }
       }
     }
@@ -182,11 +217,24 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
       c_d += (uint64_t)__popcll(d);
       ull bits = __ballot(d != 0ull);
       while (bits != 0ull) {
-        const int j = __ffsll((long long)bits) - 1;
-        bits &= bits - 1ull;
-        const uint32_t wj = read_lane(w, j);
-        const ull dj = read_lane64(d, j);
-        if ((dj >> lane) & 1ull) acc += S.psi[(gbase + wj) * kLanes + lane];
+        int j[4];
+        int c = 0;
+        for (; c < 4 && bits != 0ull; ++c) {
+          j[c] = __ffsll((long long)bits) - 1;
+          bits &= bits - 1ull;
+        }
+        double x[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q < c) {
+            const uint32_t wq = read_lane(w, j[q]);
+            const ull dq = read_lane64(d, j[q]);
+            if ((dq >> lane) & 1ull) x[q] = S.psi[(gbase + wq) * kLanes + lane];
+          }
+        }
+        // arc order is kept, and adding 0.0 for a lane off the DAG leaves acc unchanged
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += x[q];
       }
     }
     if (need) {
@@ -211,7 +259,9 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
 }
 
-// Reset what the batch touched: masks and sigma rows of every item.
+// Reset what the batch touched: the masks of every item.  (Path counts need
+// no reset: every lane's count is written by the pull before anything reads
+// it, and only lanes named by a mask are ever read.)
 __global__ void k_batch_cleanup(BatchState S, uint64_t total) {
   const uint64_t GN = (uint64_t)S.G * (uint64_t)S.n;
   const int lane = lane_id();
@@ -220,9 +270,8 @@ __global__ void k_batch_cleanup(BatchState S, uint64_t total) {
   if (total > S.cap) total = S.cap;
   for (uint64_t i = wave; i < total; i += nwaves) {
     const uint32_t it = S.items[i];
-    S.sig[(uint64_t)it * kLanes + lane] = 0ull;
     if (lane == 0) S.vis[it] = 0ull;
-    if (lane < 3) S.fr[(uint64_t)lane * GN + it] = 0ull;
+    if (lane < 4) S.fr[(uint64_t)lane * GN + it] = 0ull;
   }
 }
 
