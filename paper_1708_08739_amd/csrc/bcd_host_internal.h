@@ -109,6 +109,9 @@ struct Graph {
   std::mutex pool_mu;
   std::vector<std::unique_ptr<Workspace>> pool;
   std::atomic<bool> profiling{false};
+  std::mutex lm_mu;                // landmark distance signatures (source ordering)
+  bool lm_ready = false;
+  std::vector<uint8_t> lm_sig;     // [n][16] BFS distance to each hub, 255 = unreachable
   mutable std::mutex prof_mu;
   bcd_kernel_profile prof[2]{};
 
@@ -142,7 +145,7 @@ struct SourceRun {
 
 // Query layer (bcd_query.hip).
 bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::vector<uint32_t> &bits,
-                     int64_t *count);
+                     int64_t *count, uint8_t *d_lev);
 bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
                         const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
 bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t k, uint64_t *dist,
@@ -153,6 +156,9 @@ bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t 
 bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
 bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
 double compensated_sum(const double *x, size_t k, size_t stride);
+// Positions of src in the order batches should take them (sources with
+// similar hub-distance signatures together); results never depend on it.
+bcd_status source_order(Graph *g, Workspace *ws, const std::vector<int32_t> &src, std::vector<uint32_t> &ord);
 bcd_status collect_counters(Workspace *ws, uint64_t *ctr, uint64_t *dev_acc);
 uint64_t splitmix_at(uint64_t seed, uint64_t t);
 uint64_t index_below(uint64_t x, uint64_t k);

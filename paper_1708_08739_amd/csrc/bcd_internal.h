@@ -121,8 +121,8 @@ hipError_t launch_plain_export(const PlainState &P, uint64_t total, uint64_t *di
 // Reachability BFS over one CSR (reverse graph for RV, forward for FR).
 hipError_t launch_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t root, hipStream_t st);
 hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap, const int32_t *qin,
-                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, Launch L,
-                              hipStream_t st);
+                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, uint8_t *lev, int level,
+                              Launch L, hipStream_t st);
 hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set, hipStream_t st);
 hipError_t launch_plain_gather(const PlainState &P, const int32_t *verts, int k, int32_t *d_out,
                                double *delta_out, hipStream_t st);

@@ -447,7 +447,8 @@ __global__ void k_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap,
                                                        const int32_t *qin, const uint32_t *qin_n,
-                                                       int32_t *qout, uint32_t *qout_n) {
+                                                       int32_t *qout, uint32_t *qout_n, uint8_t *lev,
+                                                       int level) {
   const int lane = lane_id();
   const uint32_t count = *qin_n;
   const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
@@ -463,6 +464,7 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
         u = col[my];
         const uint32_t bit = 1u << (u & 31);
         if (!(bitmap[u >> 5] & bit)) enq = !(atomicOr(&bitmap[u >> 5], bit) & bit);
+        if (enq && lev) lev[u] = (uint8_t)(level + 1 < 254 ? level + 1 : 254);
       }
       const ull eb = __ballot(enq);
       if (eb != 0ull) {
@@ -572,8 +574,9 @@ hipError_t launch_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t
 }
 
 hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap, const int32_t *qin,
-                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, Launch L, hipStream_t st) {
-  DISPATCH_BLOCK(L, k_reach_level, rp, col, bitmap, qin, qin_n, qout, qout_n);
+                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, uint8_t *lev, int level,
+                              Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_reach_level, rp, col, bitmap, qin, qin_n, qout, qout_n, lev, level);
   return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ uint64_t index_below(uint64_t x, uint64_t k) {
 // Def.3: the vertices that reach root) or the graph itself.  Bit v of
 // `bits` is set for every vertex met, root included; *count excludes root.
 bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::vector<uint32_t> &bits,
-                     int64_t *count) {
+                     int64_t *count, uint8_t *d_lev) {
   STCHK(ws->ensure_reach());
   const int64_t n = g->n;
   const size_t words = (size_t)(n + 31) / 32;
@@ -70,7 +70,7 @@ bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::v
     for (int i = 0; i < chunk; ++i, ++level) {
       HIPCHK(hipMemsetAsync(&ws->rqn[1 - cur], 0, sizeof(uint32_t), st));
       HIPCHK(launch_reach_level(rp, col, ws->bitmap, ws->rq[cur], &ws->rqn[cur], ws->rq[1 - cur],
-                                &ws->rqn[1 - cur], L, st));
+                                &ws->rqn[1 - cur], d_lev, (int)level, L, st));
       cur = 1 - cur;
     }
     uint32_t *h = reinterpret_cast<uint32_t *>(ws->h_misc);
@@ -98,6 +98,80 @@ void bits_to_list(const std::vector<uint32_t> &bits, int64_t n, int32_t skip, st
       if (v < n && v != skip) out.push_back((int32_t)v);
     }
   }
+}
+
+// ------------------------------------------------------ source order
+//
+// The cost of a batch grows with the number of distinct BFS levels a vertex
+// has across the 64 sources of a column group.  Sources whose distances to
+// a few hub vertices agree tend to agree everywhere, so batches are filled
+// in the order of that distance signature.  This only decides which sources
+// share a batch: each source's dependency is independent of its batch, and
+// every reduction still runs in the order the paper's sums are written in.
+
+constexpr int kLandmarks = 16;
+
+static bcd_status ensure_landmarks(Graph *g, Workspace *ws) {
+  std::lock_guard<std::mutex> lk(g->lm_mu);
+  if (g->lm_ready) return BCD_OK;
+  const int64_t n = g->n;
+  // the kLandmarks vertices of largest in-degree (ties: smaller id)
+  std::vector<int64_t> indeg((size_t)n, 0);
+  {
+    std::vector<int64_t> irp((size_t)n + 1);
+    HIPCHK(hipMemcpy(irp.data(), g->d_irp, ((size_t)n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (int64_t v = 0; v < n; ++v) indeg[(size_t)v] = irp[(size_t)v + 1] - irp[(size_t)v];
+  }
+  std::vector<int32_t> ids((size_t)n);
+  for (int64_t v = 0; v < n; ++v) ids[(size_t)v] = (int32_t)v;
+  const int k = (int)std::min<int64_t>(kLandmarks, n);
+  std::partial_sort(ids.begin(), ids.begin() + k, ids.end(), [&](int32_t a, int32_t b) {
+    return indeg[(size_t)a] != indeg[(size_t)b] ? indeg[(size_t)a] > indeg[(size_t)b] : a < b;
+  });
+  g->lm_sig.assign((size_t)n * kLandmarks, 255);
+  uint8_t *d_lev = nullptr;
+  if (hipMalloc((void **)&d_lev, (size_t)n) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BCD_ERR_OUT_OF_MEMORY, "landmark level buffer");
+  }
+  std::vector<uint8_t> lev((size_t)n);
+  std::vector<uint32_t> bits;
+  bcd_status rc = BCD_OK;
+  for (int h = 0; h < k && rc == BCD_OK; ++h) {
+    hipError_t e = hipMemsetAsync(d_lev, 255, (size_t)n, ws->stream);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "landmark reset");
+      break;
+    }
+    int64_t cnt = 0;
+    // distance from every vertex to the hub = BFS level from the hub on the reverse graph
+    rc = reach_set(g, ws, ids[(size_t)h], true, bits, &cnt, d_lev);
+    if (rc != BCD_OK) break;
+    e = hipMemcpy(lev.data(), d_lev, (size_t)n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "landmark copy");
+      break;
+    }
+    lev[(size_t)ids[(size_t)h]] = 0;
+    for (int64_t v = 0; v < n; ++v) g->lm_sig[(size_t)v * kLandmarks + h] = lev[(size_t)v];
+  }
+  (void)hipFree(d_lev);
+  if (rc == BCD_OK) g->lm_ready = true;
+  return rc;
+}
+
+// Processing order (positions into src) for the batched engines.
+bcd_status source_order(Graph *g, Workspace *ws, const std::vector<int32_t> &src, std::vector<uint32_t> &ord) {
+  ord.resize(src.size());
+  for (size_t i = 0; i < src.size(); ++i) ord[i] = (uint32_t)i;
+  if (src.size() <= (size_t)kLanes || g->n < 4096) return BCD_OK;
+  STCHK(ensure_landmarks(g, ws));
+  const uint8_t *sig = g->lm_sig.data();
+  std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+    const int c = std::memcmp(sig + (size_t)src[a] * kLandmarks, sig + (size_t)src[b] * kLandmarks, kLandmarks);
+    return c != 0 ? c < 0 : src[a] < src[b];
+  });
+  return BCD_OK;
 }
 
 // --------------------------------------------------------- targets
@@ -308,21 +382,23 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
   bool ovf = false;
   uint64_t tot[C_COUNT] = {0};
   const size_t per = want_counters ? 1 : G64;  // counters per source need one source per batch
+  std::vector<uint32_t> ord;
+  STCHK(source_order(g, ws, src, ord));
   for (size_t b0 = 0; b0 < ns; b0 += per) {
     const int k = (int)std::min(per, ns - b0);
     for (int i = 0; i < k; ++i) {
-      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[b0 + i]);
+      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[ord[b0 + i]]);
       ws->h_masks0[i] = 1ull << (i % kLanes);
     }
     STCHK(run_one_batch(g, ws, k, ntgt, false, nullptr, &prof, &ovf));
     for (int i = 0; i < k; ++i)
-      for (int t = 0; t < ntgt; ++t) out.dep[(b0 + i) * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
+      for (int t = 0; t < ntgt; ++t) out.dep[(size_t)ord[b0 + i] * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
     if (want_counters) {
       uint64_t c[C_COUNT];
       STCHK(collect_counters(ws, c, ws->S.acc));
-      out.counters[b0 * 3 + 0] = c[C_FWD_VPAIRS];
-      out.counters[b0 * 3 + 1] = c[C_FWD_APAIRS];
-      out.counters[b0 * 3 + 2] = c[C_FWD_DPAIRS];
+      out.counters[(size_t)ord[b0] * 3 + 0] = c[C_FWD_VPAIRS];
+      out.counters[(size_t)ord[b0] * 3 + 1] = c[C_FWD_APAIRS];
+      out.counters[(size_t)ord[b0] * 3 + 2] = c[C_FWD_DPAIRS];
       for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
     }
   }
@@ -528,7 +604,7 @@ bcd_status bcd_rv(const bcd_graph *gh, bcd_vid r, bcd_vid *out, int64_t cap, int
   STCHK(lease_ws(g, ls));
   std::vector<uint32_t> bits;
   int64_t k = 0;
-  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
   if (out && k > cap) {
     *count = k;
     return fail(BCD_ERR_BUFFER_TOO_SMALL, "RV(r) has " + std::to_string(k) + " vertices");
@@ -559,7 +635,7 @@ bcd_status bcd_bc_exact(const bcd_graph *gh, bcd_vid r, double *bc, bcd_stats *s
   const double t0 = now_s();
   std::vector<uint32_t> bits;
   int64_t k = 0;
-  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
   std::vector<int32_t> rv;
   bits_to_list(bits, g->n, r, rv);
   const double t1 = now_s();
@@ -596,7 +672,7 @@ bcd_status bcd_bc_set(const bcd_graph *gh, const bcd_vid *rs, int64_t l, double 
   for (int32_t r : tg) {
     if (g->outdeg(r) == 0) continue;
     int64_t k = 0;
-    STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+    STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
     bits[(size_t)r >> 5] &= ~(1u << (r & 31));
     for (size_t i = 0; i < uni.size(); ++i) uni[i] |= bits[i];
   }
@@ -649,7 +725,7 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
   const double t0 = now_s();
   std::vector<uint32_t> bits;
   int64_t k = 0;
-  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
   std::vector<int32_t> rv;
   bits_to_list(bits, g->n, r, rv);
   s.rv_size = k;
@@ -659,7 +735,7 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
     if (!(p->flags & BCD_K_TRIVIAL)) {
       int64_t fr = 0;
       std::vector<uint32_t> fb;
-      STCHK(reach_set(g, ls.w.get(), r, false, fb, &fr));
+      STCHK(reach_set(g, ls.w.get(), r, false, fb, &fr, nullptr));
       s.fr_size = fr;
       K = (double)fr;
     }

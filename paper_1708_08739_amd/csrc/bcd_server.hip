@@ -49,6 +49,7 @@ struct SQuery {
   std::vector<int32_t> targets;  // distinct targets
   std::vector<int32_t> sources;  // distinct sources, in reduction order
   std::vector<int64_t> draw;     // sampled: draw -> source slot
+  std::vector<uint32_t> order;   // scheduling order of the source slots
   double *dres = nullptr;        // device [ns][nt]
   size_t bytes = 0;
   size_t next = 0;               // next source to schedule
@@ -136,7 +137,7 @@ static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
     std::vector<uint32_t> uni((size_t)(g->n + 31) / 32, 0u);
     for (int32_t r : q.targets) {
       if (g->outdeg(r) == 0) continue;
-      STCHK(reach_set(g, ws, r, true, bits, &k));
+      STCHK(reach_set(g, ws, r, true, bits, &k, nullptr));
       bits[(size_t)r >> 5] &= ~(1u << (r & 31));
       for (size_t i = 0; i < uni.size(); ++i) uni[i] |= bits[i];
     }
@@ -151,7 +152,7 @@ static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
     st.rv_size = -1;
     return BCD_OK;
   }
-  STCHK(reach_set(g, ws, r, true, bits, &k));
+  STCHK(reach_set(g, ws, r, true, bits, &k, nullptr));
   std::vector<int32_t> rv;
   bits_to_list(bits, g->n, r, rv);
   st.rv_size = k;
@@ -167,7 +168,7 @@ static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
     if (!(p.flags & BCD_K_TRIVIAL)) {
       int64_t fr = 0;
       std::vector<uint32_t> fb;
-      STCHK(reach_set(g, ws, r, false, fb, &fr));
+      STCHK(reach_set(g, ws, r, false, fb, &fr, nullptr));
       st.fr_size = fr;
       K = (double)fr;
     }
@@ -209,6 +210,7 @@ static void planner_loop(bcd_server *S) {
     }
     const double t0 = steady_now();
     bcd_status rc = plan_query(S, ws, *q);
+    if (rc == BCD_OK) rc = source_order(S->g, ws, q->sources, q->order);
     q->res.stats.t_rv_s = steady_now() - t0;
     const size_t cells = q->sources.size() * q->targets.size();
     q->bytes = std::max<size_t>(cells, 1) * sizeof(double);
@@ -294,14 +296,15 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
       std::unordered_map<int32_t, size_t> where;
       for (auto &q : S->active) {
         while (q->next < q->sources.size() && lanes.size() < width) {
-          const int32_t s = q->sources[q->next];
+          const uint32_t slot = q->order[q->next];
+          const int32_t s = q->sources[slot];
           auto it = where.find(s);
           if (it == where.end()) {
             where.emplace(s, lanes.size());
             lanes.push_back(Lane{s, {}});
             it = where.find(s);
           }
-          lanes[it->second].users.emplace_back(q, (uint32_t)q->next);
+          lanes[it->second].users.emplace_back(q, slot);
           q->next++;
         }
         if (lanes.size() >= width) break;

@@ -24,7 +24,7 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
     STCHK(ls->init_common(g));
     std::vector<uint32_t> bits;
     int64_t k = 0;
-    STCHK(reach_set(g, ls.w.get(), r, true, bits, &k));
+    STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
     bits_to_list(bits, g->n, r, rv);
   }
   if (rv.empty()) return fail(BCD_ERR_INVALID_ARG, "RV(r) is empty");

@@ -588,6 +588,8 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   const bool one = want_counters || cfg.engine == BCD_ENGINE_PLAIN;
   const size_t per = one ? 1 : G64;
   out.width = (int32_t)per;
+  std::vector<uint32_t> ord;
+  STCHK(source_order(g, ws, src, ord));
   double msf = 0, msb = 0;
   int64_t lf = 0, lb = 0;
   bool ovf = false;
@@ -596,19 +598,19 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   for (size_t b0 = 0; b0 < ns && rc == BCD_OK; b0 += per) {
     const int k = (int)std::min(per, ns - b0);
     for (int i = 0; i < k; ++i) {
-      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[b0 + i]);
+      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[ord[b0 + i]]);
       ws->h_masks0[i] = 1ull << (i % kLanes);
     }
     rc = run_one_wbatch(g, ws, k, ntgt, false, nullptr, &msf, &msb, &lf, &lb, &ovf);
     if (rc != BCD_OK) break;
     for (int i = 0; i < k; ++i)
-      for (int t = 0; t < ntgt; ++t) out.dep[(b0 + i) * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
+      for (int t = 0; t < ntgt; ++t) out.dep[(size_t)ord[b0 + i] * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
     if (want_counters) {
       uint64_t c[C_COUNT];
       rc = wcounters(ws, c);
-      out.counters[b0 * 3 + 0] = c[C_FWD_VPAIRS];
-      out.counters[b0 * 3 + 1] = c[C_FWD_APAIRS];
-      out.counters[b0 * 3 + 2] = c[C_FWD_DPAIRS];
+      out.counters[(size_t)ord[b0] * 3 + 0] = c[C_FWD_VPAIRS];
+      out.counters[(size_t)ord[b0] * 3 + 1] = c[C_FWD_APAIRS];
+      out.counters[(size_t)ord[b0] * 3 + 2] = c[C_FWD_DPAIRS];
       for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
     }
   }
