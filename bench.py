@@ -181,6 +181,8 @@ def main():
     ap.add_argument("--workers", type=int, default=2, help="serving: concurrent batches")
     ap.add_argument("--hbm-budget", type=int, default=64, help="serving: HBM budget in GiB")
     ap.add_argument("--set-size", type=int, default=64)
+    ap.add_argument("--probe-bw", action="store_true",
+                    help="also run the library's streaming-copy probe (1 GiB copied, known traffic)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
@@ -294,6 +296,11 @@ def main():
         cpu = cpu_baseline(g, queries[0], args.cpu_budget, threads)
         log(f"[bench] cpu baseline: {cpu}")
 
+    bw = None
+    if args.probe_bw:
+        bw = round(bcd.bcd_bandwidth_probe(1 << 30, 3), 1)
+        log(f"[bench] copy probe: {bw} GB/s (1 GiB read + 1 GiB written per launch)")
+
     lat_ms = np.array(lat) * 1e3
     value = te_total / wall / 1e9
     out = {
@@ -319,6 +326,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if bw is not None:
+        out["copy_probe_gbs"] = bw
     print(json.dumps(out), flush=True)
 
 

@@ -69,4 +69,25 @@ __device__ __forceinline__ void flush_counters(uint64_t *ctr, int slots, int k0,
   }
 }
 
+// This workgroup's share of a partitioned item list (see BatchState).
+struct PartView {
+  int p;              // partition served
+  uint64_t wave;      // this wavefront's index within the partition
+  uint64_t nwaves;    // wavefronts serving the partition
+  uint64_t thread;    // this thread's index within the partition
+  uint64_t nthreads;
+};
+
+template <int BLOCK>
+static __device__ __forceinline__ PartView part_view(int P) {
+  PartView r;
+  r.p = (int)(blockIdx.x % (unsigned)P);
+  const uint64_t lb = blockIdx.x / (unsigned)P, nwg = gridDim.x / (unsigned)P;
+  r.wave = (lb * BLOCK + threadIdx.x) >> 6;
+  r.nwaves = (nwg * BLOCK) >> 6;
+  r.thread = lb * BLOCK + threadIdx.x;
+  r.nthreads = nwg * BLOCK;
+  return r;
+}
+
 }  // namespace bcd

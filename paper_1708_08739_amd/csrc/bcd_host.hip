@@ -122,6 +122,8 @@ void Workspace::release() {
   dfree(S.ovl);
   dfree(d_items0);
   dfree(d_masks0);
+  dfree(d_dest0);
+  hfree(h_dest0);
   dfree(d_lane_slot);
   dfree(P.d);
   dfree(P.sig);
@@ -181,7 +183,8 @@ bcd_status Workspace::ensure_batch(int G_) {
     dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.bt);
     dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tlev); dfree(S.tmin);
     dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
-    dfree(d_items0); dfree(d_masks0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0); hfree(h_res);
+    dfree(d_items0); dfree(d_masks0); dfree(d_dest0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0);
+    hfree(h_dest0); hfree(h_res);
     batch_ready = false;
   }
   if ((uint64_t)G_ * (uint64_t)n >= (1ull << 32))
@@ -196,10 +199,12 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.vis, GN));
   STCHK(dalloc(&S.fr, 4 * GN));
   STCHK(dalloc(&S.bt, 2 * GN));
-  S.cap = (uint64_t)GN * 16;
+  S.P = std::min(kMaxParts, G);
+  S.capP = ((uint64_t)GN * 16 + (uint64_t)S.P - 1) / (uint64_t)S.P;
+  S.cap = S.capP * (uint64_t)S.P;
   STCHK(dalloc(&S.items, S.cap));
   STCHK(dalloc(&S.imask, S.cap));
-  const size_t levels = (size_t)n + kLevelChunkMax + 4;
+  const size_t levels = ((size_t)n + kLevelChunkMax + 4) * kMaxParts;
   STCHK(dalloc(&S.cnt, levels));
   STCHK(dalloc(&S.off, levels));
   STCHK(dalloc(&S.tlev, (size_t)G * kLanes));
@@ -215,11 +220,13 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.res, res_cap));
   STCHK(dalloc(&d_items0, (size_t)G * kLanes));
   STCHK(dalloc(&d_masks0, (size_t)G * kLanes));
+  STCHK(dalloc(&d_dest0, (size_t)G * kLanes));
+  STCHK(halloc(&h_dest0, (size_t)G * kLanes));
   STCHK(dalloc(&d_lane_slot, (size_t)G * kLanes));
   STCHK(halloc(&h_items0, (size_t)G * kLanes));
   STCHK(halloc(&h_masks0, (size_t)G * kLanes));
   STCHK(halloc(&h_res, res_cap));
-  if (!h_cnt) STCHK(halloc(&h_cnt, kLevelChunkMax + 8));
+  if (!h_cnt) STCHK(halloc(&h_cnt, kCntStage + 16));
   if (!h_misc) STCHK(halloc(&h_misc, 64));
   if (!h_ctr) STCHK(halloc(&h_ctr, (size_t)kCtrSlots * C_COUNT));
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
@@ -233,8 +240,37 @@ bcd_status Workspace::ensure_batch(int G_) {
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));
   HIPCHK(hipStreamSynchronize(stream));
   S.epoch = 0;
+  STCHK(write_partition_bases());
   batch_ready = true;
   return BCD_OK;
+}
+
+// Level 0 of partition p starts at p * capP; kernels only ever write the
+// offsets of later levels.
+bcd_status Workspace::write_partition_bases() {
+  std::vector<uint64_t> b((size_t)S.P);
+  for (int p = 0; p < S.P; ++p) b[(size_t)p] = (uint64_t)p * S.capP;
+  HIPCHK(hipMemcpy(S.off, b.data(), (size_t)S.P * sizeof(uint64_t), hipMemcpyHostToDevice));
+  return BCD_OK;
+}
+
+void Workspace::stage_sources(const int32_t *src, int k) {
+  for (int i = 0; i < k; ++i) {
+    h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)n + (uint64_t)src[i]);
+    h_masks0[i] = 1ull << (i % kLanes);
+  }
+  staged = k;
+  stage_sources_dest(k);
+}
+
+// Level-0 slot of every staged item in its group's partition.
+void Workspace::stage_sources_dest(int k) {
+  uint32_t fill[kMaxParts] = {0};
+  for (int i = 0; i < k; ++i) {
+    const int p = (i / kLanes) % S.P;
+    h_dest0[i] = (uint32_t)((uint64_t)p * S.capP + fill[p]++);
+  }
+  for (int p = 0; p < kMaxParts; ++p) h_cnt0[p] = fill[p];
 }
 
 bcd_status Workspace::ensure_res(size_t need) {
@@ -254,13 +290,14 @@ bcd_status Workspace::ensure_dout() {
 
 bcd_status Workspace::grow_items() {
   const uint64_t GN = (uint64_t)G * (uint64_t)n;
-  const uint64_t ncap = std::min<uint64_t>(S.cap * 2, GN * kLanes + (uint64_t)kLanes * G);
+  const uint64_t ncapP = std::min<uint64_t>(S.capP * 2, (GN * kLanes) / (uint64_t)S.P + (uint64_t)kLanes * G);
   dfree(S.items);
   dfree(S.imask);
-  S.cap = ncap;
+  S.capP = ncapP;
+  S.cap = S.capP * (uint64_t)S.P;
   STCHK(dalloc(&S.items, S.cap));
   STCHK(dalloc(&S.imask, S.cap));
-  return BCD_OK;
+  return write_partition_bases();
 }
 
 // Full reset after an aborted batch (item list overflow): the sparse cleanup
@@ -270,7 +307,7 @@ bcd_status Workspace::reset_batch_dense() {
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
   HIPCHK(hipMemsetAsync(S.fr, 0, 4 * GN * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)n + kLevelChunkMax + 4) * sizeof(uint32_t), stream));
+  HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)n + kLevelChunkMax + 4) * kMaxParts * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));
   HIPCHK(hipStreamSynchronize(stream));
@@ -294,7 +331,7 @@ bcd_status Workspace::ensure_plain() {
   STCHK(dalloc(&P.ctr, (size_t)kCtrSlots * C_COUNT));
   STCHK(dalloc(&P.acc, (size_t)C_COUNT));
   HIPCHK(hipMemsetAsync(P.acc, 0, (size_t)C_COUNT * sizeof(uint64_t), stream));
-  if (!h_cnt) STCHK(halloc(&h_cnt, kLevelChunkMax + 8));
+  if (!h_cnt) STCHK(halloc(&h_cnt, kCntStage + 16));
   if (!h_misc) STCHK(halloc(&h_misc, 64));
   if (!h_ctr) STCHK(halloc(&h_ctr, (size_t)kCtrSlots * C_COUNT));
   HIPCHK(hipMemsetAsync(P.d, 0xFF, (size_t)n * sizeof(int32_t), stream));
@@ -341,6 +378,12 @@ DevGraph Graph::dev() const {
   G.icol = d_icol;
   G.iw = d_iw;
   return G;
+}
+
+Launch Graph::launch_parts(int P) const {
+  Launch L = launch();
+  if (P > 1) L.grid = std::max(P, L.grid - L.grid % P);
+  return L;
 }
 
 Launch Graph::launch() const {

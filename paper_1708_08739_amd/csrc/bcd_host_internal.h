@@ -28,6 +28,8 @@ namespace bcd {
 
 constexpr int kCtrSlots = 8192;       // max workgroups of a traversal launch
 constexpr int kLevelChunkMax = 64;    // level launches enqueued between host checks
+constexpr int kMaxParts = 8;          // item-list partitions (one per XCD)
+constexpr int kCntStage = (kLevelChunkMax + 2) * kMaxParts;  // pinned slots for level counts
 
 bcd_status fail(bcd_status s, const std::string &msg);
 bcd_status hip_fail(hipError_t e, const char *what);
@@ -55,9 +57,12 @@ struct Workspace {
   size_t res_cap = 0;
   uint32_t *d_items0 = nullptr;
   unsigned long long *d_masks0 = nullptr;
+  uint32_t *d_dest0 = nullptr;
   int32_t *d_lane_slot = nullptr;
   uint32_t *h_items0 = nullptr;
   unsigned long long *h_masks0 = nullptr;
+  uint32_t *h_dest0 = nullptr;
+  uint32_t h_cnt0[8] = {0};  // level-0 items per partition of the staged batch
   double *h_res = nullptr;
   int last_depth = 8;
   // plain engine
@@ -85,6 +90,12 @@ struct Workspace {
   bcd_status grow_items();
   bcd_status reset_batch_dense();
   bcd_status ensure_plain();
+  // Stage a batch: lane i of the batch (column group i / 64, lane i % 64)
+  // runs source vertex src[i]; vertices must be distinct within a group.
+  void stage_sources(const int32_t *src, int k);
+  void stage_sources_dest(int k);
+  int staged = 0;
+  bcd_status write_partition_bases();
   bool weighted_ready = false;
   int weighted_G = 0;
   bcd_status ensure_weighted();
@@ -118,6 +129,7 @@ struct Graph {
   ~Graph();
   DevGraph dev() const;
   Launch launch() const;
+  Launch launch_parts(int P) const;  // grid a multiple of P
   bcd_config config() const;
   std::unique_ptr<Workspace> acquire();
   void release(std::unique_ptr<Workspace> w);

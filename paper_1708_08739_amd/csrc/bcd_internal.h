@@ -43,11 +43,18 @@ struct BatchState {
   unsigned long long *vis;   // [G][n] lanes settled on a level < current (lagging, see kernel)
   unsigned long long *fr;    // [4][G][n] rotating level masks: current, next, previous, retiring
   LevMask *bt;               // [2][G][n] backward level masks, by level parity
-  uint32_t *items;           // [cap] g * n + v, grouped by level
+  // Item lists are split into P partitions (group g belongs to partition
+  // g % P); workgroup b serves partition b % P, so with P = 8 every XCD
+  // (workgroups are dealt to the 8 XCDs round-robin) walks only its own
+  // groups and their masks stay in that XCD's L2.  Partition p owns items
+  // [p * capP, (p + 1) * capP).
+  uint32_t *items;           // [cap] g * n + v, grouped by partition, then level
   unsigned long long *imask; // [cap] lanes of the item on its level
-  uint64_t cap;
-  uint32_t *cnt;             // [n + 2] items per level
-  uint64_t *off;             // [n + 2] first item of each level
+  uint64_t cap;              // = P * capP
+  uint64_t capP;
+  int P;
+  uint32_t *cnt;             // [(n + 2) * 8] items per (level, partition): index level * P + p
+  uint64_t *off;             // [(n + 2) * 8] first item of each (level, partition)
   uint32_t *tlev;            // [G][64] smallest level at which the lane met a target
   uint32_t *tmin;            // [1] smallest over all lanes
   int32_t *tgt_of;           // [n] target index of a vertex, -1 if none
@@ -100,12 +107,15 @@ struct Launch {
 };
 
 // ---- launchers (bcd_kernels.hip) ----
+struct PartTotals {
+  uint64_t t[8];  // items per partition over all levels of a batch
+};
 hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const unsigned long long *masks0,
-                             int k, hipStream_t st);
+                             const uint32_t *dest0, int k, hipStream_t st);
 hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st);
 hipError_t launch_bwd_level(const DevGraph &G, const BatchState &S, int level, int ntgt, int full,
                             Launch L, hipStream_t st);
-hipError_t launch_batch_cleanup(const BatchState &S, uint64_t total_items, Launch L, hipStream_t st);
+hipError_t launch_batch_cleanup(const BatchState &S, const PartTotals &tot, Launch L, hipStream_t st);
 hipError_t launch_batch_export(const BatchState &S, int level, uint64_t begin, uint64_t count,
                                const int32_t *lane_slot, uint64_t *dist, unsigned long long *sigma,
                                double *delta, int64_t k, hipStream_t st);
@@ -127,8 +137,8 @@ hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, 
 hipError_t launch_plain_gather(const PlainState &P, const int32_t *verts, int k, int32_t *d_out,
                                double *delta_out, hipStream_t st);
 // weighted engine (bcd_weighted.hip)
-hipError_t launch_w_init(const BatchState &S, const uint32_t *items0, const unsigned long long *masks0, int k,
-                         hipStream_t st);
+hipError_t launch_w_init(const BatchState &S, const uint32_t *items0, const unsigned long long *masks0,
+                         const uint32_t *dest0, int k, hipStream_t st);
 hipError_t launch_w_relax(const DevGraph &G, const BatchState &S, int round, Launch L, hipStream_t st);
 hipError_t launch_w_count(const DevGraph &G, const BatchState &S, Launch L, hipStream_t st);
 hipError_t launch_w_sigma(const DevGraph &G, const BatchState &S, int round, Launch L, hipStream_t st);

@@ -20,13 +20,13 @@ namespace bcd {
 
 // Level 0: each item is (g, source vertex) with the lanes it is the source
 // of; sigma = 1 on those lanes.
-__global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *masks0, int k) {
+__global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *masks0, const uint32_t *dest0, int k) {
   const size_t GN = (size_t)S.G * (size_t)S.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     const uint32_t it = items0[i];
     const ull m = masks0[i];
     S.fr[it] = m;  // fr[0] = level-0 masks
-    S.items[i] = it;
+    S.items[dest0[i]] = it;
     for (int b = 0; b < kLanes; ++b)
       if ((m >> b) & 1ull) S.sig[(size_t)it * kLanes + b] = 1ull;
   }
@@ -47,15 +47,80 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
 // built), prv (level-1, read by the pull) and old (level-2, retired here).
 // vis lags: the owner of (g, v) ORs cur into vis during this launch, so a
 // reader sees vis | cur, which is the same union either way.
+// Sum of sigma_b(u) over the in-arcs of one 64-arc chunk whose tail u is on
+// the previous level for lane b (pm = lanes of that arc); row loads of up to
+// eight predecessors are issued before any of them is consumed.
+static __device__ __forceinline__ void pull_chunk(const BatchState &S, uint64_t gbase, uint32_t u, ull pm,
+                                                  int lane, ull &acc, bool &lov) {
+  ull bits = __ballot(pm != 0ull);
+  while (bits != 0ull) {
+    int j[8];
+    int c = 0;
+    for (; c < 8 && bits != 0ull; ++c) {
+      j[c] = __ffsll((long long)bits) - 1;
+      bits &= bits - 1ull;
+    }
+    ull x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      x[q] = 0ull;
+      if (q < c) {
+        const uint32_t uq = read_lane(u, j[q]);
+        const ull dq = read_lane64(pm, j[q]);
+        if ((dq >> lane) & 1ull) x[q] = S.sig[(gbase + uq) * kLanes + lane];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const ull t = acc + x[q];
+      if (t < acc) lov = true;
+      acc = t;
+    }
+  }
+}
+
+// Discovered heads are staged in a per-wavefront LDS buffer and copied to
+// the next level's list in blocks: one counter atomic per block instead of
+// one per out-arc chunk, which keeps the partition's tail counter cold.
+constexpr int kStage = 256;
+
+static __device__ __forceinline__ void flush_stage(const BatchState &S, uint32_t *stage, int &nst,
+                                                   uint32_t *next_cnt, uint64_t nbase, uint64_t rend) {
+  if (nst == 0) return;
+  uint32_t p0 = 0;
+  if (lane_id() == 0) p0 = atomicAdd(next_cnt, (uint32_t)nst);
+  p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+  for (int j = lane_id(); j < nst; j += 64) {
+    const uint64_t p = nbase + p0 + (uint64_t)j;
+    if (p < rend) S.items[p] = stage[j];
+    else atomicOr(&S.flags[1], 1u);
+  }
+  nst = 0;
+}
+
+static __device__ __forceinline__ void append_chunk(const BatchState &S, uint32_t *stage, int &nst,
+                                                    uint32_t *next_cnt, uint64_t nbase, uint64_t rend,
+                                                    uint64_t gbase, uint32_t w, bool enq) {
+  const ull eb = __ballot(enq);
+  if (eb == 0ull) return;
+  const int c = __popcll(eb);
+  if (nst + c > kStage) flush_stage(S, stage, nst, next_cnt, nbase, rend);
+  if (enq) stage[nst + lanes_below(eb)] = (uint32_t)(gbase + w);
+  nst += c;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, int level) {
   const uint64_t n = (uint64_t)S.n;
   const uint64_t GN = (uint64_t)S.G * n;
-  const uint64_t base = S.off[level];
-  const uint64_t count = S.cnt[level];
+  const int P = S.P;
+  const PartView pv = part_view<BLOCK>(P);
+  const uint64_t base = S.off[(uint64_t)level * P + pv.p];
+  const uint64_t count = S.cnt[(uint64_t)level * P + pv.p];
   const uint64_t nbase = base + count;
-  if (blockIdx.x == 0 && threadIdx.x == 0) S.off[level + 1] = nbase;
-  if (S.flags[1] != 0u || nbase > S.cap) return;  // capacity exceeded earlier: batch is redone
+  const uint64_t rend = (uint64_t)(pv.p + 1) * S.capP;
+  if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
+  if (S.flags[1] != 0u || nbase > rend) return;  // capacity exceeded earlier: batch is redone
   const int lane = lane_id();
   ull *cur = S.fr + (uint64_t)(level & 3) * GN;
   ull *nxt = S.fr + (uint64_t)((level + 1) & 3) * GN;
@@ -64,107 +129,98 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
 
   // retire the masks of level-2 so that array can collect level+2
   if (level >= 2) {
-    const uint64_t pb = S.off[level - 2];
-    const uint64_t pc = S.cnt[level - 2];
-    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pc; i += (uint64_t)gridDim.x * BLOCK)
-      old[S.items[pb + i]] = 0ull;
+    const uint64_t pb = S.off[(uint64_t)(level - 2) * P + pv.p];
+    const uint64_t pc = S.cnt[(uint64_t)(level - 2) * P + pv.p];
+    for (uint64_t i = pv.thread; i < pc; i += pv.nthreads) old[S.items[pb + i]] = 0ull;
   }
 
   uint64_t c_v = 0, c_a = 0, c_d = 0;
   bool ovf = false;
-  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  const uint64_t wave = pv.wave;
+  const uint64_t nwaves = pv.nwaves;
+  uint32_t *next_cnt = &S.cnt[(uint64_t)(level + 1) * P + pv.p];
+  __shared__ uint32_t stage_all[(BLOCK / 64) * kStage];
+  uint32_t *stage = stage_all + (threadIdx.x >> 6) * kStage;
+  int nst = 0;
+  uint32_t it_next = wave < count ? S.items[base + wave] : 0u;
   for (uint64_t i = wave; i < count; i += nwaves) {
-    const uint32_t it = S.items[base + i];
+    const uint32_t it = it_next;
+    if (i + nwaves < count) it_next = S.items[base + i + nwaves];  // prefetch the next item
     const uint32_t g = (uint32_t)(it / n);
     const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
     const uint64_t gbase = (uint64_t)g * n;
+    // independent loads of this item, issued together
     const ull mask = cur[it];
+    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    const int64_t f0 = level > 0 ? G.irp[v] : 0, f1 = level > 0 ? G.irp[v + 1] : 0;
+    const int32_t tg = S.tgt_of[v];
     if (lane == 0) {
       S.imask[base + i] = mask;
       S.vis[it] = S.vis[it] | mask;
     }
     const bool act = (mask >> lane) & 1ull;
-    if (S.tgt_of[v] >= 0) {
+    if (tg >= 0) {
       if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
       if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
     }
-
-    // 1. path counts of this level's lanes, pulled from level-1
-    if (level > 0) {
-      ull acc = 0ull;
-      bool lov = false;
-      const int64_t f0 = G.irp[v], f1 = G.irp[v + 1];
-      for (int64_t e = f0; e < f1; e += 64) {
-        const int64_t my = e + lane;
-        uint32_t u = 0;
-        ull pm = 0ull;
-        if (my < f1) {
-          u = (uint32_t)G.icol[my];
-          pm = prv[gbase + u] & mask;
-        }
-        c_d += (uint64_t)__popcll(pm);
-        ull bits = __ballot(pm != 0ull);
-        while (bits != 0ull) {
-          int j[4];
-          int c = 0;
-          for (; c < 4 && bits != 0ull; ++c) {
-            j[c] = __ffsll((long long)bits) - 1;
-            bits &= bits - 1ull;
-          }
-          ull x[4] = {0ull, 0ull, 0ull, 0ull};
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (q < c) {
-              const uint32_t uq = read_lane(u, j[q]);
-              const ull dq = read_lane64(pm, j[q]);
-              if ((dq >> lane) & 1ull) x[q] = S.sig[(gbase + uq) * kLanes + lane];
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const ull t = acc + x[q];
-            if (t < acc) lov = true;
-            acc = t;
-          }
-        }
+    const uint64_t pc = (uint64_t)__popcll(mask);
+    if (lane == 0) {
+      c_v += pc;
+      c_a += pc * (uint64_t)(e1 - e0);
+    }
+    // first chunk of in-arcs (sigma pull) and of out-arcs (discovery), interleaved:
+    // 1. both index chunks
+    const int64_t mi = f0 + lane, mo = e0 + lane;
+    uint32_t u = 0, w = 0;
+    if (mi < f1) u = (uint32_t)G.icol[mi];
+    if (mo < e1) w = (uint32_t)G.col[mo];
+    // 2. both mask gathers
+    ull pm = 0ull, dag = 0ull;
+    if (mi < f1) pm = prv[gbase + u] & mask;
+    // lanes already flagged for level+1 by another wavefront need no atomic
+    // (a stale read only costs a redundant atomic)
+    if (mo < e1) dag = mask & ~(S.vis[gbase + w] | cur[gbase + w] | nxt[gbase + w]);
+    // 3. discovery flags, then the predecessor rows; the flag results are
+    //    consumed only after the rows
+    bool enq = false;
+    if (dag != 0ull) enq = (atomicOr(&nxt[gbase + w], dag) == 0ull);
+    ull acc = 0ull;
+    bool lov = false;
+    c_d += (uint64_t)__popcll(pm);
+    pull_chunk(S, gbase, u, pm, lane, acc, lov);
+    append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, w, enq);
+    // remaining chunks (vertices of degree > 64)
+    for (int64_t e = f0 + 64; e < f1; e += 64) {
+      const int64_t my = e + lane;
+      uint32_t uu = 0;
+      ull pp = 0ull;
+      if (my < f1) {
+        uu = (uint32_t)G.icol[my];
+        pp = prv[gbase + uu] & mask;
       }
+      c_d += (uint64_t)__popcll(pp);
+      pull_chunk(S, gbase, uu, pp, lane, acc, lov);
+    }
+    for (int64_t e = e0 + 64; e < e1; e += 64) {
+      const int64_t my = e + lane;
+      uint32_t ww = 0;
+      bool eq = false;
+      if (my < e1) {
+        ww = (uint32_t)G.col[my];
+        const ull dd = mask & ~(S.vis[gbase + ww] | cur[gbase + ww] | nxt[gbase + ww]);
+        if (dd != 0ull) eq = (atomicOr(&nxt[gbase + ww], dd) == 0ull);
+      }
+      append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, ww, eq);
+    }
+    if (level > 0) {
       if (act) S.sig[(uint64_t)it * kLanes + lane] = acc;
       if (lov) {
         ovf = true;
         atomicOr(&S.ovl[g], 1ull << lane);
       }
     }
-
-    // 2. discovery of level+1
-    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    const uint64_t pc = (uint64_t)__popcll(mask);
-    if (lane == 0) {
-      c_v += pc;
-      c_a += pc * (uint64_t)(e1 - e0);
-    }
-    for (int64_t e = e0; e < e1; e += 64) {
-      const int64_t my = e + lane;
-      uint32_t w = 0;
-      bool enq = false;
-      if (my < e1) {
-        w = (uint32_t)G.col[my];
-        const ull dag = mask & ~(S.vis[gbase + w] | cur[gbase + w]);
-        if (dag != 0ull) enq = (atomicOr(&nxt[gbase + w], dag) == 0ull);
-      }
-      const ull eb = __ballot(enq);
-      if (eb != 0ull) {
-        uint32_t p0 = 0;
-        if (lane == 0) p0 = atomicAdd(&S.cnt[level + 1], (uint32_t)__popcll(eb));
-        p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
-        if (enq) {
-          const uint64_t p = nbase + p0 + (uint64_t)lanes_below(eb);
-          if (p < S.cap) S.items[p] = (uint32_t)(gbase + w);
-          else atomicOr(&S.flags[1], 1u);
-        }
-      }
-    }
   }
+  flush_stage(S, stage, nst, next_cnt, nbase, rend);
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
 }
 
@@ -181,16 +237,18 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
                                                      int full) {
   const uint64_t n = (uint64_t)S.n;
   const uint64_t GN = (uint64_t)S.G * n;
-  const uint64_t base = S.off[level];
-  const uint64_t count = S.cnt[level];
-  if (base + count > S.cap) return;
+  const int P = S.P;
+  const PartView pv = part_view<BLOCK>(P);
+  const uint64_t base = S.off[(uint64_t)level * P + pv.p];
+  const uint64_t count = S.cnt[(uint64_t)level * P + pv.p];
+  if (base + count > (uint64_t)(pv.p + 1) * S.capP) return;
   const int lane = lane_id();
   const LevMask *bt_in = S.bt + (uint64_t)((level + 1) & 1) * GN;
   LevMask *bt_out = S.bt + (uint64_t)(level & 1) * GN;
   const uint32_t E = S.epoch;
   uint64_t c_v = 0, c_a = 0, c_d = 0;
-  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  const uint64_t wave = pv.wave;
+  const uint64_t nwaves = pv.nwaves;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = S.items[base + i];
     const uint32_t g = (uint32_t)(it / n);
@@ -203,6 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
     const ull em = __ballot(need);
     if (em == 0ull) continue;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    const ull sg = need ? S.sig[(uint64_t)it * kLanes + lane] : 1ull;
     double acc = 0.0;
     for (int64_t e = e0; e < e1; e += 64) {
       const int64_t my = e + lane;
@@ -217,15 +276,16 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
       c_d += (uint64_t)__popcll(d);
       ull bits = __ballot(d != 0ull);
       while (bits != 0ull) {
-        int j[4];
+        int j[8];
         int c = 0;
-        for (; c < 4 && bits != 0ull; ++c) {
+        for (; c < 8 && bits != 0ull; ++c) {
           j[c] = __ffsll((long long)bits) - 1;
           bits &= bits - 1ull;
         }
-        double x[4] = {0.0, 0.0, 0.0, 0.0};
+        double x[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 8; ++q) {
+          x[q] = 0.0;
           if (q < c) {
             const uint32_t wq = read_lane(w, j[q]);
             const ull dq = read_lane64(d, j[q]);
@@ -234,11 +294,11 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
         }
         // arc order is kept, and adding 0.0 for a lane off the DAG leaves acc unchanged
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc += x[q];
+        for (int q = 0; q < 8; ++q) acc += x[q];
       }
     }
     if (need) {
-      const double s = (double)S.sig[(uint64_t)it * kLanes + lane];
+      const double s = (double)sg;
       const double dl = s * acc;
       S.psi[(uint64_t)it * kLanes + lane] = acc + 1.0 / s;
       if (S.dout) S.dout[(uint64_t)it * kLanes + lane] = dl;
@@ -262,16 +322,19 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
 // Reset what the batch touched: the masks of every item.  (Path counts need
 // no reset: every lane's count is written by the pull before anything reads
 // it, and only lanes named by a mask are ever read.)
-__global__ void k_batch_cleanup(BatchState S, uint64_t total) {
+__global__ void k_batch_cleanup(BatchState S, PartTotals tot) {
   const uint64_t GN = (uint64_t)S.G * (uint64_t)S.n;
-  const int lane = lane_id();
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  if (total > S.cap) total = S.cap;
-  for (uint64_t i = wave; i < total; i += nwaves) {
-    const uint32_t it = S.items[i];
-    if (lane == 0) S.vis[it] = 0ull;
-    if (lane < 4) S.fr[(uint64_t)lane * GN + it] = 0ull;
+  for (int p = 0; p < S.P; ++p) {
+    uint64_t total = tot.t[p];
+    if (total > S.capP) total = S.capP;
+    const uint32_t *items = S.items + (uint64_t)p * S.capP;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+      const uint32_t it = items[i];
+      S.vis[it] = 0ull;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S.fr[(uint64_t)k * GN + it] = 0ull;
+    }
   }
 }
 
@@ -286,7 +349,7 @@ __global__ void k_batch_export(BatchState S, int level, uint64_t begin, uint64_t
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   if (begin + count > S.cap) return;
   for (uint64_t i = wave; i < count; i += nwaves) {
-    const uint32_t it = S.items[begin + i];
+    const uint32_t it = S.items[begin + i];  // begin: absolute position (partition region + level offset)
     const uint32_t g = (uint32_t)(it / n);
     const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
     const ull mask = S.imask[begin + i];
@@ -494,11 +557,11 @@ __global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst,
     }                                                                                      \
   } while (0)
 
-hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const ull *masks0, int k,
-                             hipStream_t st) {
+hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const ull *masks0, const uint32_t *dest0,
+                             int k, hipStream_t st) {
   if (k <= 0) return hipSuccess;
   const int grid = (k + 255) / 256;
-  hipLaunchKernelGGL(k_batch_init, dim3(grid), dim3(256), 0, st, S, items0, masks0, k);
+  hipLaunchKernelGGL(k_batch_init, dim3(grid), dim3(256), 0, st, S, items0, masks0, dest0, k);
   return hipGetLastError();
 }
 
@@ -513,9 +576,8 @@ hipError_t launch_bwd_level(const DevGraph &G, const BatchState &S, int level, i
   return hipGetLastError();
 }
 
-hipError_t launch_batch_cleanup(const BatchState &S, uint64_t total, Launch L, hipStream_t st) {
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_cleanup, dim3(L.grid), dim3(256), 0, st, S, total);
+hipError_t launch_batch_cleanup(const BatchState &S, const PartTotals &tot, Launch L, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_cleanup, dim3(L.grid), dim3(256), 0, st, S, tot);
   return hipGetLastError();
 }
 
@@ -602,26 +664,24 @@ __global__ void k_plain_gather(PlainState P, const int32_t *verts, int k, int32_
 }
 
 __global__ void k_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc) {
-  __shared__ uint64_t part[256];
-  for (int k = 0; k < C_COUNT; ++k) {
-    uint64_t s = 0;
-    for (int i = threadIdx.x; i < slots; i += blockDim.x) {
-      s += ctr[(size_t)i * C_COUNT + k];
-      ctr[(size_t)i * C_COUNT + k] = 0;
-    }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) acc[k] += part[0];
+  __shared__ uint64_t part[1024];
+  const int k = blockIdx.x;  // one counter per workgroup
+  uint64_t s = 0;
+  for (int i = threadIdx.x; i < slots; i += blockDim.x) {
+    s += ctr[(size_t)i * C_COUNT + k];
+    ctr[(size_t)i * C_COUNT + k] = 0;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x == 0) acc[k] += part[0];
 }
 
 hipError_t launch_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctr_fold, dim3(1), dim3(256), 0, st, ctr, slots, acc);
+  hipLaunchKernelGGL(k_ctr_fold, dim3(C_COUNT), dim3(1024), 0, st, ctr, slots, acc);
   return hipGetLastError();
 }
 

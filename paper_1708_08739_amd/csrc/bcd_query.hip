@@ -228,7 +228,6 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
                                 unsigned long long *ovl_out = nullptr) {
   hipStream_t st = ws->stream;
   const DevGraph D = g->dev();
-  const Launch L = g->launch();
   const bool profiling = g->profiling.load();
   const size_t G64 = (size_t)ws->G * kLanes;
   HIPCHK(hipMemcpyAsync(ws->d_items0, ws->h_items0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
@@ -238,19 +237,24 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     ws->S.epoch += 1;
     BatchState S = ws->S;  // kernel arguments: this batch's epoch and capacity
     if (!ex) S.dout = nullptr;
+    const int P = S.P;
+    const Launch L = g->launch_parts(P);
+    // level-0 placement depends on the partition sizes (they change when the list grows)
+    ws->stage_sources_dest(k);
+    HIPCHK(hipMemcpyAsync(ws->d_dest0, ws->h_dest0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     uint32_t *hc = ws->h_cnt;
-    hc[kLevelChunkMax + 4] = (uint32_t)k;
-    HIPCHK(hipMemcpyAsync(&S.cnt[0], &hc[kLevelChunkMax + 4], sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    uint32_t *hc0 = hc + kCntStage;
+    for (int p = 0; p < P; ++p) hc0[p] = ws->h_cnt0[p];
+    HIPCHK(hipMemcpyAsync(&S.cnt[0], hc0, (size_t)P * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (ntgt > 0) HIPCHK(hipMemsetAsync(S.res, 0, (size_t)ntgt * G64 * sizeof(double), st));
     HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
-    HIPCHK(launch_batch_init(S, ws->d_items0, ws->d_masks0, k, st));
+    HIPCHK(launch_batch_init(S, ws->d_items0, ws->d_masks0, ws->d_dest0, k, st));
 
     // forward, in chunks of levels between host checks
-    std::vector<uint32_t> cnt;  // cnt[l] = items on level l
-    cnt.push_back((uint32_t)k);
+    std::vector<uint32_t> cntp(hc0, hc0 + P);  // cntp[l * P + p] = items of partition p on level l
     int lmax = -1;
     int level = 0;
     int chunk = std::min(kLevelChunkMax, std::max(4, ws->last_depth + 2));
@@ -267,7 +271,8 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
           ++ev;
         }
       }
-      HIPCHK(hipMemcpyAsync(hc, &S.cnt[first + 1], (size_t)launched * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hc, &S.cnt[(size_t)(first + 1) * P], (size_t)launched * P * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, st));
       uint32_t *hm = reinterpret_cast<uint32_t *>(ws->h_misc);
       HIPCHK(hipMemcpyAsync(hm, S.flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(hm + 2, S.tmin, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -277,11 +282,13 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
       tmin_h = hm[2];
       if (flags_h[1]) break;
       for (int i = 0; i < launched; ++i) {
-        if (hc[i] == 0) {
+        uint64_t tot = 0;
+        for (int p = 0; p < P; ++p) tot += hc[(size_t)i * P + p];
+        if (tot == 0) {
           lmax = first + i;
           break;
         }
-        cnt.push_back(hc[i]);
+        cntp.insert(cntp.end(), hc + (size_t)i * P, hc + (size_t)(i + 1) * P);
       }
       if (lmax < 0 && level > g->n) return fail(BCD_ERR_DEVICE, "forward pass did not terminate");
       chunk = kLevelChunkMax;
@@ -311,24 +318,28 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
         }
       }
     }
-    uint64_t total = 0;
-    std::vector<uint64_t> off(cnt.size() + 1, 0);
-    for (size_t i = 0; i < cnt.size(); ++i) {
-      off[i + 1] = off[i] + cnt[i];
-      total += cnt[i];
-    }
+    const int levels = (int)(cntp.size() / P);
+    PartTotals tot{};
+    for (int l = 0; l < levels; ++l)
+      for (int p = 0; p < P; ++p) tot.t[p] += cntp[(size_t)l * P + p];
     if (ex) {
-      for (size_t lv = 0; lv < cnt.size(); ++lv)
-        HIPCHK(launch_batch_export(S, (int)lv, off[lv], cnt[lv], ws->d_lane_slot, ex->dist, ex->sigma, ex->delta,
-                                   ex->k, st));
+      std::vector<uint64_t> pos((size_t)P);
+      for (int p = 0; p < P; ++p) pos[(size_t)p] = (uint64_t)p * S.capP;
+      for (int l = 0; l < levels; ++l)
+        for (int p = 0; p < P; ++p) {
+          const uint64_t c = cntp[(size_t)l * P + p];
+          HIPCHK(launch_batch_export(S, l, pos[(size_t)p], c, ws->d_lane_slot, ex->dist, ex->sigma, ex->delta, ex->k,
+                                     st));
+          pos[(size_t)p] += c;
+        }
     }
     if (ntgt > 0 && copy_res)
       HIPCHK(hipMemcpyAsync(ws->h_res, S.res, (size_t)ntgt * G64 * sizeof(double), hipMemcpyDeviceToHost, st));
     if (ovl_out)
       HIPCHK(hipMemcpyAsync(ovl_out, S.ovl, (size_t)ws->G * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    HIPCHK(launch_batch_cleanup(S, total, L, st));
+    HIPCHK(launch_batch_cleanup(S, tot, L, st));
     HIPCHK(launch_ctr_fold(S.ctr, kCtrSlots, S.acc, st));
-    HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * P * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
     if (profiling && prof) {
       for (size_t i = 0; i < ev; ++i) {
@@ -386,10 +397,9 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
   STCHK(source_order(g, ws, src, ord));
   for (size_t b0 = 0; b0 < ns; b0 += per) {
     const int k = (int)std::min(per, ns - b0);
-    for (int i = 0; i < k; ++i) {
-      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[ord[b0 + i]]);
-      ws->h_masks0[i] = 1ull << (i % kLanes);
-    }
+    std::vector<int32_t> bsrc((size_t)k);
+    for (int i = 0; i < k; ++i) bsrc[(size_t)i] = src[ord[b0 + i]];
+    ws->stage_sources(bsrc.data(), k);
     STCHK(run_one_batch(g, ws, k, ntgt, false, nullptr, &prof, &ovf));
     for (int i = 0; i < k; ++i)
       for (int t = 0; t < ntgt; ++t) out.dep[(size_t)ord[b0 + i] * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
@@ -863,10 +873,7 @@ bcd_status bcd_multi_source_pass(const bcd_graph *gh, const bcd_vid *sources, in
     cleanup();
     return hip_fail(e, "export setup");
   }
-  for (int64_t i = 0; i < k; ++i) {
-    ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)sources[i]);
-    ws->h_masks0[i] = 1ull << (i % kLanes);
-  }
+  ws->stage_sources(sources, (int)k);
   ex.dist = dd;
   ex.sigma = ds;
   ex.delta = dl;

@@ -317,9 +317,10 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
     tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
     // stage the batch
     const int k = (int)lanes.size();
-    for (int i = 0; i < k; ++i) {
-      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)lanes[(size_t)i].vertex);
-      ws->h_masks0[i] = 1ull << (i % kLanes);
+    {
+      std::vector<int32_t> bsrc((size_t)k);
+      for (int i = 0; i < k; ++i) bsrc[(size_t)i] = lanes[(size_t)i].vertex;
+      ws->stage_sources(bsrc.data(), k);
     }
     const int ntgt = (int)tg.size();
     bcd_status rc = ws->ensure_res((size_t)std::max(ntgt, 1) * width);

@@ -27,12 +27,12 @@ namespace bcd {
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
-__global__ void k_w_init(BatchState S, const uint32_t *items0, const ull *masks0, int k) {
+__global__ void k_w_init(BatchState S, const uint32_t *items0, const ull *masks0, const uint32_t *dest0, int k) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     const uint32_t it = items0[i];
     const ull m = masks0[i];
     S.fr[it] = m;       // topological round 0
-    S.items[i] = it;
+    S.items[dest0[i]] = it;
     S.chg[it] = m;      // relaxation round 0: the sources changed
     S.bq[i] = it;
     S.rl[i] = it;
@@ -151,24 +151,27 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int level) {
   const uint64_t n = (uint64_t)S.n;
   const uint64_t GN = (uint64_t)S.G * n;
-  const uint64_t base = S.off[level];
-  const uint64_t count = S.cnt[level];
+  const int P = S.P;
+  const PartView pv = part_view<BLOCK>(P);
+  const uint64_t base = S.off[(uint64_t)level * P + pv.p];
+  const uint64_t count = S.cnt[(uint64_t)level * P + pv.p];
   const uint64_t nbase = base + count;
-  if (blockIdx.x == 0 && threadIdx.x == 0) S.off[level + 1] = nbase;
-  if (S.flags[1] != 0u || nbase > S.cap) return;
+  const uint64_t rend = (uint64_t)(pv.p + 1) * S.capP;
+  if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
+  if (S.flags[1] != 0u || nbase > rend) return;
   const int lane = lane_id();
   ull *cur = S.fr + (uint64_t)(level % 3) * GN;
   ull *nxt = S.fr + (uint64_t)((level + 1) % 3) * GN;
   ull *old = S.fr + (uint64_t)((level + 2) % 3) * GN;
   if (level > 0) {
-    const uint64_t pb = S.off[level - 1];
-    const uint64_t pc = S.cnt[level - 1];
-    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pc; i += (uint64_t)gridDim.x * BLOCK)
-      old[S.items[pb + i]] = 0ull;
+    const uint64_t pb = S.off[(uint64_t)(level - 1) * P + pv.p];
+    const uint64_t pc = S.cnt[(uint64_t)(level - 1) * P + pv.p];
+    for (uint64_t i = pv.thread; i < pc; i += pv.nthreads) old[S.items[pb + i]] = 0ull;
   }
   bool ovf = false;
-  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  const uint64_t wave = pv.wave;
+  const uint64_t nwaves = pv.nwaves;
+  uint32_t *next_cnt = &S.cnt[(uint64_t)(level + 1) * P + pv.p];
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = S.items[base + i];
     const uint32_t g = (uint32_t)(it / n);
@@ -200,8 +203,8 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
       const ull rm = __ballot(ready);
       if (rm != 0ull && lane == 0) {
         if (atomicOr(&nxt[gbase + w], rm) == 0ull) {
-          const uint32_t p = atomicAdd(&S.cnt[level + 1], 1u);
-          if (nbase + p < S.cap) S.items[nbase + p] = (uint32_t)(gbase + w);
+          const uint32_t p = atomicAdd(next_cnt, 1u);
+          if (nbase + p < rend) S.items[nbase + p] = (uint32_t)(gbase + w);
           else atomicOr(&S.flags[1], 1u);
         }
       }
@@ -216,13 +219,15 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int level, int ntgt, int full) {
   const uint64_t n = (uint64_t)S.n;
-  const uint64_t base = S.off[level];
-  const uint64_t count = S.cnt[level];
-  if (base + count > S.cap) return;
+  const int P = S.P;
+  const PartView pv = part_view<BLOCK>(P);
+  const uint64_t base = S.off[(uint64_t)level * P + pv.p];
+  const uint64_t count = S.cnt[(uint64_t)level * P + pv.p];
+  if (base + count > (uint64_t)(pv.p + 1) * S.capP) return;
   const int lane = lane_id();
   uint64_t c_v = 0, c_a = 0, c_d = 0;
-  const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
-  const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  const uint64_t wave = pv.wave;
+  const uint64_t nwaves = pv.nwaves;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = S.items[base + i];
     const uint32_t g = (uint32_t)(it / n);
@@ -315,9 +320,10 @@ __global__ void k_w_export(BatchState S, const int32_t *lane_slot, uint64_t *dis
     }                                                                                                   \
   } while (0)
 
-hipError_t launch_w_init(const BatchState &S, const uint32_t *items0, const ull *masks0, int k, hipStream_t st) {
+hipError_t launch_w_init(const BatchState &S, const uint32_t *items0, const ull *masks0, const uint32_t *dest0, int k,
+                         hipStream_t st) {
   const int grid = std::max(1, (k + 255) / 256);
-  hipLaunchKernelGGL(k_w_init, dim3(grid), dim3(256), 0, st, S, items0, masks0, k);
+  hipLaunchKernelGGL(k_w_init, dim3(grid), dim3(256), 0, st, S, items0, masks0, dest0, k);
   return hipGetLastError();
 }
 
@@ -421,7 +427,6 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
                                  bool copy_res = true, unsigned long long *ovl_out = nullptr) {
   hipStream_t st = ws->stream;
   const DevGraph D = g->dev();
-  const Launch L = g->launch();
   const bool profiling = g->profiling.load();
   const size_t G64 = (size_t)ws->G * kLanes;
   HIPCHK(hipMemcpyAsync(ws->d_items0, ws->h_items0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
@@ -431,16 +436,21 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     ws->S.epoch += 1;
     BatchState S = ws->S;
     if (!ex) S.dout = nullptr;
+    const int P = S.P;
+    const Launch L = g->launch_parts(P);
+    ws->stage_sources_dest(k);
+    HIPCHK(hipMemcpyAsync(ws->d_dest0, ws->h_dest0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     uint32_t *hc = ws->h_cnt;
+    uint32_t *hc0 = hc + kCntStage;
     uint32_t *hm = reinterpret_cast<uint32_t *>(ws->h_misc);
-    hc[kLevelChunkMax + 4] = (uint32_t)k;
-    HIPCHK(hipMemcpyAsync(&S.cnt[0], &hc[kLevelChunkMax + 4], sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    for (int p = 0; p < P; ++p) hc0[p] = ws->h_cnt0[p];
+    HIPCHK(hipMemcpyAsync(&S.cnt[0], hc0, (size_t)P * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (ntgt > 0) HIPCHK(hipMemsetAsync(S.res, 0, (size_t)ntgt * G64 * sizeof(double), st));
     HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
-    HIPCHK(launch_w_init(S, ws->d_items0, ws->d_masks0, k, st));
+    HIPCHK(launch_w_init(S, ws->d_items0, ws->d_masks0, ws->d_dest0, k, st));
     size_t ev = 0;
     auto rec0 = [&]() -> hipError_t {
       return profiling ? hipEventRecord(ws->event_pair(ev).first, st) : hipSuccess;
@@ -470,7 +480,7 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     HIPCHK(launch_w_count(D, S, L, st));
     HIPCHK(rec1());
     // 3. path counts in topological rounds
-    std::vector<uint32_t> cnt{(uint32_t)k};
+    std::vector<uint32_t> cntp(hc0, hc0 + P);
     int lmax = -1, level = 0;
     int chunk = std::min(kLevelChunkMax, std::max(4, ws->last_depth + 2));
     uint32_t flags_h[2] = {0, 0}, tmin_h = 0xFFFFFFFFu;
@@ -482,7 +492,8 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
         HIPCHK(launch_w_sigma(D, S, level, L, st));
         HIPCHK(rec1());
       }
-      HIPCHK(hipMemcpyAsync(hc, &S.cnt[first + 1], (size_t)launched * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hc, &S.cnt[(size_t)(first + 1) * P], (size_t)launched * P * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(hm, S.flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(hm + 2, S.tmin, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -491,11 +502,13 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
       tmin_h = hm[2];
       if (flags_h[1]) break;
       for (int i = 0; i < launched; ++i) {
-        if (hc[i] == 0) {
+        uint64_t tot = 0;
+        for (int p = 0; p < P; ++p) tot += hc[(size_t)i * P + p];
+        if (tot == 0) {
           lmax = first + i;
           break;
         }
-        cnt.push_back(hc[i]);
+        cntp.insert(cntp.end(), hc + (size_t)i * P, hc + (size_t)(i + 1) * P);
       }
       if (lmax < 0 && level > g->n) return fail(BCD_ERR_DEVICE, "topological rounds did not terminate");
       chunk = kLevelChunkMax;
@@ -527,7 +540,7 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
       HIPCHK(hipMemcpyAsync(ovl_out, S.ovl, (size_t)ws->G * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HIPCHK(launch_w_cleanup(S, L, st));
     HIPCHK(launch_ctr_fold(S.ctr, kCtrSlots, S.acc, st));
-    HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * P * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
     if (profiling) {
       for (size_t i = 0; i < ev; ++i) {
@@ -597,10 +610,9 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   bcd_status rc = BCD_OK;
   for (size_t b0 = 0; b0 < ns && rc == BCD_OK; b0 += per) {
     const int k = (int)std::min(per, ns - b0);
-    for (int i = 0; i < k; ++i) {
-      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)src[ord[b0 + i]]);
-      ws->h_masks0[i] = 1ull << (i % kLanes);
-    }
+    std::vector<int32_t> bsrc((size_t)k);
+    for (int i = 0; i < k; ++i) bsrc[(size_t)i] = src[ord[b0 + i]];
+    ws->stage_sources(bsrc.data(), k);
     rc = run_one_wbatch(g, ws, k, ntgt, false, nullptr, &msf, &msb, &lf, &lb, &ovf);
     if (rc != BCD_OK) break;
     for (int i = 0; i < k; ++i)
@@ -668,10 +680,7 @@ bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t 
   }
   bool ovf = false;
   if (rc == BCD_OK) {
-    for (int64_t i = 0; i < k; ++i) {
-      ws->h_items0[i] = (uint32_t)((uint64_t)(i / kLanes) * (uint64_t)g->n + (uint64_t)sources[i]);
-      ws->h_masks0[i] = 1ull << (i % kLanes);
-    }
+    ws->stage_sources(sources, (int)k);
     double a = 0, b = 0;
     int64_t c = 0, d = 0;
     rc = run_one_wbatch(g, ws, (int)k, 0, true, &ex, &a, &b, &c, &d, &ovf);
