@@ -69,6 +69,34 @@ __device__ __forceinline__ void flush_counters(uint64_t *ctr, int slots, int k0,
   }
 }
 
+// Per-wavefront LDS staging of list appends: values are collected in an LDS
+// buffer and copied out with one tail atomic per block, so a list's shared
+// tail counter is not hit once per appended element.
+static __device__ __forceinline__ void stage_flush(uint32_t *buf, int &nbuf, uint32_t *tail, uint32_t *dst,
+                                                   uint64_t dst_base, uint64_t dst_end, uint32_t *overflow_flag) {
+  if (nbuf == 0) return;
+  uint32_t p0 = 0;
+  if ((threadIdx.x & 63) == 0) p0 = atomicAdd(tail, (uint32_t)nbuf);
+  p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+  for (int j = (int)(threadIdx.x & 63); j < nbuf; j += 64) {
+    const uint64_t p = dst_base + p0 + (uint64_t)j;
+    if (p < dst_end) dst[p] = buf[j];
+    else if (overflow_flag) atomicOr(overflow_flag, 1u);
+  }
+  nbuf = 0;
+}
+
+// Append one wave-uniform value (when `pred` is true on the wavefront).
+template <int CAP>
+static __device__ __forceinline__ void stage_one(uint32_t *buf, int &nbuf, bool pred, uint32_t value, uint32_t *tail,
+                                                 uint32_t *dst, uint64_t dst_base, uint64_t dst_end,
+                                                 uint32_t *overflow_flag) {
+  if (!pred) return;
+  if (nbuf == CAP) stage_flush(buf, nbuf, tail, dst, dst_base, dst_end, overflow_flag);
+  if ((threadIdx.x & 63) == 0) buf[nbuf] = value;
+  nbuf += 1;
+}
+
 // This workgroup's share of a partitioned item list (see BatchState).
 struct PartView {
   int p;              // partition served

@@ -36,10 +36,11 @@ bcd_status hip_fail(hipError_t e, const char *what);
 bcd_status device_check(int *cus);
 
 inline int default_groups(int64_t n) {
-  // keep the two [G][n][64] state arrays near 1 GiB, at least one group
-  int64_t g = (1ll << 30) / (2 * 8 * 64 * std::max<int64_t>(n, 1));
+  // keep the [G][n][64] path-count and psi arrays near 16 GiB (HBM is 288 GB),
+  // at least one group, at most 64
+  int64_t g = (1ll << 34) / (2 * 8 * 64 * std::max<int64_t>(n, 1));
   if (g < 1) g = 1;
-  if (g > 16) g = 16;
+  if (g > 64) g = 64;
   while (g > 1 && (uint64_t)g * (uint64_t)n >= (1ull << 32)) --g;
   return (int)g;
 }

@@ -516,6 +516,9 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
   const uint32_t count = *qin_n;
   const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  __shared__ uint32_t st_all[(BLOCK / 64) * kStage];
+  uint32_t *stg = st_all + (threadIdx.x >> 6) * kStage;
+  int nst = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const int32_t v = qin[i];
     const int64_t e0 = rp[v], e1 = rp[v + 1];
@@ -531,13 +534,15 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
       }
       const ull eb = __ballot(enq);
       if (eb != 0ull) {
-        uint32_t p0 = 0;
-        if (lane == 0) p0 = atomicAdd(qout_n, (uint32_t)__popcll(eb));
-        p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
-        if (enq) qout[p0 + lanes_below(eb)] = u;
+        const int c = __popcll(eb);
+        // every vertex is claimed once, so the queue (length n) cannot overflow
+        if (nst + c > kStage) stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
+        if (enq) stg[nst + lanes_below(eb)] = (uint32_t)u;
+        nst += c;
       }
     }
   }
+  stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
 }
 
 __global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {

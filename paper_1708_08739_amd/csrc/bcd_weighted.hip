@@ -69,6 +69,12 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
   uint64_t c_r = 0;
   const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
+  constexpr int kCap = 128;
+  __shared__ uint32_t qst_all[(BLOCK / 64) * kCap];
+  __shared__ uint32_t rst_all[(BLOCK / 64) * kCap];
+  uint32_t *qst = qst_all + (threadIdx.x >> 6) * kCap;
+  uint32_t *rst = rst_all + (threadIdx.x >> 6) * kCap;
+  int nq = 0, nr = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = qin[i];
     const uint32_t g = (uint32_t)(it / n);
@@ -81,28 +87,47 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
     const bool live = act && dv != kInf;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
     if (lane == 0) c_r += (uint64_t)__popcll(mask) * (uint64_t)(e1 - e0);
-    for (int64_t e = e0; e < e1; ++e) {
-      const uint32_t w = (uint32_t)G.col[e];
-      const uint32_t len = G.w[e];
-      uint32_t *pw = &S.wd[(gbase + w) * kLanes + lane];
-      const uint32_t nd = dv + len;
-      bool imp = false;
-      if (live && nd < *pw) imp = atomicMin(pw, nd) > nd;
-      const ull im = __ballot(imp);
-      if (im != 0ull && lane == 0) {
-        const ull o = atomicOr(&cnxt[gbase + w], im);
-        if (o == 0ull) {
-          const uint32_t p = atomicAdd(qout_n, 1u);
-          if (p < GN) qout[p] = (uint32_t)(gbase + w);
+    for (int64_t e = e0; e < e1; e += 8) {
+      const int c = (int)((e1 - e) < 8 ? (e1 - e) : 8);
+      uint32_t wq[8], nd[8], dw[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        wq[q] = 0u;
+        nd[q] = kInf;
+        if (q < c) {
+          wq[q] = (uint32_t)G.col[e + q];
+          nd[q] = dv + G.w[e + q];
         }
-        const ull r = atomicOr(&S.vis[gbase + w], im);
-        if (r == 0ull) {
-          const uint32_t p = atomicAdd(S.rln, 1u);
-          if (p < GN) S.rl[p] = (uint32_t)(gbase + w);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dw[q] = (q < c && live) ? S.wd[(gbase + wq[q]) * kLanes + lane] : 0u;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q >= c) break;
+        // a lower tentative distance: lower it (the minimum wins whatever the
+        // order) and flag the vertex for the next round; a flag raised by a
+        // value another wavefront has already beaten only costs a re-scan
+        const bool imp = live && nd[q] < dw[q];
+        if (imp)
+          __hip_atomic_fetch_min(&S.wd[(gbase + wq[q]) * kLanes + lane], nd[q], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        const ull im = __ballot(imp);
+        if (im != 0ull) {
+          bool fq = false, fr = false;
+          if (lane == 0) {
+            fq = atomicOr(&cnxt[gbase + wq[q]], im) == 0ull;
+            fr = atomicOr(&S.vis[gbase + wq[q]], im) == 0ull;
+          }
+          fq = __builtin_amdgcn_readfirstlane((int)fq) != 0;
+          fr = __builtin_amdgcn_readfirstlane((int)fr) != 0;
+          stage_one<kCap>(qst, nq, fq, (uint32_t)(gbase + wq[q]), qout_n, qout, 0, GN, nullptr);
+          stage_one<kCap>(rst, nr, fr, (uint32_t)(gbase + wq[q]), S.rln, S.rl, 0, GN, nullptr);
         }
       }
     }
   }
+  stage_flush(qst, nq, qout_n, qout, 0, GN, nullptr);
+  stage_flush(rst, nr, S.rln, S.rl, 0, GN, nullptr);
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_RLX_APAIRS, c_r, 0, 0, false, S.flags);
 }
 
@@ -126,11 +151,21 @@ __global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
     const bool fin = dw != kInf;
     uint32_t c = 0;
     const int64_t e0 = G.irp[w], e1 = G.irp[w + 1];
-    for (int64_t e = e0; e < e1; ++e) {
-      const uint32_t u = (uint32_t)G.icol[e];
-      const uint32_t len = G.iw[e];
-      const uint32_t du = S.wd[(gbase + u) * kLanes + lane];
-      if (fin && du != kInf && du + len == dw) ++c;
+    for (int64_t e = e0; e < e1; e += 8) {
+      const int cc = (int)((e1 - e) < 8 ? (e1 - e) : 8);
+      uint32_t du[8], ln[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        du[q] = kInf;
+        ln[q] = 0u;
+        if (q < cc && fin) {
+          ln[q] = G.iw[e + q];
+          du[q] = S.wd[(gbase + (uint32_t)G.icol[e + q]) * kLanes + lane];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (du[q] != kInf && du[q] + ln[q] == dw) ++c;
     }
     S.wc[(uint64_t)it * kLanes + lane] = c;
     const ull fm = __ballot(fin);
@@ -172,6 +207,10 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
   const uint64_t wave = pv.wave;
   const uint64_t nwaves = pv.nwaves;
   uint32_t *next_cnt = &S.cnt[(uint64_t)(level + 1) * P + pv.p];
+  constexpr int kCap = 256;
+  __shared__ uint32_t st_all[(BLOCK / 64) * kCap];
+  uint32_t *stg = st_all + (threadIdx.x >> 6) * kCap;
+  int nst = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = S.items[base + i];
     const uint32_t g = (uint32_t)(it / n);
@@ -187,29 +226,53 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
       if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
     }
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    for (int64_t e = e0; e < e1; ++e) {
-      const uint32_t w = (uint32_t)G.col[e];
-      const uint32_t len = G.w[e];
-      const uint64_t row = (gbase + w) * kLanes + lane;
-      bool ready = false;
-      if (act && S.wd[row] == dv + len) {
-        const ull o = atomicAdd(&S.sig[row], sv);
-        if (o + sv < o) {
+    for (int64_t e = e0; e < e1; e += 8) {
+      const int c = (int)((e1 - e) < 8 ? (e1 - e) : 8);
+      uint32_t wq[8], nd[8], dw[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        wq[q] = 0u;
+        nd[q] = kInf;
+        if (q < c) {
+          wq[q] = (uint32_t)G.col[e + q];
+          nd[q] = dv + G.w[e + q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dw[q] = (q < c && act) ? S.wd[(gbase + wq[q]) * kLanes + lane] : kInf - 1u;
+      // DAG arcs of the batch: push sigma and count down, all atomics issued
+      // before any result is used
+      ull so[8];
+      uint32_t co[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        so[q] = 0ull;
+        co[q] = 0u;
+        if (q < c && act && dw[q] == nd[q]) {
+          const uint64_t row = (gbase + wq[q]) * kLanes + lane;
+          so[q] = atomicAdd(&S.sig[row], sv);
+          co[q] = atomicSub(&S.wc[row], 1u);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q >= c) break;
+        const bool dag = act && dw[q] == nd[q];
+        if (dag && so[q] + sv < so[q]) {
           ovf = true;
           atomicOr(&S.ovl[g], 1ull << lane);
         }
-        ready = atomicSub(&S.wc[row], 1u) == 1u;
-      }
-      const ull rm = __ballot(ready);
-      if (rm != 0ull && lane == 0) {
-        if (atomicOr(&nxt[gbase + w], rm) == 0ull) {
-          const uint32_t p = atomicAdd(next_cnt, 1u);
-          if (nbase + p < rend) S.items[nbase + p] = (uint32_t)(gbase + w);
-          else atomicOr(&S.flags[1], 1u);
+        const ull rm = __ballot(dag && co[q] == 1u);
+        if (rm != 0ull) {
+          bool first = false;
+          if (lane == 0) first = atomicOr(&nxt[gbase + wq[q]], rm) == 0ull;
+          first = __builtin_amdgcn_readfirstlane((int)first) != 0;
+          stage_one<kCap>(stg, nst, first, (uint32_t)(gbase + wq[q]), next_cnt, S.items, nbase, rend, &S.flags[1]);
         }
       }
     }
   }
+  stage_flush(stg, nst, next_cnt, S.items, nbase, rend, &S.flags[1]);
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_SCRATCH, 0, 0, 0, ovf, S.flags);
 }
 
@@ -242,14 +305,32 @@ __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int l
     const uint32_t dv = need ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
     double acc = 0.0;
-    for (int64_t e = e0; e < e1; ++e) {
-      const uint32_t w = (uint32_t)G.col[e];
-      const uint32_t len = G.w[e];
-      const uint64_t row = (gbase + w) * kLanes + lane;
-      if (need && S.wd[row] == dv + len) {
-        acc += S.psi[row];
-        ++c_d;
+    for (int64_t e = e0; e < e1; e += 8) {
+      const int c = (int)((e1 - e) < 8 ? (e1 - e) : 8);
+      uint32_t wq[8], nd[8], dw[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        wq[q] = 0u;
+        nd[q] = kInf;
+        if (q < c) {
+          wq[q] = (uint32_t)G.col[e + q];
+          nd[q] = dv + G.w[e + q];
+        }
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dw[q] = (q < c && need) ? S.wd[(gbase + wq[q]) * kLanes + lane] : kInf - 1u;
+      double x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        x[q] = 0.0;
+        if (q < c && need && dw[q] == nd[q]) {
+          x[q] = S.psi[(gbase + wq[q]) * kLanes + lane];
+          ++c_d;
+        }
+      }
+      // arc order is kept; 0.0 for arcs off the lane's DAG leaves acc unchanged
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += x[q];
     }
     if (need) {
       const double s = (double)S.sig[(uint64_t)it * kLanes + lane];
@@ -569,8 +650,8 @@ static void wprofile(Graph *g, double msf, double msb, int64_t lf, int64_t lb, c
 }
 
 bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
-  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_w >= 0xFFFFFFFFull)
-    return fail(BCD_ERR_UNSUPPORTED, "(n-1) * max weight must stay below 2^32 - 1 for 32-bit distances");
+  if ((uint64_t)g->n * (uint64_t)g->max_w >= 0xFFFFFFFFull)
+    return fail(BCD_ERR_UNSUPPORTED, "n * max weight must stay below 2^32 - 1 for 32-bit distances");
   STCHK(ws->ensure_weighted());
   double a = 0, b = 0;
   int64_t c = 0, d = 0;
@@ -580,8 +661,8 @@ bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned 
 bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
                         bool want_counters, SourceRun &out) {
   const bcd_config cfg = g->config();
-  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_w >= 0xFFFFFFFFull)
-    return fail(BCD_ERR_UNSUPPORTED, "(n-1) * max weight must stay below 2^32 - 1 for 32-bit distances");
+  if ((uint64_t)g->n * (uint64_t)g->max_w >= 0xFFFFFFFFull)
+    return fail(BCD_ERR_UNSUPPORTED, "n * max weight must stay below 2^32 - 1 for 32-bit distances");
   STCHK(ws->ensure_batch(cfg.groups));
   STCHK(ws->ensure_weighted());
   const int ntgt = (int)tgt.size();
@@ -645,8 +726,8 @@ bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t 
                                       double *delta) {
   const bcd_config cfg = g->config();
   if (k > (int64_t)cfg.groups * kLanes) return fail(BCD_ERR_INVALID_ARG, "k exceeds the batch width");
-  if ((uint64_t)(g->n - 1) * (uint64_t)g->max_w >= 0xFFFFFFFFull)
-    return fail(BCD_ERR_UNSUPPORTED, "(n-1) * max weight must stay below 2^32 - 1 for 32-bit distances");
+  if ((uint64_t)g->n * (uint64_t)g->max_w >= 0xFFFFFFFFull)
+    return fail(BCD_ERR_UNSUPPORTED, "n * max weight must stay below 2^32 - 1 for 32-bit distances");
   for (int64_t i = 0; i < k; ++i) {
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "source out of range");
     for (int64_t j = 0; j < i; ++j)
