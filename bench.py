@@ -118,16 +118,19 @@ def serve(G, g, args):
         while len(res) < len(qs):
             res += S.poll(timeout_s=1.0)
         wall = time.perf_counter() - t0
+        sst = S.stats()
         S.close()
         bad = [x for x in res if x["status"] != bcd.BCD_OK]
         if bad:
             raise SystemExit(f"serving: {len(bad)} queries failed: {bad[0]}")
         lat = np.array([x["t_done_s"] - x["t_arrive_s"] for x in res])
-        te = sum(x["stats"]["traversed_edges"] for x in res)
+        te = sst["traversed_edges"]
         return {"queries": len(qs), "wall_s": round(wall, 3), "qps": round(len(qs) / wall, 3),
                 "gteps": round(te / wall / 1e9, 3), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
                 "samples_mean": float(np.mean([x["stats"]["samples"] for x in res])),
+                "batches": sst["batches"], "lane_occupancy": round(sst["lanes_used"] / max(sst["lane_slots"], 1), 3),
+                "shared_lanes": sst["shared_lanes"],
                 "distinct_sources_mean": float(np.mean([x["stats"]["distinct_sources"] for x in res]))}, te
     sat, te = run(0.0)
     log(f"[bench] serving saturation: {sat}")

@@ -267,6 +267,19 @@ bcd_status bcd_server_submit(bcd_server *s, const bcd_query *q, uint64_t *ticket
  * timeout_ns for the first one (0 = do not wait, < 0 = wait forever).
  * Returns AGAIN if none finished in time. */
 bcd_status bcd_server_poll(bcd_server *s, bcd_result *out, int32_t cap, int32_t *n_out, int64_t timeout_ns);
+/* Aggregate counters of a server since creation.  Traversed arcs of shared
+ * batches cannot be split between the queries that share them, so per-query
+ * stats carry no traversed_edges; these totals do. */
+typedef struct bcd_server_stats {
+  uint64_t queries_done;
+  uint64_t batches;
+  uint64_t lanes_used;        /* sum over batches of sources run */
+  uint64_t lane_slots;        /* sum over batches of the batch width */
+  uint64_t traversed_edges;   /* sum of m_s over every source run */
+  uint64_t shared_lanes;      /* lanes whose source served more than one query */
+} bcd_server_stats;
+bcd_status bcd_server_get_stats(bcd_server *s, bcd_server_stats *out);
+
 /* Library steady-clock time in seconds (the clock of the t_* fields). */
 double bcd_server_now(void);
 /* Stop: queued queries finish with CANCELLED, running batches drain.  NULL is a no-op. */

@@ -79,6 +79,11 @@ class Result(C.Structure):
                 ("t_done_s", C.c_double)]
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("queries_done", C.c_uint64), ("batches", C.c_uint64), ("lanes_used", C.c_uint64),
+                ("lane_slots", C.c_uint64), ("traversed_edges", C.c_uint64), ("shared_lanes", C.c_uint64)]
+
+
 BCD_QUERY_EXACT = 0
 BCD_QUERY_SAMPLED = 1
 BCD_QUERY_SET = 2
@@ -122,6 +127,7 @@ SIGNATURES = {
     "bcd_server_submit": [_p, C.POINTER(Query), C.POINTER(_u64)],
     "bcd_server_poll": [_p, _p, _i32, C.POINTER(_i32), _i64],
     "bcd_server_destroy": [_p],
+    "bcd_server_get_stats": [_p, C.POINTER(ServerStats)],
 }
 OPTIONAL_SIGNATURES: dict = {}
 
@@ -358,6 +364,11 @@ class Server:
                 d["bcs"] = keep[1].copy()
             out.append(d)
         return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(load().bcd_server_get_stats(self.h, C.byref(st)), "bcd_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     @staticmethod
     def now() -> float:

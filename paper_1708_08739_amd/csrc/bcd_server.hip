@@ -80,6 +80,7 @@ struct bcd_server {
   std::vector<std::thread> workers;
   std::vector<std::unique_ptr<bcd::Workspace>> wss;
   std::unique_ptr<bcd::Workspace> plan_ws;
+  bcd_server_stats stats{};
 };
 
 namespace bcd {
@@ -367,10 +368,18 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
       (void)hipFree(d_t);
     }
     if (d_routes) (void)hipFree(d_routes);
+    uint64_t ctr[C_COUNT] = {0};
+    if (rc == BCD_OK) rc = collect_counters(ws, ctr, ws->S.acc);
     // account
     std::vector<std::shared_ptr<SQuery>> complete;
     {
       std::unique_lock<std::mutex> lk(S->mu);
+      S->stats.batches += 1;
+      S->stats.lanes_used += (uint64_t)k;
+      S->stats.lane_slots += (uint64_t)width;
+      S->stats.traversed_edges += ctr[C_FWD_APAIRS];
+      for (auto &ln : lanes)
+        if (ln.users.size() > 1) S->stats.shared_lanes += 1;
       for (int i = 0; i < k; ++i) {
         const bool lane_ovf = ovf && ((ovl[(size_t)i / kLanes] >> (i % kLanes)) & 1ull);
         for (auto &u : lanes[(size_t)i].users) {
@@ -399,6 +408,7 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
       q->res.stats.batch_width = (int32_t)width;
       std::unique_lock<std::mutex> lk(S->mu);
       release_query(S, *q);
+      S->stats.queries_done += 1;
       post_result(S, q, status);
     }
   }
@@ -517,6 +527,13 @@ bcd_status bcd_server_poll(bcd_server *S, bcd_result *out, int32_t cap, int32_t 
   }
   *n_out = k;
   if (k == 0) return fail(BCD_ERR_AGAIN, "no result ready");
+  return BCD_OK;
+}
+
+bcd_status bcd_server_get_stats(bcd_server *S, bcd_server_stats *out) {
+  if (!S || !out) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->stats;
   return BCD_OK;
 }
 
