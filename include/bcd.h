@@ -99,6 +99,9 @@ typedef struct bcd_sample_params {
 #define BCD_EPS_ABSOLUTE 1u      /* eps is an absolute error on BC(r) */
 #define BCD_K_TRIVIAL 2u         /* K = n - 2 instead of K = |vertices reachable from r| */
 #define BCD_NO_EXACT_FALLBACK 4u /* sample even when T >= |RV(r)| */
+#define BCD_SAMPLE_ALL_VERTICES 8u /* baseline without the pruning: draw uniformly from V \ {r}
+                                      (ascending), bc = (n-1)/T * sum_t delta_{v_t}.(r), and Eq.(8)
+                                      with n-1 in place of |RV(r)|; never falls back to exact */
 
 /* ------------------------------------------------------------- graph */
 
@@ -160,6 +163,12 @@ bcd_status bcd_bc_exact(const bcd_graph *g, bcd_vid r, double *bc, bcd_stats *st
  * in (0,1) when T_override <= 0. */
 bcd_status bcd_bc_sampled(const bcd_graph *g, bcd_vid r, const bcd_sample_params *p, double *bc,
                           bcd_stats *st);
+
+/* The BCD procedure of Section 5: find RV(r); if |RV(r)| <= tau run E-BCD
+ * (Alg.1), otherwise A-BCD (Alg.2) with T = tau draws (seeded as in
+ * bcd_sample_params).  st->ran_exact tells which.  Errors: INVALID_ARG for
+ * tau < 1. */
+bcd_status bcd_bc_bcd(const bcd_graph *g, bcd_vid r, int64_t tau, uint64_t seed, double *bc, bcd_stats *st);
 
 /* BC of every vertex of rs[0..l-1] (Section 4.2): D = union of the RV(r_i);
  * one pass per s in D serves every r_i; bc[i] sums delta_s.(r_i) over s in

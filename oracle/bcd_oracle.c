@@ -631,6 +631,45 @@ int oracle_bc_sampled(int64_t n, int64_t m, const int64_t *rp, const int32_t *co
   return rc;
 }
 
+/* Baseline without the pruning (uniform source sampling over V, the
+ * related-work estimator the paper compares its sample bound with after
+ * Eq.(8)): draws index the ascending list V \ {r} with the same SplitMix64
+ * rule; bc = (n-1)/T * sum_t delta_{v_t}.(r).  Unbiased because sources
+ * outside RV(r) contribute 0 (Prop.1). */
+int oracle_bc_sampled_all(int64_t n, int64_t m, const int64_t *rp, const int32_t *col, const uint32_t *w,
+                          int32_t r, int64_t T, uint64_t seed, int nthreads, double *bc) {
+  if (r < 0 || r >= n || T <= 0 || !bc || n < 2) return OR_INVALID;
+  og G = {n, m, rp, col, w};
+  if (rp[r + 1] == rp[r]) { *bc = 0.0; return OR_OK; }
+  const int64_t k = n - 1;
+  int64_t *draw = malloc((size_t)T * sizeof(int64_t));
+  int32_t *uniq = malloc((size_t)T * sizeof(int32_t));
+  int64_t *slot = malloc((size_t)k * sizeof(int64_t));
+  if (!draw || !uniq || !slot) { free(draw); free(uniq); free(slot); return OR_NOMEM; }
+  for (int64_t i = 0; i < k; ++i) slot[i] = -1;
+  int64_t nu = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    int64_t idx = oracle_draw_index(seed, t, k);
+    if (slot[idx] < 0) {
+      slot[idx] = nu;
+      uniq[nu++] = (int32_t)(idx < r ? idx : idx + 1); /* idx-th vertex of V \ {r} */
+    }
+    draw[t] = slot[idx];
+  }
+  double *res = malloc((size_t)nu * sizeof(double));
+  double *seq = malloc((size_t)T * sizeof(double));
+  if (!res || !seq) { free(draw); free(uniq); free(slot); free(res); free(seq); return OR_NOMEM; }
+  int ovf = 0;
+  int rc = run_sources(&G, uniq, nu, &r, 1, nthreads, res, NULL, &ovf);
+  if (rc == OR_OK && ovf) rc = OR_OVERFLOW;
+  if (rc == OR_OK) {
+    for (int64_t t = 0; t < T; ++t) seq[t] = res[draw[t]];
+    *bc = comp_sum(seq, T, 1) * (double)k / (double)T;
+  }
+  free(draw); free(uniq); free(slot); free(res); free(seq);
+  return rc;
+}
+
 /* ------------------------------------------------- definition, Eq.(1)
  * delta_s.(r) straight from the definition, without the Eq.(4) recursion:
  * a shortest s->t path passes through r iff d(s,r) + d(r,t) = d(s,t), and

@@ -58,6 +58,7 @@ def lib():
         L.oracle_draw_index.argtypes = [u64, i64, i64]
         L.oracle_draw_index.restype = i64
         L.oracle_pair_dependency.argtypes = [i64, i64, p, p, p, i32, i32, p]
+        L.oracle_bc_sampled_all.argtypes = [i64, i64, p, p, p, i32, i64, u64, C.c_int, p]
         _lib = L
     return _lib
 
@@ -164,6 +165,24 @@ def bc_sampled(g, r: int, T: int, seed: int, threads: int | None = None):
                                    seed & 0xFFFFFFFFFFFFFFFF, threads or default_threads(),
                                    C.byref(bc), C.byref(st)), "bc_sampled")
     return bc.value, _stats(st)
+
+
+def bc_sampled_all(g, r: int, T: int, seed: int, threads: int | None = None) -> float:
+    """Uniform source sampling over V minus r (the unpruned baseline)."""
+    rp, col, w = _g(g)
+    bc = C.c_double()
+    _check(lib().oracle_bc_sampled_all(g.n, g.m, _ptr(rp), _ptr(col), _ptr(w), r, T,
+                                       seed & 0xFFFFFFFFFFFFFFFF, threads or default_threads(),
+                                       C.byref(bc)), "bc_sampled_all")
+    return bc.value
+
+
+def bc_bcd(g, r: int, tau: int, seed: int, threads: int | None = None):
+    """The procedure of Section 5: exact when |RV(r)| <= tau, else tau draws."""
+    k = len(rv(g, r))
+    if k <= tau:
+        return bc_exact(g, r, threads=threads)[0], True
+    return bc_sampled(g, r, tau, seed, threads=threads)[0], False
 
 
 def sample_count(eps_abs: float, delta: float, K: float, rv_size: int) -> int:

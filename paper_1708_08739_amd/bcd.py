@@ -34,6 +34,7 @@ BCD_ENGINE_PLAIN = 1
 BCD_EPS_ABSOLUTE = 1
 BCD_K_TRIVIAL = 2
 BCD_NO_EXACT_FALLBACK = 4
+BCD_SAMPLE_ALL_VERTICES = 8
 
 U64_MAX = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -114,6 +115,7 @@ SIGNATURES = {
     "bcd_bc_exact": [_p, _i32, C.POINTER(_d), C.POINTER(Stats)],
     "bcd_bc_sampled": [_p, _i32, C.POINTER(SampleParams), C.POINTER(_d), C.POINTER(Stats)],
     "bcd_bc_set": [_p, _p, _i64, _p, C.POINTER(Stats)],
+    "bcd_bc_bcd": [_p, _i32, _i64, _u64, C.POINTER(_d), C.POINTER(Stats)],
     "bcd_source_pass": [_p, _i32, _p, _p, _p],
     "bcd_multi_source_pass": [_p, _p, _i64, _p, _p, _p],
     "bcd_dependencies": [_p, _i32, _p, _i64, _p, _p],
@@ -261,6 +263,13 @@ class Graph:
         bc = C.c_double()
         st = Stats()
         check(load().bcd_bc_sampled(self.h, r, C.byref(p), C.byref(bc), C.byref(st)), "bcd_bc_sampled")
+        return bc.value, st.as_dict()
+
+    def bc_bcd(self, r: int, tau: int = 1000, seed: int = 0):
+        """The BCD procedure (exact if |RV(r)| <= tau, else tau draws)."""
+        bc = C.c_double()
+        st = Stats()
+        check(load().bcd_bc_bcd(self.h, r, tau, seed & 0xFFFFFFFFFFFFFFFF, C.byref(bc), C.byref(st)), "bcd_bc_bcd")
         return bc.value, st.as_dict()
 
     def bc_set(self, rs):

@@ -724,6 +724,7 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
   }
   bcd_stats s{};
   s.fr_size = -1;
+  const bool all_v = (p->flags & BCD_SAMPLE_ALL_VERTICES) != 0;
   if (g->outdeg(r) == 0) {  // Prop.1
     s.rv_size = -1;
     *bc = 0.0;
@@ -733,11 +734,19 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
   Lease ls(g);
   STCHK(lease_ws(g, ls));
   const double t0 = now_s();
-  std::vector<uint32_t> bits;
-  int64_t k = 0;
-  STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
   std::vector<int32_t> rv;
-  bits_to_list(bits, g->n, r, rv);
+  int64_t k = 0;
+  if (all_v) {
+    // the unpruned baseline: every vertex but r is a candidate source
+    rv.reserve((size_t)g->n - 1);
+    for (int64_t v = 0; v < g->n; ++v)
+      if (v != r) rv.push_back((int32_t)v);
+    k = (int64_t)rv.size();
+  } else {
+    std::vector<uint32_t> bits;
+    STCHK(reach_set(g, ls.w.get(), r, true, bits, &k, nullptr));
+    bits_to_list(bits, g->n, r, rv);
+  }
   s.rv_size = k;
   int64_t T = p->T_override;
   if (T <= 0) {
@@ -760,7 +769,7 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
     if (st) *st = s;
     return BCD_OK;
   }
-  if (T >= k && !(p->flags & BCD_NO_EXACT_FALLBACK)) {
+  if (T >= k && !(p->flags & (BCD_NO_EXACT_FALLBACK | BCD_SAMPLE_ALL_VERTICES))) {
     SourceRun run;
     STCHK(run_sources(g, ls.w.get(), rv, std::vector<int32_t>{r}, false, run));
     *bc = compensated_sum(run.dep.data(), rv.size(), 1);
@@ -799,6 +808,15 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
   s.t_bc_s = now_s() - t1;
   if (st) *st = s;
   return BCD_OK;
+}
+
+bcd_status bcd_bc_bcd(const bcd_graph *gh, bcd_vid r, int64_t tau, uint64_t seed, double *bc, bcd_stats *st) {
+  if (tau < 1) return fail(BCD_ERR_INVALID_ARG, "tau must be >= 1");
+  // T = tau draws, and the exact sum whenever |RV(r)| <= tau (T >= |RV| fallback)
+  bcd_sample_params p{};
+  p.seed = seed;
+  p.T_override = tau;
+  return bcd_bc_sampled(gh, r, &p, bc, st);
 }
 
 bcd_status bcd_dependencies(const bcd_graph *gh, bcd_vid r, const bcd_vid *sources, int64_t k, double *dep,

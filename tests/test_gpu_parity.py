@@ -304,3 +304,59 @@ def test_weighted_bc_and_counters(B, oracle):
     g0 = gg.rmat(10, 8, seed=3)
     r = gg.top_out_degree(g0, 1)[0]
     assert dev(B, g1).bc_exact(r)[0] == dev(B, g0).bc_exact(r)[0] or close(dev(B, g1).bc_exact(r)[0], dev(B, g0).bc_exact(r)[0])
+
+
+def test_bcd_procedure_and_unpruned_sampling(B, oracle):
+    g = gg.rmat(12, 8, seed=7)
+    G = dev(B, g)
+    r = gg.top_out_degree(g, 1)[0]
+    k = len(oracle.rv(g, r))
+    for tau, seed in [(k, 3), (k - 1, 3), (50, 11)]:
+        got, st = G.bc_bcd(r, tau=tau, seed=seed)
+        want, ex = oracle.bc_bcd(g, r, tau, seed)
+        assert close(got, want) and bool(st["ran_exact"]) == ex, (tau, got, want)
+    got, st = G.bc_sampled(r, T=64, seed=5, flags=B.BCD_SAMPLE_ALL_VERTICES)
+    assert close(got, oracle.bc_sampled_all(g, r, 64, 5)) and st["rv_size"] == g.n - 1
+
+
+# ------------------------------------ full-size workloads, sampled sources
+
+def _sampled_parity(B, oracle, g, r, nsrc, seed, **cfg):
+    G = dev(B, g, **cfg)
+    rv = G.rv(r)
+    assert np.array_equal(rv, oracle.rv(g, r))
+    pick = rv[np.sort(np.unique(gg.below(gg.stream(seed, 0, nsrc), rv.size).astype(np.int64)))]
+    dep, cnt = G.dependencies(r, pick, counters=True)
+    odep, ocnt = oracle.dependencies(g, r, pick)
+    assert close(dep, odep)
+    assert np.array_equal(cnt, ocnt)
+    # the same sources inside one full-width batch (bench configuration)
+    assert np.array_equal(G.dependencies(r, pick), dep)
+    return G, rv
+
+
+def test_rmat18_weighted_sampled_sources(B, oracle):
+    """R-MAT scale 18, edge factor 16, weights in [1,100]."""
+    g, q = gg.rmat18_weighted()
+    print("rmat18w", g.m, flush=True)
+    _sampled_parity(B, oracle, g, q[0], 24, 18)
+
+
+def test_rmat20_sampled_sources(B, oracle):
+    """R-MAT scale 20, edge factor 16: a giant-class vertex."""
+    g = gg.rmat20()
+    r = gg.top_out_degree(g, 1)[0]
+    print("rmat20", g.m, flush=True)
+    _sampled_parity(B, oracle, g, r, 24, 20)
+
+
+def test_rmat22_sampled_sources_and_draws(B, oracle):
+    """R-MAT scale 22, edge factor 16: sampled sources, and an A-BCD call
+    whose draws the oracle recomputes."""
+    g = gg.rmat22()
+    r = gg.top_out_degree(g, 1)[0]
+    print("rmat22", g.m, flush=True)
+    G, rv = _sampled_parity(B, oracle, g, r, 8, 22)
+    got, st = G.bc_sampled(r, T=12, seed=7, flags=B.BCD_NO_EXACT_FALLBACK)
+    want, ost = oracle.bc_sampled(g, r, 12, 7)
+    assert close(got, want) and st["distinct_sources"] == ost["distinct_sources"]

@@ -340,3 +340,35 @@ def test_prop3_unbiased_and_prop4_tail(oracle):
     eps = 0.25 * K * len(rv)
     bound = 2 * math.exp(-2 * T * (eps / (K * len(rv))) ** 2)
     assert np.mean(np.abs(ests - exact) > eps) <= bound
+
+
+def test_uniform_over_v_estimator(oracle):
+    """The unpruned baseline draws from V minus r with weight (n-1)/T: it
+    equals its definition on the drawn sources, and is unbiased (mean over
+    seeds within 4 standard errors of BC(r)), with a wider spread than the
+    RV(r)-restricted estimator at equal T (the point of Eq.(8))."""
+    g = gg.rmat(9, 6, seed=14)
+    r = gg.top_out_degree(g, 1)[0]
+    exact, _ = oracle.bc_exact(g, r)
+    others = np.array([v for v in range(g.n) if v != r], dtype=np.int32)
+    T, seed = 37, 99
+    idx = [(int(x) * others.size) >> 64 for x in gg.stream(seed, 0, T)]
+    dep, _ = oracle.dependencies(g, r, others[idx])
+    want = float(np.sum(dep)) * others.size / T
+    assert close(oracle.bc_sampled_all(g, r, T, seed), want, 1e-12)
+    allv = np.array([oracle.bc_sampled_all(g, r, 40, s) for s in range(400)])
+    pruned = np.array([oracle.bc_sampled(g, r, 40, s)[0] for s in range(400)])
+    se = allv.std(ddof=1) / math.sqrt(allv.size)
+    assert abs(allv.mean() - exact) <= 4 * se
+    assert allv.std() > pruned.std()
+
+
+def test_bcd_procedure_oracle(oracle):
+    """Section 5: exact when |RV(r)| <= tau, otherwise tau draws."""
+    g = gg.rmat(10, 8, seed=23)
+    r = gg.top_out_degree(g, 1)[0]
+    k = len(oracle.rv(g, r))
+    v, ex = oracle.bc_bcd(g, r, tau=k, seed=1)
+    assert ex and v == oracle.bc_exact(g, r)[0]
+    v, ex = oracle.bc_bcd(g, r, tau=k - 1, seed=1)
+    assert not ex and v == oracle.bc_sampled(g, r, k - 1, 1)[0]
