@@ -107,6 +107,7 @@ void Workspace::release() {
   dfree(S.dout);
   dfree(S.vis);
   dfree(S.fr);
+  dfree(S.rec);
   dfree(S.bt);
   dfree(S.items);
   dfree(S.imask);
@@ -159,6 +160,7 @@ void Workspace::release() {
 bcd_status Workspace::init_common(Graph *g) {
   graph = g;
   n = g->n;
+  weighted_graph = g->weighted;
   if (!stream) HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   return BCD_OK;
 }
@@ -180,7 +182,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   if (batch_ready && G == G_) return BCD_OK;
   if (batch_ready) {
     release_weighted();
-    dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.bt);
+    dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.rec); dfree(S.bt);
     dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tlev); dfree(S.tmin);
     dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
     dfree(d_items0); dfree(d_masks0); dfree(d_dest0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0);
@@ -196,8 +198,12 @@ bcd_status Workspace::ensure_batch(int G_) {
   S.G = G;
   STCHK(dalloc(&S.sig, GN * kLanes));
   STCHK(dalloc(&S.psi, GN * kLanes));
-  STCHK(dalloc(&S.vis, GN));
-  STCHK(dalloc(&S.fr, 4 * GN));
+  if (weighted_graph) {
+    STCHK(dalloc(&S.vis, GN));
+    STCHK(dalloc(&S.fr, 3 * GN));
+  } else {
+    STCHK(dalloc(&S.rec, GN));
+  }
   STCHK(dalloc(&S.bt, 2 * GN));
   S.P = std::min(kMaxParts, G);
   S.capP = ((uint64_t)GN * 16 + (uint64_t)S.P - 1) / (uint64_t)S.P;
@@ -230,8 +236,9 @@ bcd_status Workspace::ensure_batch(int G_) {
   if (!h_misc) STCHK(halloc(&h_misc, 64));
   if (!h_ctr) STCHK(halloc(&h_ctr, (size_t)kCtrSlots * C_COUNT));
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.fr, 0, 4 * GN * sizeof(uint64_t), stream));
+  if (S.vis) HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
+  if (S.fr) HIPCHK(hipMemsetAsync(S.fr, 0, 3 * GN * sizeof(uint64_t), stream));
+  if (S.rec) HIPCHK(hipMemsetAsync(S.rec, 0, GN * sizeof(MaskRec), stream));
   HIPCHK(hipMemsetAsync(S.bt, 0, 2 * GN * sizeof(LevMask), stream));
   HIPCHK(hipMemsetAsync(S.cnt, 0, levels * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.off, 0, levels * sizeof(uint64_t), stream));
@@ -305,8 +312,9 @@ bcd_status Workspace::grow_items() {
 bcd_status Workspace::reset_batch_dense() {
   const size_t GN = (size_t)G * (size_t)n;
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
-  HIPCHK(hipMemsetAsync(S.fr, 0, 4 * GN * sizeof(uint64_t), stream));
+  if (S.vis) HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
+  if (S.fr) HIPCHK(hipMemsetAsync(S.fr, 0, 3 * GN * sizeof(uint64_t), stream));
+  if (S.rec) HIPCHK(hipMemsetAsync(S.rec, 0, GN * sizeof(MaskRec), stream));
   HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)n + kLevelChunkMax + 4) * kMaxParts * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));

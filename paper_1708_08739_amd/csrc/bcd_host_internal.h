@@ -50,6 +50,7 @@ struct Graph;
 struct Workspace {
   Graph *graph = nullptr;
   int64_t n = 0;
+  bool weighted_graph = false;
   hipStream_t stream = nullptr;
   // batched engine
   bool batch_ready = false;

@@ -17,6 +17,15 @@ struct __align__(16) LevMask {
   uint32_t epoch;
 };
 
+// All level masks of one (group, vertex) of the unweighted engine in one
+// 64-byte record, so the test "is w settled for these sources" and the flag
+// for the next level touch a single cache line per arc.
+struct __align__(64) MaskRec {
+  unsigned long long vis;    // lanes settled on a level < current (lagging, see the forward kernel)
+  unsigned long long fr[4];  // rotating level masks: current, next, previous, retiring
+  unsigned long long pad[3];
+};
+
 // Counters accumulated per workgroup slot (no atomics), reduced on the host.
 enum Ctr {
   C_FWD_VPAIRS = 0,  // (source, vertex) pairs expanded by the forward kernel
@@ -40,8 +49,9 @@ struct BatchState {
   unsigned long long *sig;   // [G][n][64] path counts
   double *psi;               // [G][n][64] (1 + delta) / sigma
   double *dout;              // [G][n][64] delta, verification hook only (may be null)
-  unsigned long long *vis;   // [G][n] lanes settled on a level < current (lagging, see kernel)
-  unsigned long long *fr;    // [4][G][n] rotating level masks: current, next, previous, retiring
+  MaskRec *rec;              // [G][n] level masks (unweighted engine)
+  unsigned long long *vis;   // [G][n] reached lanes (weighted engine)
+  unsigned long long *fr;    // [3][G][n] rotating round masks (weighted engine)
   LevMask *bt;               // [2][G][n] backward level masks, by level parity
   // Item lists are split into P partitions (group g belongs to partition
   // g % P); workgroup b serves partition b % P, so with P = 8 every XCD

@@ -25,7 +25,7 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     const uint32_t it = items0[i];
     const ull m = masks0[i];
-    S.fr[it] = m;  // fr[0] = level-0 masks
+    S.rec[it].fr[0] = m;  // level-0 masks
     S.items[dest0[i]] = it;
     for (int b = 0; b < kLanes; ++b)
       if ((m >> b) & 1ull) S.sig[(size_t)it * kLanes + b] = 1ull;
@@ -122,16 +122,15 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
   if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
   if (S.flags[1] != 0u || nbase > rend) return;  // capacity exceeded earlier: batch is redone
   const int lane = lane_id();
-  ull *cur = S.fr + (uint64_t)(level & 3) * GN;
-  ull *nxt = S.fr + (uint64_t)((level + 1) & 3) * GN;
-  ull *old = S.fr + (uint64_t)((level + 2) & 3) * GN;
-  const ull *prv = S.fr + (uint64_t)((level + 3) & 3) * GN;
+  MaskRec *rec = S.rec;
+  const int kc = level & 3, kn = (level + 1) & 3, ko = (level + 2) & 3, kp = (level + 3) & 3;
+  (void)GN;
 
   // retire the masks of level-2 so that array can collect level+2
   if (level >= 2) {
     const uint64_t pb = S.off[(uint64_t)(level - 2) * P + pv.p];
     const uint64_t pc = S.cnt[(uint64_t)(level - 2) * P + pv.p];
-    for (uint64_t i = pv.thread; i < pc; i += pv.nthreads) old[S.items[pb + i]] = 0ull;
+    for (uint64_t i = pv.thread; i < pc; i += pv.nthreads) rec[S.items[pb + i]].fr[ko] = 0ull;
   }
 
   uint64_t c_v = 0, c_a = 0, c_d = 0;
@@ -150,13 +149,13 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
     const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
     const uint64_t gbase = (uint64_t)g * n;
     // independent loads of this item, issued together
-    const ull mask = cur[it];
+    const ull mask = rec[it].fr[kc];
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
     const int64_t f0 = level > 0 ? G.irp[v] : 0, f1 = level > 0 ? G.irp[v + 1] : 0;
     const int32_t tg = S.tgt_of[v];
     if (lane == 0) {
       S.imask[base + i] = mask;
-      S.vis[it] = S.vis[it] | mask;
+      rec[it].vis = rec[it].vis | mask;
     }
     const bool act = (mask >> lane) & 1ull;
     if (tg >= 0) {
@@ -176,14 +175,17 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
     if (mo < e1) w = (uint32_t)G.col[mo];
     // 2. both mask gathers
     ull pm = 0ull, dag = 0ull;
-    if (mi < f1) pm = prv[gbase + u] & mask;
+    if (mi < f1) pm = rec[gbase + u].fr[kp] & mask;
     // lanes already flagged for level+1 by another wavefront need no atomic
     // (a stale read only costs a redundant atomic)
-    if (mo < e1) dag = mask & ~(S.vis[gbase + w] | cur[gbase + w] | nxt[gbase + w]);
+    if (mo < e1) {
+      const MaskRec &R = rec[gbase + w];
+      dag = mask & ~(R.vis | R.fr[kc] | R.fr[kn]);
+    }
     // 3. discovery flags, then the predecessor rows; the flag results are
     //    consumed only after the rows
     bool enq = false;
-    if (dag != 0ull) enq = (atomicOr(&nxt[gbase + w], dag) == 0ull);
+    if (dag != 0ull) enq = (atomicOr(&rec[gbase + w].fr[kn], dag) == 0ull);
     ull acc = 0ull;
     bool lov = false;
     c_d += (uint64_t)__popcll(pm);
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
       ull pp = 0ull;
       if (my < f1) {
         uu = (uint32_t)G.icol[my];
-        pp = prv[gbase + uu] & mask;
+        pp = rec[gbase + uu].fr[kp] & mask;
       }
       c_d += (uint64_t)__popcll(pp);
       pull_chunk(S, gbase, uu, pp, lane, acc, lov);
@@ -207,8 +209,9 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
       bool eq = false;
       if (my < e1) {
         ww = (uint32_t)G.col[my];
-        const ull dd = mask & ~(S.vis[gbase + ww] | cur[gbase + ww] | nxt[gbase + ww]);
-        if (dd != 0ull) eq = (atomicOr(&nxt[gbase + ww], dd) == 0ull);
+        const MaskRec &R = rec[gbase + ww];
+        const ull dd = mask & ~(R.vis | R.fr[kc] | R.fr[kn]);
+        if (dd != 0ull) eq = (atomicOr(&rec[gbase + ww].fr[kn], dd) == 0ull);
       }
       append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, ww, eq);
     }
@@ -323,7 +326,6 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
 // no reset: every lane's count is written by the pull before anything reads
 // it, and only lanes named by a mask are ever read.)
 __global__ void k_batch_cleanup(BatchState S, PartTotals tot) {
-  const uint64_t GN = (uint64_t)S.G * (uint64_t)S.n;
   for (int p = 0; p < S.P; ++p) {
     uint64_t total = tot.t[p];
     if (total > S.capP) total = S.capP;
@@ -331,9 +333,10 @@ __global__ void k_batch_cleanup(BatchState S, PartTotals tot) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x) {
       const uint32_t it = items[i];
-      S.vis[it] = 0ull;
+      MaskRec &R = S.rec[it];
+      R.vis = 0ull;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) S.fr[(uint64_t)k * GN + it] = 0ull;
+      for (int k = 0; k < 4; ++k) R.fr[k] = 0ull;
     }
   }
 }
