@@ -252,12 +252,19 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
   uint64_t c_v = 0, c_a = 0, c_d = 0;
   const uint64_t wave = pv.wave;
   const uint64_t nwaves = pv.nwaves;
+  // the next item's id and mask are loaded while this one is processed
+  uint32_t it_next = wave < count ? S.items[base + wave] : 0u;
+  ull mask_next = wave < count ? S.imask[base + wave] : 0ull;
   for (uint64_t i = wave; i < count; i += nwaves) {
-    const uint32_t it = S.items[base + i];
+    const uint32_t it = it_next;
+    const ull mask = mask_next;
+    if (i + nwaves < count) {
+      it_next = S.items[base + i + nwaves];
+      mask_next = S.imask[base + i + nwaves];
+    }
     const uint32_t g = (uint32_t)(it / n);
     const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
     const uint64_t gbase = (uint64_t)g * n;
-    const ull mask = S.imask[base + i];
     const int32_t tg = S.tgt_of[v];
     const uint32_t tl = S.tlev[g * kLanes + lane];
     const bool need = ((mask >> lane) & 1ull) && (full || (uint32_t)level > tl || tg >= 0);
