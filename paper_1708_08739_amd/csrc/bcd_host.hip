@@ -247,19 +247,10 @@ bcd_status Workspace::ensure_batch(int G_) {
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));
   HIPCHK(hipStreamSynchronize(stream));
   S.epoch = 0;
-  STCHK(write_partition_bases());
   batch_ready = true;
   return BCD_OK;
 }
 
-// Level 0 of partition p starts at p * capP; kernels only ever write the
-// offsets of later levels.
-bcd_status Workspace::write_partition_bases() {
-  std::vector<uint64_t> b((size_t)S.P);
-  for (int p = 0; p < S.P; ++p) b[(size_t)p] = (uint64_t)p * S.capP;
-  HIPCHK(hipMemcpy(S.off, b.data(), (size_t)S.P * sizeof(uint64_t), hipMemcpyHostToDevice));
-  return BCD_OK;
-}
 
 void Workspace::stage_sources(const int32_t *src, int k) {
   for (int i = 0; i < k; ++i) {
@@ -273,8 +264,9 @@ void Workspace::stage_sources(const int32_t *src, int k) {
 // Level-0 slot of every staged item in its group's partition.
 void Workspace::stage_sources_dest(int k) {
   uint32_t fill[kMaxParts] = {0};
+  const int P = batch_parts(k);
   for (int i = 0; i < k; ++i) {
-    const int p = (i / kLanes) % S.P;
+    const int p = (i / kLanes) % P;
     h_dest0[i] = (uint32_t)((uint64_t)p * S.capP + fill[p]++);
   }
   for (int p = 0; p < kMaxParts; ++p) h_cnt0[p] = fill[p];
@@ -304,7 +296,7 @@ bcd_status Workspace::grow_items() {
   S.cap = S.capP * (uint64_t)S.P;
   STCHK(dalloc(&S.items, S.cap));
   STCHK(dalloc(&S.imask, S.cap));
-  return write_partition_bases();
+  return BCD_OK;
 }
 
 // Full reset after an aborted batch (item list overflow): the sparse cleanup
@@ -552,7 +544,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->cfg.engine = BCD_ENGINE_BATCHED;
   g->cfg.groups = default_groups(n);
   g->cfg.block = 256;
-  g->cfg.grid_mult = 8;
+  g->cfg.grid_mult = 32;
   *out = reinterpret_cast<bcd_graph *>(g.release());
   return BCD_OK;
 }

@@ -36,9 +36,9 @@ bcd_status hip_fail(hipError_t e, const char *what);
 bcd_status device_check(int *cus);
 
 inline int default_groups(int64_t n) {
-  // keep the [G][n][64] path-count and psi arrays near 16 GiB (HBM is 288 GB),
+  // keep the [G][n][64] path-count and psi arrays near 64 GiB (HBM is 288 GB),
   // at least one group, at most 64
-  int64_t g = (1ll << 34) / (2 * 8 * 64 * std::max<int64_t>(n, 1));
+  int64_t g = (1ll << 36) / (2 * 8 * 64 * std::max<int64_t>(n, 1));
   if (g < 1) g = 1;
   if (g > 64) g = 64;
   while (g > 1 && (uint64_t)g * (uint64_t)n >= (1ull << 32)) --g;
@@ -96,8 +96,11 @@ struct Workspace {
   // runs source vertex src[i]; vertices must be distinct within a group.
   void stage_sources(const int32_t *src, int k);
   void stage_sources_dest(int k);
+  // Partitions a batch of k staged sources uses: its groups are 0..ceil(k/64)-1
+  // and group g belongs to partition g % P, so a batch of fewer groups than
+  // S.P uses one partition per group and no workgroup is left without work.
+  int batch_parts(int k) const { return std::max(1, std::min(S.P, (k + kLanes - 1) / kLanes)); }
   int staged = 0;
-  bcd_status write_partition_bases();
   bool weighted_ready = false;
   int weighted_G = 0;
   bcd_status ensure_weighted();

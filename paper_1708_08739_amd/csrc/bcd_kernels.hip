@@ -30,6 +30,8 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
     for (int b = 0; b < kLanes; ++b)
       if ((m >> b) & 1ull) S.sig[(size_t)it * kLanes + b] = 1ull;
   }
+  // level-0 item-list base of every partition of this batch
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)S.P) S.off[threadIdx.x] = (uint64_t)threadIdx.x * S.capP;
   (void)GN;
 }
 

@@ -237,6 +237,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     ws->S.epoch += 1;
     BatchState S = ws->S;  // kernel arguments: this batch's epoch and capacity
     if (!ex) S.dout = nullptr;
+    S.P = ws->batch_parts(k);  // partitions that hold this batch's groups
     const int P = S.P;
     const Launch L = g->launch_parts(P);
     // level-0 placement depends on the partition sizes (they change when the list grows)

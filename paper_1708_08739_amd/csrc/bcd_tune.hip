@@ -43,7 +43,7 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
   for (int G = 1; G <= max_groups && rc == BCD_OK; G *= 2) {
     if ((uint64_t)G * (uint64_t)g->n >= (1ull << 32)) break;
     for (int block : {256, 512}) {
-      for (int gm : {4, 8, 16}) {
+      for (int gm : {8, 16, 32}) {
         cand.groups = G;
         cand.block = block;
         cand.grid_mult = gm;

@@ -43,6 +43,7 @@ __global__ void k_w_init(BatchState S, const uint32_t *items0, const ull *masks0
         S.wd[(size_t)it * kLanes + b] = 0u;
       }
   }
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)S.P) S.off[threadIdx.x] = (uint64_t)threadIdx.x * S.capP;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     S.bqn[0] = (uint32_t)k;
     S.bqn[1] = 0u;
@@ -517,6 +518,7 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     ws->S.epoch += 1;
     BatchState S = ws->S;
     if (!ex) S.dout = nullptr;
+    S.P = ws->batch_parts(k);  // partitions that hold this batch's groups
     const int P = S.P;
     const Launch L = g->launch_parts(P);
     ws->stage_sources_dest(k);

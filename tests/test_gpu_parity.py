@@ -100,6 +100,22 @@ def test_multi_source_pass_groups(B, oracle, k):
         assert close(dl[i], odl), (k, i, s)
 
 
+def test_partition_count_changes_between_batches(B, oracle):
+    """Batches of 1, 2, 8 and 3 groups on one workspace (groups=8): each uses
+    min(8, groups used) partitions, so the item-list layout changes from one
+    batch to the next, unweighted and weighted."""
+    for weighted in (False, True):
+        g = gg.rmat(12, 8, seed=21, weighted=weighted, max_weight=20)
+        r = gg.top_out_degree(g, 1)[0]
+        rv = oracle.rv(g, r)
+        G = dev(B, g, groups=8)
+        for k in (30, 100, 512, 150, 1):
+            src = rv[gg.uniform_vertices(rv.size, min(k, rv.size), seed=k)]
+            print("parts weighted", weighted, "k", src.size, flush=True)
+            dep = G.dependencies(r, src)
+            assert close(dep, oracle.dependencies(g, r, src)[0]), (weighted, k)
+
+
 def test_counters_match_oracle(B, oracle):
     g = gg.rmat(10, 8, seed=3)
     r = gg.top_out_degree(g, 1)[0]
