@@ -135,8 +135,15 @@ def serve(G, g, args):
     pool = [v for v in gg.uniform_vertices(g.n, 20 * args.queries, seed=105) if ind[v] > 0 and outd[v] > 0]
     qs = pool[: args.queries]
 
+    # largest group count whose workspaces fit in three quarters of the budget
+    budget = args.hbm_budget << 30
+    groups = G.config().groups
+    while groups > 1 and bcd.Server.workspace_bytes(G, groups, args.workers) > budget * 3 // 4:
+        groups //= 2
+    log(f"[bench] serving: {args.workers} workers x {groups} groups, budget {args.hbm_budget} GiB")
+
     def run(rate):
-        S = bcd.Server(G, workers=args.workers, groups=G.config().groups, hbm_budget_bytes=args.hbm_budget << 30)
+        S = bcd.Server(G, workers=args.workers, groups=groups, hbm_budget_bytes=budget)
         gaps = [0.0] * len(qs)
         if rate > 0:
             u = gg.unit(gg.stream(205, 0, len(qs)))
@@ -169,7 +176,7 @@ def serve(G, g, args):
                 "distinct_sources_mean": float(np.mean([x["stats"]["distinct_sources"] for x in res]))}, te
     sat, te = run(0.0)
     log(f"[bench] serving saturation: {sat}")
-    out = {"saturation": sat}
+    out = {"workers": args.workers, "groups": groups, "hbm_budget_gib": args.hbm_budget, "saturation": sat}
     for frac in (0.5, 0.9):
         r, _ = run(frac * sat["qps"])
         log(f"[bench] serving at {frac} x saturation: {r}")
@@ -217,7 +224,7 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--queries", type=int, default=64, help="serving: number of sampled queries")
     ap.add_argument("--workers", type=int, default=2, help="serving: concurrent batches")
-    ap.add_argument("--hbm-budget", type=int, default=64, help="serving: HBM budget in GiB")
+    ap.add_argument("--hbm-budget", type=int, default=192, help="serving: HBM budget in GiB")
     ap.add_argument("--set-size", type=int, default=64)
     ap.add_argument("--probe-bw", action="store_true",
                     help="also run the library's streaming-copy probe (1 GiB copied, known traffic)")
@@ -267,8 +274,9 @@ def main():
                           "value": round(te / wall / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
                           "workload": wname, "wall_s": round(wall, 3), "traversed_edges": int(te),
                           "latencies_s": [round(x, 4) for x in lat][:16],
-                          "config": {"workload": wname, "n": g.n, "m": g.m, "groups": cfg.groups,
-                                     "block": cfg.block, "grid_mult": cfg.grid_mult},
+                          "config": {"workload": wname, "n": g.n, "m": g.m,
+                                     "groups": extra.get("serving", {}).get("groups", cfg.groups),
+                                     "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items},
                           **extra}), flush=True)
         return
 
@@ -359,7 +367,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "graph": g.name, "n": g.n, "m": g.m, "queries": [int(q) for q in queries],
                    "engine": "batched", "batch_width": 64 * cfg.groups, "block": cfg.block,
-                   "grid_mult": cfg.grid_mult},
+                   "grid_mult": cfg.grid_mult, "items": cfg.items},
         "p50_query_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_query_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "traversed_edges_per_step": te_total // args.steps,

@@ -84,6 +84,9 @@ typedef struct bcd_config {
   int32_t groups;     /* batched engine: 64-source column groups per batch, >= 1 */
   int32_t block;      /* threads per workgroup for traversal kernels: 64, 128, 256, 512 */
   int32_t grid_mult;  /* workgroups per compute unit for traversal kernels, >= 1 */
+  int32_t items;      /* batched engine, unweighted forward: frontier items a
+                         wavefront takes per step, 1, 2 or 4 (64 / items lanes
+                         per item for its first arcs); 0 = default */
 } bcd_config;
 
 /* Sampled estimate (Alg.2).  T comes from Eq.(8) unless T_override > 0. */
@@ -213,6 +216,9 @@ typedef struct bcd_kernel_profile {
   uint64_t vertex_pairs; /* (source, vertex) pairs processed */
   uint64_t arc_pairs;    /* (source, arc) pairs scanned */
   uint64_t dag_pairs;    /* (source, shortest-path-DAG arc) pairs used */
+  uint64_t items;        /* work items: one per (64-source column group, vertex,
+                            level) with a nonempty lane mask (0 for the
+                            weighted engine) */
 } bcd_kernel_profile;
 
 bcd_status bcd_profile_enable(bcd_graph *g, int32_t on);
@@ -266,6 +272,12 @@ typedef struct bcd_result {
   double t_admit_s;          /* admission (RV done, buffers reserved) */
   double t_done_s;           /* result reduced and queued for poll */
 } bcd_result;
+
+/* Device bytes the batch workspaces of `workers` workers with `groups`
+ * column groups take on graph g (0 = the defaults bcd_server_create uses);
+ * a server's hbm_budget_bytes must exceed this, and the rest of the budget
+ * holds per-query result buffers (8 bytes per (source, target) pair). */
+bcd_status bcd_server_workspace_bytes(const bcd_graph *g, int32_t groups, int32_t workers, uint64_t *bytes);
 
 /* Start a server on a loaded graph; the graph must outlive the server. */
 bcd_status bcd_server_create(const bcd_graph *g, const bcd_server_config *cfg, bcd_server **out);

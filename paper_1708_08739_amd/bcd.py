@@ -51,7 +51,7 @@ class Stats(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("engine", C.c_int32), ("groups", C.c_int32), ("block", C.c_int32),
-                ("grid_mult", C.c_int32)]
+                ("grid_mult", C.c_int32), ("items", C.c_int32)]
 
 
 class SampleParams(C.Structure):
@@ -61,7 +61,8 @@ class SampleParams(C.Structure):
 
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double),
-                ("vertex_pairs", C.c_uint64), ("arc_pairs", C.c_uint64), ("dag_pairs", C.c_uint64)]
+                ("vertex_pairs", C.c_uint64), ("arc_pairs", C.c_uint64), ("dag_pairs", C.c_uint64),
+                ("items", C.c_uint64)]
 
 
 class ServerConfig(C.Structure):
@@ -130,6 +131,7 @@ SIGNATURES = {
     "bcd_server_poll": [_p, _p, _i32, C.POINTER(_i32), _i64],
     "bcd_server_destroy": [_p],
     "bcd_server_get_stats": [_p, C.POINTER(ServerStats)],
+    "bcd_server_workspace_bytes": [_p, _i32, _i32, C.POINTER(_u64)],
 }
 OPTIONAL_SIGNATURES: dict = {}
 
@@ -230,8 +232,10 @@ class Graph:
         check(load().bcd_get_config(self.h, C.byref(c)), "bcd_get_config")
         return c
 
-    def set_config(self, engine=None, groups=None, block=None, grid_mult=None) -> Config:
+    def set_config(self, engine=None, groups=None, block=None, grid_mult=None, items=None) -> Config:
         c = self.config()
+        if items is not None:
+            c.items = items
         if engine is not None:
             c.engine = engine
         if groups is not None:
@@ -334,6 +338,14 @@ class Server:
         check(load().bcd_server_create(graph.h, C.byref(cfg), C.byref(h)), "bcd_server_create")
         self.h = h
         self._keep: dict[int, tuple] = {}
+
+    @staticmethod
+    def workspace_bytes(graph: Graph, groups: int = 0, workers: int = 0) -> int:
+        """Device bytes of the batch workspaces a server with these settings
+        reserves out of its HBM budget."""
+        b = C.c_uint64()
+        check(load().bcd_server_workspace_bytes(graph.h, groups, workers, C.byref(b)), "bcd_server_workspace_bytes")
+        return int(b.value)
 
     def submit(self, kind: int, r: int = 0, rs=None, eps: float = 0.01, delta: float = 0.1, seed: int = 0,
                flags: int = 0, T: int = 0, tag: int = 0) -> int:

@@ -391,6 +391,7 @@ Launch Graph::launch() const {
   std::lock_guard<std::mutex> lk(cfg_mu);
   L.block = cfg.block;
   L.grid = std::max(1, std::min(kCtrSlots, cus * cfg.grid_mult));
+  L.items = cfg.items;
   return L;
 }
 
@@ -418,7 +419,8 @@ void Graph::release(std::unique_ptr<Workspace> w) {
   pool.push_back(std::move(w));
 }
 
-void Graph::add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes) {
+void Graph::add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
+                        uint64_t items) {
   std::lock_guard<std::mutex> lk(prof_mu);
   bcd_kernel_profile &p = prof[kind];
   p.launches += launches;
@@ -427,6 +429,7 @@ void Graph::add_profile(int kind, int64_t launches, double ms, const uint64_t *c
   p.vertex_pairs += c3[0];
   p.arc_pairs += c3[1];
   p.dag_pairs += c3[2];
+  p.items += items;
 }
 
 }  // namespace bcd
@@ -545,6 +548,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->cfg.groups = default_groups(n);
   g->cfg.block = 256;
   g->cfg.grid_mult = 32;
+  g->cfg.items = kDefaultItems;
   *out = reinterpret_cast<bcd_graph *>(g.release());
   return BCD_OK;
 }
@@ -574,8 +578,11 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256 && cfg->block != 512)
     return fail(BCD_ERR_INVALID_ARG, "block must be 64, 128, 256 or 512");
   if (cfg->grid_mult < 1 || cfg->grid_mult > 32) return fail(BCD_ERR_INVALID_ARG, "grid_mult must be in [1, 32]");
+  if (cfg->items != 0 && cfg->items != 1 && cfg->items != 2 && cfg->items != 4)
+    return fail(BCD_ERR_INVALID_ARG, "items must be 1, 2 or 4 (0 = default)");
   std::lock_guard<std::mutex> lk(g->cfg_mu);
   g->cfg = *cfg;
+  if (g->cfg.items == 0) g->cfg.items = kDefaultItems;
   return BCD_OK;
 }
 

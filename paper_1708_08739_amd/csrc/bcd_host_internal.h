@@ -28,6 +28,7 @@ namespace bcd {
 
 constexpr int kCtrSlots = 8192;       // max workgroups of a traversal launch
 constexpr int kLevelChunkMax = 64;    // level launches enqueued between host checks
+constexpr int kDefaultItems = 2;      // frontier items per wavefront step, unweighted forward
 constexpr int kMaxParts = 8;          // item-list partitions (one per XCD)
 constexpr int kCntStage = (kLevelChunkMax + 2) * kMaxParts;  // pinned slots for level counts
 
@@ -138,7 +139,8 @@ struct Graph {
   bcd_config config() const;
   std::unique_ptr<Workspace> acquire();
   void release(std::unique_ptr<Workspace> w);
-  void add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes);
+  void add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
+                   uint64_t items = 0);
   int64_t outdeg(int64_t v) const { return h_rp[(size_t)v + 1] - h_rp[(size_t)v]; }
 };
 

@@ -112,8 +112,9 @@ struct DevGraph {
 };
 
 struct Launch {
-  int block;  // threads per workgroup
-  int grid;   // workgroups
+  int block;      // threads per workgroup
+  int grid;       // workgroups
+  int items = 1;  // frontier items per wavefront step (unweighted forward)
 };
 
 // ---- launchers (bcd_kernels.hip) ----

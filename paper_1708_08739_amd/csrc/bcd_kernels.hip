@@ -35,25 +35,18 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
   (void)GN;
 }
 
-// One BFS level of the batched forward pass (unweighted graphs).  For every
-// item (g, v, mask) on `level`:
-//   1. sigma pull: sigma_b(v) = sum of sigma_b(u) over in-arcs (u, v) with u
-//      on level-1 for lane b (the shortest-path-DAG predecessors of v), an
-//      exact uint64 sum with a carry check on every add; no atomics, and the
-//      row loads of four predecessors are issued together;
-//   2. discovery: for every out-arc (v, w), lanes b in mask for which w is
-//      not settled on a level <= `level` are DAG arcs; they are flagged on
-//      (g, w) for level+1 with one atomicOr per arc, lanes over arcs, and
-//      the first flagger appends (g, w) to the next level's item list.
-// Level masks rotate over four arrays: cur (level), nxt (level+1, being
-// built), prv (level-1, read by the pull) and old (level-2, retired here).
-// vis lags: the owner of (g, v) ORs cur into vis during this launch, so a
-// reader sees vis | cur, which is the same union either way.
-// Sum of sigma_b(u) over the in-arcs of one 64-arc chunk whose tail u is on
-// the previous level for lane b (pm = lanes of that arc); row loads of up to
-// eight predecessors are issued before any of them is consumed.
-static __device__ __forceinline__ void pull_chunk(const BatchState &S, uint64_t gbase, uint32_t u, ull pm,
-                                                  int lane, ull &acc, bool &lov) {
+// Sum of sigma_b(u) over the in-arcs held by one chunk of lanes whose tail u
+// is on the previous level for lane b (pm = lanes of that arc).  The chunk
+// holds the arcs of up to K items, 64 / K lanes each (arc lane l belongs to
+// the item of slot l / (64 / K), whose group base is in lane l's gbase), and
+// an arc adds into its item's accumulator.  Row loads of up to eight
+// predecessors are issued before any of them is consumed; the sums are
+// exact integers, so the order of the adds does not matter, and an
+// unsigned wrap on any add means the true sum exceeds 2^64 - 1.
+template <int K>
+static __device__ __forceinline__ void pull_slots(const BatchState &S, uint64_t gbase, uint32_t u, ull pm, int lane,
+                                                  ull (&acc)[K], bool (&lov)[K]) {
+  constexpr int SUB = kLanes / K;
   ull bits = __ballot(pm != 0ull);
   while (bits != 0ull) {
     int j[8];
@@ -62,6 +55,7 @@ static __device__ __forceinline__ void pull_chunk(const BatchState &S, uint64_t 
       j[c] = __ffsll((long long)bits) - 1;
       bits &= bits - 1ull;
     }
+    // each row load writes its own register, so all eight stay in flight
     ull x[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -69,14 +63,24 @@ static __device__ __forceinline__ void pull_chunk(const BatchState &S, uint64_t 
       if (q < c) {
         const uint32_t uq = read_lane(u, j[q]);
         const ull dq = read_lane64(pm, j[q]);
-        if ((dq >> lane) & 1ull) x[q] = S.sig[(gbase + uq) * kLanes + lane];
+        const uint64_t gq = read_lane64(gbase, j[q]);
+        if ((dq >> lane) & 1ull) x[q] = S.sig[(gq + uq) * kLanes + lane];
       }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const ull t = acc + x[q];
-      if (t < acc) lov = true;
-      acc = t;
+      const ull xq = x[q];
+      if (q < c) {
+        const int slot = j[q] / SUB;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          if (slot == t) {
+            const ull sum = acc[t] + xq;
+            if (sum < acc[t]) lov[t] = true;
+            acc[t] = sum;
+          }
+        }
+      }
     }
   }
 }
@@ -111,10 +115,28 @@ static __device__ __forceinline__ void append_chunk(const BatchState &S, uint32_
   nst += c;
 }
 
-template <int BLOCK>
+// One BFS level of the batched forward pass (unweighted graphs).  For every
+// item (g, v, mask) on `level`:
+//   1. sigma pull: sigma_b(v) = sum of sigma_b(u) over in-arcs (u, v) with u
+//      on level-1 for lane b (the shortest-path-DAG predecessors of v), an
+//      exact uint64 sum with a carry check on every add; no atomics;
+//   2. discovery: for every out-arc (v, w), lanes b in mask for which w is
+//      not settled on a level <= `level` are DAG arcs; they are flagged on
+//      (g, w) for level+1 with one atomicOr per arc, lanes over arcs, and
+//      the first flagger appends (g, w) to the next level's item list.
+// A wavefront takes K items per step: each item's first 64 / K in-arcs and
+// out-arcs sit in its own slot of lanes, so the dependent loads of K items
+// (item -> mask and CSR bounds -> arc heads -> head masks -> flags and
+// predecessor rows) are in flight together; arcs past the first 64 / K of
+// an item are then taken 64 at a time by the whole wavefront.
+// Level masks rotate over four words of the (g, v) record: cur (level), nxt
+// (level+1, being built), prv (level-1, read by the pull) and old (level-2,
+// retired here).  vis lags: the owner of (g, v) ORs cur into vis during this
+// launch, so a reader sees vis | cur, which is the same union either way.
+template <int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, int level) {
+  constexpr int SUB = kLanes / K;
   const uint64_t n = (uint64_t)S.n;
-  const uint64_t GN = (uint64_t)S.G * n;
   const int P = S.P;
   const PartView pv = part_view<BLOCK>(P);
   const uint64_t base = S.off[(uint64_t)level * P + pv.p];
@@ -124,11 +146,11 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
   if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
   if (S.flags[1] != 0u || nbase > rend) return;  // capacity exceeded earlier: batch is redone
   const int lane = lane_id();
+  const int sl = lane % SUB;  // lane within its item slot
   MaskRec *rec = S.rec;
   const int kc = level & 3, kn = (level + 1) & 3, ko = (level + 2) & 3, kp = (level + 3) & 3;
-  (void)GN;
 
-  // retire the masks of level-2 so that array can collect level+2
+  // retire the masks of level-2 so that word can collect level+2
   if (level >= 2) {
     const uint64_t pb = S.off[(uint64_t)(level - 2) * P + pv.p];
     const uint64_t pc = S.cnt[(uint64_t)(level - 2) * P + pv.p];
@@ -137,91 +159,124 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
 
   uint64_t c_v = 0, c_a = 0, c_d = 0;
   bool ovf = false;
-  const uint64_t wave = pv.wave;
-  const uint64_t nwaves = pv.nwaves;
+  const uint64_t step = pv.nwaves * (uint64_t)K;
   uint32_t *next_cnt = &S.cnt[(uint64_t)(level + 1) * P + pv.p];
   __shared__ uint32_t stage_all[(BLOCK / 64) * kStage];
   uint32_t *stage = stage_all + (threadIdx.x >> 6) * kStage;
   int nst = 0;
-  uint32_t it_next = wave < count ? S.items[base + wave] : 0u;
-  for (uint64_t i = wave; i < count; i += nwaves) {
+  uint64_t ii = pv.wave * (uint64_t)K + (uint64_t)(lane / SUB);  // this lane's item
+  uint32_t it_next = ii < count ? S.items[base + ii] : 0u;
+  for (uint64_t i0 = pv.wave * (uint64_t)K; i0 < count; i0 += step, ii += step) {
+    const bool has = ii < count;
     const uint32_t it = it_next;
-    if (i + nwaves < count) it_next = S.items[base + i + nwaves];  // prefetch the next item
+    if (ii + step < count) it_next = S.items[base + ii + step];  // prefetch the next step's items
     const uint32_t g = (uint32_t)(it / n);
     const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
     const uint64_t gbase = (uint64_t)g * n;
-    // independent loads of this item, issued together
-    const ull mask = rec[it].fr[kc];
-    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    const int64_t f0 = level > 0 ? G.irp[v] : 0, f1 = level > 0 ? G.irp[v + 1] : 0;
-    const int32_t tg = S.tgt_of[v];
-    if (lane == 0) {
-      S.imask[base + i] = mask;
+    // independent loads of this slot's item, issued together
+    ull mask = 0ull;
+    int64_t e0 = 0, e1 = 0, f0 = 0, f1 = 0;
+    int32_t tg = -1;
+    if (has) {
+      mask = rec[it].fr[kc];
+      e0 = G.rp[v];
+      e1 = G.rp[v + 1];
+      if (level > 0) {
+        f0 = G.irp[v];
+        f1 = G.irp[v + 1];
+      }
+      tg = S.tgt_of[v];
+    }
+    if (has && sl == 0) {
+      S.imask[base + ii] = mask;
       rec[it].vis = rec[it].vis | mask;
-    }
-    const bool act = (mask >> lane) & 1ull;
-    if (tg >= 0) {
-      if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
-      if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
-    }
-    const uint64_t pc = (uint64_t)__popcll(mask);
-    if (lane == 0) {
+      const uint64_t pc = (uint64_t)__popcll(mask);
       c_v += pc;
       c_a += pc * (uint64_t)(e1 - e0);
     }
-    // first chunk of in-arcs (sigma pull) and of out-arcs (discovery), interleaved:
-    // 1. both index chunks
-    const int64_t mi = f0 + lane, mo = e0 + lane;
+    // first chunk of in-arcs (sigma pull) and of out-arcs (discovery) of
+    // every slot, interleaved: 1. both index chunks
+    const int64_t mi = f0 + sl, mo = e0 + sl;
     uint32_t u = 0, w = 0;
     if (mi < f1) u = (uint32_t)G.icol[mi];
     if (mo < e1) w = (uint32_t)G.col[mo];
     // 2. both mask gathers
-    ull pm = 0ull, dag = 0ull;
-    if (mi < f1) pm = rec[gbase + u].fr[kp] & mask;
-    // lanes already flagged for level+1 by another wavefront need no atomic
-    // (a stale read only costs a redundant atomic)
+    ull pfr = 0ull, svis = 0ull, sfc = 0ull, sfn = 0ull;
+    if (mi < f1) pfr = rec[gbase + u].fr[kp];
     if (mo < e1) {
       const MaskRec &R = rec[gbase + w];
-      dag = mask & ~(R.vis | R.fr[kc] | R.fr[kn]);
+      svis = R.vis;
+      sfc = R.fr[kc];
+      sfn = R.fr[kn];
     }
+    const ull pm = pfr & mask;
+    // lanes already flagged for level+1 by another wavefront need no atomic
+    // (a stale read only costs a redundant atomic)
+    const ull dag = (mo < e1) ? (mask & ~(svis | sfc | sfn)) : 0ull;
     // 3. discovery flags, then the predecessor rows; the flag results are
     //    consumed only after the rows
     bool enq = false;
     if (dag != 0ull) enq = (atomicOr(&rec[gbase + w].fr[kn], dag) == 0ull);
-    ull acc = 0ull;
-    bool lov = false;
+    ull acc[K];
+    bool lov[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      acc[t] = 0ull;
+      lov[t] = false;
+    }
     c_d += (uint64_t)__popcll(pm);
-    pull_chunk(S, gbase, u, pm, lane, acc, lov);
+    pull_slots<K>(S, gbase, u, pm, lane, acc, lov);
     append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, w, enq);
-    // remaining chunks (vertices of degree > 64)
-    for (int64_t e = f0 + 64; e < f1; e += 64) {
-      const int64_t my = e + lane;
-      uint32_t uu = 0;
-      ull pp = 0ull;
-      if (my < f1) {
-        uu = (uint32_t)G.icol[my];
-        pp = rec[gbase + uu].fr[kp] & mask;
+    // per item: the remaining arcs with the whole wavefront, then the path
+    // counts and target levels of its lanes
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int ld = t * SUB;
+      const ull mt = read_lane64(mask, ld);
+      if (mt == 0ull) continue;  // slot past the end of the list
+      const uint32_t itt = read_lane(it, ld);
+      const uint32_t gt = read_lane(g, ld);
+      const uint64_t gbt = read_lane64(gbase, ld);
+      const int64_t F1 = (int64_t)read_lane64((ull)f1, ld), E1 = (int64_t)read_lane64((ull)e1, ld);
+      const int64_t F0 = (int64_t)read_lane64((ull)f0, ld), E0 = (int64_t)read_lane64((ull)e0, ld);
+      for (int64_t e = F0 + SUB; e < F1; e += kLanes) {
+        const int64_t my = e + lane;
+        uint32_t uu = 0;
+        ull pp = 0ull;
+        if (my < F1) {
+          uu = (uint32_t)G.icol[my];
+          pp = rec[gbt + uu].fr[kp] & mt;
+        }
+        c_d += (uint64_t)__popcll(pp);
+        ull a1[1] = {acc[t]};
+        bool l1[1] = {lov[t]};
+        pull_slots<1>(S, gbt, uu, pp, lane, a1, l1);
+        acc[t] = a1[0];
+        lov[t] = l1[0];
       }
-      c_d += (uint64_t)__popcll(pp);
-      pull_chunk(S, gbase, uu, pp, lane, acc, lov);
-    }
-    for (int64_t e = e0 + 64; e < e1; e += 64) {
-      const int64_t my = e + lane;
-      uint32_t ww = 0;
-      bool eq = false;
-      if (my < e1) {
-        ww = (uint32_t)G.col[my];
-        const MaskRec &R = rec[gbase + ww];
-        const ull dd = mask & ~(R.vis | R.fr[kc] | R.fr[kn]);
-        if (dd != 0ull) eq = (atomicOr(&rec[gbase + ww].fr[kn], dd) == 0ull);
+      for (int64_t e = E0 + SUB; e < E1; e += kLanes) {
+        const int64_t my = e + lane;
+        uint32_t ww = 0;
+        bool eq = false;
+        if (my < E1) {
+          ww = (uint32_t)G.col[my];
+          const MaskRec &R = rec[gbt + ww];
+          const ull dd = mt & ~(R.vis | R.fr[kc] | R.fr[kn]);
+          if (dd != 0ull) eq = (atomicOr(&rec[gbt + ww].fr[kn], dd) == 0ull);
+        }
+        append_chunk(S, stage, nst, next_cnt, nbase, rend, gbt, ww, eq);
       }
-      append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, ww, eq);
-    }
-    if (level > 0) {
-      if (act) S.sig[(uint64_t)it * kLanes + lane] = acc;
-      if (lov) {
-        ovf = true;
-        atomicOr(&S.ovl[g], 1ull << lane);
+      const bool act = (mt >> lane) & 1ull;
+      if ((int32_t)read_lane((uint32_t)tg, ld) >= 0) {
+        if (act) atomicMin(&S.tlev[gt * kLanes + lane], (uint32_t)level);
+        if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
+      }
+      if (level > 0) {
+        if (act) S.sig[(uint64_t)itt * kLanes + lane] = acc[t];
+        if (lov[t]) {
+          ovf = true;
+          atomicOr(&S.ovl[gt], 1ull << lane);
+        }
       }
     }
   }
@@ -582,8 +637,22 @@ hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const 
   return hipGetLastError();
 }
 
+template <int K>
+static void launch_fwd_k(const DevGraph &G, const BatchState &S, int level, const Launch &L, hipStream_t st) {
+  switch (L.block) {
+    case 64: k_fwd_level<64, K><<<dim3(L.grid), dim3(64), 0, st>>>(G, S, level); break;
+    case 128: k_fwd_level<128, K><<<dim3(L.grid), dim3(128), 0, st>>>(G, S, level); break;
+    case 512: k_fwd_level<512, K><<<dim3(L.grid), dim3(512), 0, st>>>(G, S, level); break;
+    default: k_fwd_level<256, K><<<dim3(L.grid), dim3(256), 0, st>>>(G, S, level); break;
+  }
+}
+
 hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st) {
-  DISPATCH_BLOCK(L, k_fwd_level, G, S, level);
+  switch (L.items) {
+    case 2: launch_fwd_k<2>(G, S, level, L, st); break;
+    case 4: launch_fwd_k<4>(G, S, level, L, st); break;
+    default: launch_fwd_k<1>(G, S, level, L, st); break;
+  }
   return hipGetLastError();
 }
 

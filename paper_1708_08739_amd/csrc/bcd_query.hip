@@ -216,6 +216,7 @@ struct BatchExport {
 struct ProfAcc {
   int64_t launches[2] = {0, 0};
   double ms[2] = {0, 0};
+  uint64_t items[2] = {0, 0};
 };
 
 // One batch: `k` sources already staged in ws->h_items0 / h_masks0 (lane i
@@ -350,6 +351,11 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
         prof->ms[kind] += ms;
         prof->launches[kind] += 1;
       }
+      for (int l = 0; l < levels; ++l)
+        for (int p = 0; p < P; ++p) {
+          prof->items[0] += cntp[(size_t)l * P + p];
+          if (stop >= 0 && l >= stop) prof->items[1] += cntp[(size_t)l * P + p];
+        }
     }
     return BCD_OK;
   }
@@ -373,8 +379,8 @@ static void add_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr) {
   //   backward: 32 per (source, vertex) + 8 per (source, arc) + 8 per (source, DAG arc)
   const double fb = 32.0 * ctr[C_FWD_VPAIRS] + 8.0 * ctr[C_FWD_APAIRS] + 8.0 * ctr[C_FWD_DPAIRS];
   const double bb = 32.0 * ctr[C_BWD_VPAIRS] + 8.0 * ctr[C_BWD_APAIRS] + 8.0 * ctr[C_BWD_DPAIRS];
-  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb);
-  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb);
+  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb, p.items[0]);
+  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb, p.items[1]);
 }
 
 static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t> &src,

@@ -90,14 +90,16 @@ def test_source_pass_bitexact(B, oracle, name, make, engine):
 def test_multi_source_pass_groups(B, oracle, k):
     """k sources in one batch: spans 1..3 column groups with a ragged last one."""
     g = gg.rmat(11, 8, seed=5)
-    G = dev(B, g, groups=3)
     src = gg.uniform_vertices(g.n, k, seed=k)
-    print("multi k", k, flush=True)
-    d, sg, dl = G.multi_source_pass(src)
-    for i, s in enumerate(src):
-        od, osg, odl, ovf, _ = oracle.source_pass(g, s)
-        assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (k, i, s)
-        assert close(dl[i], odl), (k, i, s)
+    want = [oracle.source_pass(g, s) for s in src]
+    for items in (1, 2, 4):
+        G = dev(B, g, groups=3, items=items)
+        print("multi k", k, "items", items, flush=True)
+        d, sg, dl = G.multi_source_pass(src)
+        for i, s in enumerate(src):
+            od, osg, odl, ovf, _ = want[i]
+            assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (k, items, i, s)
+            assert close(dl[i], odl), (k, items, i, s)
 
 
 def test_partition_count_changes_between_batches(B, oracle):
@@ -137,6 +139,9 @@ def test_bc_exact_er2000_both_engines(B, oracle):
     for cfg in [dict(engine=B.BCD_ENGINE_BATCHED, groups=1), dict(engine=B.BCD_ENGINE_BATCHED, groups=5),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=16, block=512),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=2, block=64, grid_mult=1),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=5, items=1),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=5, items=2, block=128),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=3, items=4, grid_mult=1),
                 dict(engine=B.BCD_ENGINE_PLAIN)]:
         print("er2000", cfg, flush=True)
         G = dev(B, g, **cfg)
@@ -146,8 +151,8 @@ def test_bc_exact_er2000_both_engines(B, oracle):
         assert st["traversed_edges"] == ost["te"]
         assert st["reached"] == ost["reached"] and st["dag_arcs"] == ost["dag_arcs"]
         vals.append(got)
-    # batched results do not depend on the batch width
-    assert vals[0] == vals[1] == vals[2] == vals[3]
+    # batched results do not depend on the batch width or the items per step
+    assert all(v == vals[0] for v in vals[:-1])
 
 
 def test_bc_exact_repeatable(B):
@@ -196,18 +201,31 @@ def test_degenerate_graphs(B):
     assert v == 0.0 and st["rv_size"] == 0
 
 
-def test_sigma_overflow(B):
+def test_sigma_overflow(B, oracle):
     g, ids = gg.diamond_chain(63)
     G = dev(B, g)
     assert G.bc_exact(ids["x"][31])[0] == 9 * 31 * 32
     d, sg, _ = G.source_pass(0)
     assert int(sg[ids["x"][63]]) == 1 << 63
     g64, ids64 = gg.diamond_chain(64)
-    for engine in (B.BCD_ENGINE_BATCHED, B.BCD_ENGINE_PLAIN):
-        G = dev(B, g64, engine=engine)
+    for cfg in (dict(engine=B.BCD_ENGINE_BATCHED, items=1), dict(engine=B.BCD_ENGINE_BATCHED, items=2),
+                dict(engine=B.BCD_ENGINE_BATCHED, items=4), dict(engine=B.BCD_ENGINE_PLAIN)):
+        G = dev(B, g64, **cfg)
         with pytest.raises(B.BcdError) as e:
             G.bc_exact(ids64["x"][40])
         assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW
+    # counts on both sides of 2^32 in one batch, and in one (group, vertex)
+    # row on different levels (sources at different depths of the chain)
+    g40, ids40 = gg.diamond_chain(40)
+    src = [ids40["x"][i] for i in (0, 3, 9, 20, 30)] + [ids40["a"][2], ids40["b"][7]]
+    want = [oracle.source_pass(g40, s) for s in src]
+    for items in (1, 4):
+        d, sg, dl = dev(B, g40, groups=1, items=items).multi_source_pass(src)
+        for i, s in enumerate(src):
+            od, osg, odl, ovf, _ = want[i]
+            assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (items, s)
+            assert close(dl[i], odl), (items, s)
+    assert int(want[0][1][ids40["x"][40]]) == 1 << 40
     G = dev(B, gg.grid_right_down(35, 35))
     with pytest.raises(B.BcdError) as e:
         G.source_pass(0)

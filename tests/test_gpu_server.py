@@ -72,7 +72,7 @@ def test_server_budget_admission_and_errors(B):
     alone = {r: G.bc_exact(r)[0] for r in qs}
     # budget so tight that queries must wait for each other's buffers
     nrv = max(int(G.bc_exact(r)[1]["rv_size"]) for r in qs)
-    ws = 1 * g.n * 64 * 16 + g.n * 64 + g.n * 48 + g.n * 24
+    ws = B.Server.workspace_bytes(G, groups=1, workers=1)
     S = B.Server(G, workers=1, groups=1, hbm_budget_bytes=ws + 8 * nrv + 64)
     ts = [S.submit(B.BCD_QUERY_EXACT, r=r) for r in qs]
     res = drain(S, len(ts))
