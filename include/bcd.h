@@ -87,6 +87,12 @@ typedef struct bcd_config {
   int32_t items;      /* batched engine, unweighted forward: frontier items a
                          wavefront takes per step, 1, 2 or 4 (64 / items lanes
                          per item for its first arcs); 0 = default */
+  int32_t bottom_up;  /* batched engine, unweighted forward: a BFS level is
+                         found bottom-up (in-arcs of the unsettled (group,
+                         vertex) pairs) when the level before it holds at
+                         least 1/bottom_up of the batch's (group, vertex)
+                         pairs; 0 = always top-down (the default), -1 =
+                         default */
 } bcd_config;
 
 /* Sampled estimate (Alg.2).  T comes from Eq.(8) unless T_override > 0. */

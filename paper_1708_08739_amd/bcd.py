@@ -51,7 +51,7 @@ class Stats(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("engine", C.c_int32), ("groups", C.c_int32), ("block", C.c_int32),
-                ("grid_mult", C.c_int32), ("items", C.c_int32)]
+                ("grid_mult", C.c_int32), ("items", C.c_int32), ("bottom_up", C.c_int32)]
 
 
 class SampleParams(C.Structure):
@@ -232,10 +232,13 @@ class Graph:
         check(load().bcd_get_config(self.h, C.byref(c)), "bcd_get_config")
         return c
 
-    def set_config(self, engine=None, groups=None, block=None, grid_mult=None, items=None) -> Config:
+    def set_config(self, engine=None, groups=None, block=None, grid_mult=None, items=None,
+                   bottom_up=None) -> Config:
         c = self.config()
         if items is not None:
             c.items = items
+        if bottom_up is not None:
+            c.bottom_up = bottom_up
         if engine is not None:
             c.engine = engine
         if groups is not None:

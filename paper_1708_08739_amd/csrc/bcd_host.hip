@@ -549,6 +549,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->cfg.block = 256;
   g->cfg.grid_mult = 32;
   g->cfg.items = kDefaultItems;
+  g->cfg.bottom_up = kDefaultBottomUp;
   *out = reinterpret_cast<bcd_graph *>(g.release());
   return BCD_OK;
 }
@@ -580,9 +581,12 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
   if (cfg->grid_mult < 1 || cfg->grid_mult > 32) return fail(BCD_ERR_INVALID_ARG, "grid_mult must be in [1, 32]");
   if (cfg->items != 0 && cfg->items != 1 && cfg->items != 2 && cfg->items != 4)
     return fail(BCD_ERR_INVALID_ARG, "items must be 1, 2 or 4 (0 = default)");
+  if (cfg->bottom_up < -1 || cfg->bottom_up > 4096)
+    return fail(BCD_ERR_INVALID_ARG, "bottom_up must be in [-1, 4096]");
   std::lock_guard<std::mutex> lk(g->cfg_mu);
   g->cfg = *cfg;
   if (g->cfg.items == 0) g->cfg.items = kDefaultItems;
+  if (g->cfg.bottom_up < 0) g->cfg.bottom_up = kDefaultBottomUp;
   return BCD_OK;
 }
 

@@ -29,6 +29,7 @@ namespace bcd {
 constexpr int kCtrSlots = 8192;       // max workgroups of a traversal launch
 constexpr int kLevelChunkMax = 64;    // level launches enqueued between host checks
 constexpr int kDefaultItems = 2;      // frontier items per wavefront step, unweighted forward
+constexpr int kDefaultBottomUp = 0;   // bottom-up threshold denominator (0: top-down only), unweighted forward
 constexpr int kMaxParts = 8;          // item-list partitions (one per XCD)
 constexpr int kCntStage = (kLevelChunkMax + 2) * kMaxParts;  // pinned slots for level counts
 

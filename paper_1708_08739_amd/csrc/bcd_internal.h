@@ -75,6 +75,10 @@ struct BatchState {
   unsigned long long *ovl;   // [G] lanes whose sigma overflowed
   uint32_t epoch;
   int ctr_slots;
+  // per batch (unweighted engine)
+  int gused;                     // column groups holding sources: 0 .. gused-1
+  unsigned long long last_lanes; // lanes of group gused-1 that hold a source
+  int bu_den;                    // bottom-up levels: see level_bottom_up (0 = never)
   // weighted graphs only
   uint32_t *wd;              // [G][n][64] distances, 0xFFFFFFFF unreached
   uint32_t *wc;              // [G][n][64] shortest-path-DAG in-arcs not yet pushed
@@ -111,6 +115,15 @@ struct DevGraph {
   const uint32_t *iw;
 };
 
+// Whether BFS level `level` (>= 2) of a batch is found bottom-up, from the
+// item count of level-1 (complete before any kernel of `level` starts):
+// when level-1 holds at least 1 / bu_den of the batch's (group, vertex)
+// pairs, scanning the in-arcs of the unsettled pairs is cheaper than the
+// out-arcs of the frontier.  Host and device evaluate the same integer rule.
+__host__ __device__ inline bool bottom_up_rule(int bu_den, int level, uint64_t prev_count, int gused, int64_t n) {
+  return bu_den > 0 && level >= 2 && prev_count * (uint64_t)bu_den >= (uint64_t)gused * (uint64_t)n;
+}
+
 struct Launch {
   int block;      // threads per workgroup
   int grid;       // workgroups
@@ -124,6 +137,7 @@ struct PartTotals {
 hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const unsigned long long *masks0,
                              const uint32_t *dest0, int k, hipStream_t st);
 hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st);
+hipError_t launch_bu_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st);
 hipError_t launch_bwd_level(const DevGraph &G, const BatchState &S, int level, int ntgt, int full,
                             Launch L, hipStream_t st);
 hipError_t launch_batch_cleanup(const BatchState &S, const PartTotals &tot, Launch L, hipStream_t st);

@@ -43,9 +43,9 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
 // predecessors are issued before any of them is consumed; the sums are
 // exact integers, so the order of the adds does not matter, and an
 // unsigned wrap on any add means the true sum exceeds 2^64 - 1.
-template <int K>
+template <int K, bool HIT = false>
 static __device__ __forceinline__ void pull_slots(const BatchState &S, uint64_t gbase, uint32_t u, ull pm, int lane,
-                                                  ull (&acc)[K], bool (&lov)[K]) {
+                                                  ull (&acc)[K], bool (&lov)[K], bool (&hit)[K]) {
   constexpr int SUB = kLanes / K;
   ull bits = __ballot(pm != 0ull);
   while (bits != 0ull) {
@@ -65,6 +65,17 @@ static __device__ __forceinline__ void pull_slots(const BatchState &S, uint64_t 
         const ull dq = read_lane64(pm, j[q]);
         const uint64_t gq = read_lane64(gbase, j[q]);
         if ((dq >> lane) & 1ull) x[q] = S.sig[(gq + uq) * kLanes + lane];
+      }
+    }
+    if (HIT) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (q < c && ((read_lane64(pm, j[q]) >> lane) & 1ull)) {
+          const int slot = j[q] / SUB;
+#pragma unroll
+          for (int t = 0; t < K; ++t)
+            if (slot == t) hit[t] = true;
+        }
       }
     }
 #pragma unroll
@@ -144,7 +155,9 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
   const uint64_t nbase = base + count;
   const uint64_t rend = (uint64_t)(pv.p + 1) * S.capP;
   if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
-  if (S.flags[1] != 0u || nbase > rend) return;  // capacity exceeded earlier: batch is redone
+  // capacity exceeded (the batch is redone); the test is the same for every
+  // thread of the workgroup, so no wave leaves before the counter barrier
+  if (nbase > rend) return;
   const int lane = lane_id();
   const int sl = lane % SUB;  // lane within its item slot
   MaskRec *rec = S.rec;
@@ -156,6 +169,17 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
     const uint64_t pc = S.cnt[(uint64_t)(level - 2) * P + pv.p];
     for (uint64_t i = pv.thread; i < pc; i += pv.nthreads) rec[S.items[pb + i]].fr[ko] = 0ull;
   }
+  // This launch pulls sigma for the level's items (and settles their lanes)
+  // unless the bottom-up kernel already found them with their counts, and
+  // discovers level+1 unless that level will be found bottom-up.  Both
+  // tests read complete counts, so every workgroup decides alike.
+  uint64_t prev = 0;
+  if (level >= 1)
+    for (int p = 0; p < P; ++p) prev += S.cnt[(uint64_t)(level - 1) * P + p];
+  uint64_t cur = 0;
+  for (int p = 0; p < P; ++p) cur += S.cnt[(uint64_t)level * P + p];
+  const bool pull = !bottom_up_rule(S.bu_den, level, prev, S.gused, S.n);
+  const bool disc = !bottom_up_rule(S.bu_den, level + 1, cur, S.gused, S.n);
 
   uint64_t c_v = 0, c_a = 0, c_d = 0;
   bool ovf = false;
@@ -181,29 +205,32 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
       mask = rec[it].fr[kc];
       e0 = G.rp[v];
       e1 = G.rp[v + 1];
-      if (level > 0) {
+      if (level > 0 && pull) {
         f0 = G.irp[v];
         f1 = G.irp[v + 1];
       }
-      tg = S.tgt_of[v];
+      if (pull) tg = S.tgt_of[v];
     }
+    const int64_t d1 = disc ? e1 : e0;  // end of the out-arcs to scan
     if (has && sl == 0) {
       S.imask[base + ii] = mask;
-      rec[it].vis = rec[it].vis | mask;
-      const uint64_t pc = (uint64_t)__popcll(mask);
-      c_v += pc;
-      c_a += pc * (uint64_t)(e1 - e0);
+      if (pull) {
+        rec[it].vis = rec[it].vis | mask;
+        const uint64_t pc = (uint64_t)__popcll(mask);
+        c_v += pc;
+        c_a += pc * (uint64_t)(e1 - e0);
+      }
     }
     // first chunk of in-arcs (sigma pull) and of out-arcs (discovery) of
     // every slot, interleaved: 1. both index chunks
     const int64_t mi = f0 + sl, mo = e0 + sl;
     uint32_t u = 0, w = 0;
     if (mi < f1) u = (uint32_t)G.icol[mi];
-    if (mo < e1) w = (uint32_t)G.col[mo];
+    if (mo < d1) w = (uint32_t)G.col[mo];
     // 2. both mask gathers
     ull pfr = 0ull, svis = 0ull, sfc = 0ull, sfn = 0ull;
     if (mi < f1) pfr = rec[gbase + u].fr[kp];
-    if (mo < e1) {
+    if (mo < d1) {
       const MaskRec &R = rec[gbase + w];
       svis = R.vis;
       sfc = R.fr[kc];
@@ -212,7 +239,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
     const ull pm = pfr & mask;
     // lanes already flagged for level+1 by another wavefront need no atomic
     // (a stale read only costs a redundant atomic)
-    const ull dag = (mo < e1) ? (mask & ~(svis | sfc | sfn)) : 0ull;
+    const ull dag = (mo < d1) ? (mask & ~(svis | sfc | sfn)) : 0ull;
     // 3. discovery flags, then the predecessor rows; the flag results are
     //    consumed only after the rows
     bool enq = false;
@@ -225,7 +252,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
       lov[t] = false;
     }
     c_d += (uint64_t)__popcll(pm);
-    pull_slots<K>(S, gbase, u, pm, lane, acc, lov);
+    pull_slots<K>(S, gbase, u, pm, lane, acc, lov, lov);
     append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, w, enq);
     // per item: the remaining arcs with the whole wavefront, then the path
     // counts and target levels of its lanes
@@ -237,7 +264,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
       const uint32_t itt = read_lane(it, ld);
       const uint32_t gt = read_lane(g, ld);
       const uint64_t gbt = read_lane64(gbase, ld);
-      const int64_t F1 = (int64_t)read_lane64((ull)f1, ld), E1 = (int64_t)read_lane64((ull)e1, ld);
+      const int64_t F1 = (int64_t)read_lane64((ull)f1, ld), E1 = (int64_t)read_lane64((ull)d1, ld);
       const int64_t F0 = (int64_t)read_lane64((ull)f0, ld), E0 = (int64_t)read_lane64((ull)e0, ld);
       for (int64_t e = F0 + SUB; e < F1; e += kLanes) {
         const int64_t my = e + lane;
@@ -250,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
         c_d += (uint64_t)__popcll(pp);
         ull a1[1] = {acc[t]};
         bool l1[1] = {lov[t]};
-        pull_slots<1>(S, gbt, uu, pp, lane, a1, l1);
+        pull_slots<1>(S, gbt, uu, pp, lane, a1, l1, l1);
         acc[t] = a1[0];
         lov[t] = l1[0];
       }
@@ -266,6 +293,7 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
         }
         append_chunk(S, stage, nst, next_cnt, nbase, rend, gbt, ww, eq);
       }
+      if (!pull) continue;
       const bool act = (mt >> lane) & 1ull;
       if ((int32_t)read_lane((uint32_t)tg, ld) >= 0) {
         if (act) atomicMin(&S.tlev[gt * kLanes + lane], (uint32_t)level);
@@ -281,6 +309,155 @@ __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, i
     }
   }
   flush_stage(S, stage, nst, next_cnt, nbase, rend);
+  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
+}
+
+// 64-bit lane shuffle (ds_bpermute on both halves).
+static __device__ __forceinline__ ull shfl64(ull x, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src);
+  return ((ull)hi << 32) | lo;
+}
+
+// One BFS level found bottom-up (direction-optimizing BFS, here over 64
+// sources at once): every (g, w) of the batch with in-arcs and with lanes
+// not yet settled scans its in-arcs (u, w); lanes b of u's previous-level
+// mask that are unsettled at w are DAG arcs of w on this level, so one scan
+// both finds the level's lanes of w and pulls their path counts (a lane is
+// on the level iff some in-arc delivered a count to it).  No atomics on the
+// masks; (g, w) is appended to the level's list if it gained any lane.
+// Runs before the top-down kernel of the same level, and only when
+// bottom_up_rule holds for the level.  The unsettled pairs of a 64-vertex
+// block are taken K at a time, 64 / K lanes each for their first in-arcs.
+template <int BLOCK, int K>
+__global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, int level) {
+  constexpr int SUB = kLanes / K;
+  const uint64_t n = (uint64_t)S.n;
+  const int P = S.P;
+  uint64_t prev = 0;
+  for (int p = 0; p < P; ++p) prev += S.cnt[(uint64_t)(level - 1) * P + p];
+  if (!bottom_up_rule(S.bu_den, level, prev, S.gused, S.n)) return;
+  const PartView pv = part_view<BLOCK>(P);
+  const uint64_t base = S.off[(uint64_t)level * P + pv.p];
+  const uint64_t rend = (uint64_t)(pv.p + 1) * S.capP;
+  if (base > rend) return;  // capacity exceeded earlier (workgroup-uniform test): the batch is redone
+  const int lane = lane_id();
+  const int slot = lane / SUB, sl = lane % SUB;
+  MaskRec *rec = S.rec;
+  const int kc = level & 3, kp = (level + 3) & 3;
+  uint32_t *cnt_here = &S.cnt[(uint64_t)level * P + pv.p];
+  __shared__ uint32_t stage_all[(BLOCK / 64) * kStage];
+  uint32_t *stage = stage_all + (threadIdx.x >> 6) * kStage;
+  int nst = 0;
+  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  bool ovf = false;
+  // groups p, p + P, ... below gused belong to this partition
+  const uint64_t ngp = S.gused > pv.p ? (uint64_t)(S.gused - pv.p + P - 1) / (uint64_t)P : 0;
+  const uint64_t nvb = (n + 63) / 64;
+  for (uint64_t b = pv.wave; b < ngp * nvb; b += pv.nwaves) {
+    const uint64_t gl = b / nvb;
+    const uint32_t g = (uint32_t)(pv.p + gl * (uint64_t)P);
+    const uint64_t gbase = (uint64_t)g * n;
+    const uint64_t w0 = (b - gl * nvb) * 64;
+    const uint64_t w = w0 + lane;
+    const ull act_lanes = (g + 1 == (uint32_t)S.gused) ? S.last_lanes : ~0ull;
+    int64_t f0 = 0, f1 = 0;
+    ull uns = 0ull;
+    if (w < n) {
+      f0 = G.irp[w];
+      f1 = G.irp[w + 1];
+      if (f1 > f0) uns = act_lanes & ~rec[gbase + w].vis;
+    }
+    ull cm = __ballot(uns != 0ull);
+    while (cm != 0ull) {
+      // the next K candidates of the block, one per slot
+      int jc[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        jc[t] = cm != 0ull ? __ffsll((long long)cm) - 1 : -1;
+        if (cm != 0ull) cm &= cm - 1ull;
+      }
+      int js = jc[0];
+#pragma unroll
+      for (int t = 1; t < K; ++t)
+        if (slot == t) js = jc[t];
+      // the shuffles run on every lane: a permute reads nothing from a lane
+      // that is switched off, and the candidate's own lane may sit in a slot
+      // that has no candidate this step
+      const int src = js < 0 ? 0 : js;
+      const ull un_src = shfl64(uns, src);
+      const int64_t F0 = (int64_t)shfl64((ull)f0, src);
+      const int64_t F1_src = (int64_t)shfl64((ull)f1, src);
+      const ull un = js < 0 ? 0ull : un_src;
+      const int64_t F1 = js < 0 ? F0 : F1_src;
+      // first chunk of every slot's in-arcs
+      const int64_t mi = F0 + sl;
+      uint32_t u = 0;
+      ull pfr = 0ull;
+      if (mi < F1) {
+        u = (uint32_t)G.icol[mi];
+        pfr = rec[gbase + u].fr[kp];
+      }
+      const ull pm = pfr & un;
+      ull acc[K];
+      bool lov[K], hit[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        acc[t] = 0ull;
+        lov[t] = false;
+        hit[t] = false;
+      }
+      c_d += (uint64_t)__popcll(pm);
+      pull_slots<K, true>(S, gbase, u, pm, lane, acc, lov, hit);
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        if (jc[t] < 0) continue;
+        const ull ut = read_lane64(uns, jc[t]);
+        const int64_t G0 = (int64_t)read_lane64((ull)f0, jc[t]), G1 = (int64_t)read_lane64((ull)f1, jc[t]);
+        for (int64_t e = G0 + SUB; e < G1; e += kLanes) {
+          const int64_t my = e + lane;
+          uint32_t uu = 0;
+          ull pp = 0ull;
+          if (my < G1) {
+            uu = (uint32_t)G.icol[my];
+            pp = rec[gbase + uu].fr[kp] & ut;
+          }
+          c_d += (uint64_t)__popcll(pp);
+          ull a1[1] = {acc[t]};
+          bool l1[1] = {lov[t]}, h1[1] = {hit[t]};
+          pull_slots<1, true>(S, gbase, uu, pp, lane, a1, l1, h1);
+          acc[t] = a1[0];
+          lov[t] = l1[0];
+          hit[t] = h1[0];
+        }
+        const ull nm = __ballot(hit[t]);  // lanes of w on this level
+        if (nm == 0ull) continue;
+        const uint32_t wt = (uint32_t)(w0 + (uint64_t)jc[t]);
+        const uint32_t it = (uint32_t)(gbase + wt);
+        const bool act = (nm >> lane) & 1ull;
+        const int64_t e0 = G.rp[wt], e1 = G.rp[wt + 1];
+        const int32_t tg = S.tgt_of[wt];
+        if (act) S.sig[(uint64_t)it * kLanes + lane] = acc[t];
+        if (lov[t]) {
+          ovf = true;
+          atomicOr(&S.ovl[g], 1ull << lane);
+        }
+        if (lane == 0) {
+          rec[it].fr[kc] = nm;
+          rec[it].vis = rec[it].vis | nm;
+          const uint64_t pc = (uint64_t)__popcll(nm);
+          c_v += pc;
+          c_a += pc * (uint64_t)(e1 - e0);
+        }
+        if (tg >= 0) {
+          if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
+          if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
+        }
+        append_chunk(S, stage, nst, cnt_here, base, rend, gbase, wt, lane == 0);
+      }
+    }
+  }
+  flush_stage(S, stage, nst, cnt_here, base, rend);
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
 }
 
@@ -645,6 +822,25 @@ static void launch_fwd_k(const DevGraph &G, const BatchState &S, int level, cons
     case 512: k_fwd_level<512, K><<<dim3(L.grid), dim3(512), 0, st>>>(G, S, level); break;
     default: k_fwd_level<256, K><<<dim3(L.grid), dim3(256), 0, st>>>(G, S, level); break;
   }
+}
+
+template <int K>
+static void launch_bu_k(const DevGraph &G, const BatchState &S, int level, const Launch &L, hipStream_t st) {
+  switch (L.block) {
+    case 64: k_bu_level<64, K><<<dim3(L.grid), dim3(64), 0, st>>>(G, S, level); break;
+    case 128: k_bu_level<128, K><<<dim3(L.grid), dim3(128), 0, st>>>(G, S, level); break;
+    case 512: k_bu_level<512, K><<<dim3(L.grid), dim3(512), 0, st>>>(G, S, level); break;
+    default: k_bu_level<256, K><<<dim3(L.grid), dim3(256), 0, st>>>(G, S, level); break;
+  }
+}
+
+hipError_t launch_bu_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st) {
+  switch (L.items) {
+    case 2: launch_bu_k<2>(G, S, level, L, st); break;
+    case 4: launch_bu_k<4>(G, S, level, L, st); break;
+    default: launch_bu_k<1>(G, S, level, L, st); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, Launch L, hipStream_t st) {

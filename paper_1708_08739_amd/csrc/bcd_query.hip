@@ -239,6 +239,9 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     BatchState S = ws->S;  // kernel arguments: this batch's epoch and capacity
     if (!ex) S.dout = nullptr;
     S.P = ws->batch_parts(k);  // partitions that hold this batch's groups
+    S.gused = (k + kLanes - 1) / kLanes;
+    S.last_lanes = (k % kLanes) == 0 ? ~0ull : ((1ull << (k % kLanes)) - 1ull);
+    S.bu_den = g->config().bottom_up;
     const int P = S.P;
     const Launch L = g->launch_parts(P);
     // level-0 placement depends on the partition sizes (they change when the list grows)
@@ -255,17 +258,27 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
     HIPCHK(launch_batch_init(S, ws->d_items0, ws->d_masks0, ws->d_dest0, k, st));
 
-    // forward, in chunks of levels between host checks
+    // forward, in chunks of levels between host checks; a level found
+    // bottom-up gets its own kernel, launched before the level's top-down
+    // kernel (both decide on the device whether they have work)
     std::vector<uint32_t> cntp(hc0, hc0 + P);  // cntp[l * P + p] = items of partition p on level l
+    uint64_t last_tot = (uint64_t)k;           // items of the last recorded level
     int lmax = -1;
     int level = 0;
     int chunk = std::min(kLevelChunkMax, std::max(4, ws->last_depth + 2));
     uint32_t flags_h[2] = {0, 0}, tmin_h = 0xFFFFFFFFu;
     size_t ev = 0;
     while (lmax < 0) {
-      const int first = level;
       int launched = 0;
       for (; launched < chunk && level <= g->n; ++launched, ++level) {
+        if (S.bu_den > 0 && level >= 2) {
+          if (profiling) HIPCHK(hipEventRecord(ws->event_pair(ev).first, st));
+          HIPCHK(launch_bu_level(D, S, level, L, st));
+          if (profiling) {
+            HIPCHK(hipEventRecord(ws->event_pair(ev).second, st));
+            ++ev;
+          }
+        }
         if (profiling) HIPCHK(hipEventRecord(ws->event_pair(ev).first, st));
         HIPCHK(launch_fwd_level(D, S, level, L, st));
         if (profiling) {
@@ -273,7 +286,11 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
           ++ev;
         }
       }
-      HIPCHK(hipMemcpyAsync(hc, &S.cnt[(size_t)(first + 1) * P], (size_t)launched * P * sizeof(uint32_t),
+      // counts of the levels not recorded yet, up to the one the last
+      // launch discovered (or that the next chunk finds bottom-up)
+      const int rec_from = (int)(cntp.size() / P);
+      const int nrec = level - rec_from + 1;
+      HIPCHK(hipMemcpyAsync(hc, &S.cnt[(size_t)rec_from * P], (size_t)nrec * P * sizeof(uint32_t),
                             hipMemcpyDeviceToHost, st));
       uint32_t *hm = reinterpret_cast<uint32_t *>(ws->h_misc);
       HIPCHK(hipMemcpyAsync(hm, S.flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -283,14 +300,18 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
       flags_h[1] = hm[1];
       tmin_h = hm[2];
       if (flags_h[1]) break;
-      for (int i = 0; i < launched; ++i) {
+      for (int i = 0; i < nrec; ++i) {
+        const int l = rec_from + i;
         uint64_t tot = 0;
         for (int p = 0; p < P; ++p) tot += hc[(size_t)i * P + p];
+        // level `level` is only counted once its bottom-up kernel has run
+        if (l == level && bottom_up_rule(S.bu_den, l, last_tot, S.gused, S.n)) break;
         if (tot == 0) {
-          lmax = first + i;
+          lmax = l;
           break;
         }
         cntp.insert(cntp.end(), hc + (size_t)i * P, hc + (size_t)(i + 1) * P);
+        last_tot = tot;
       }
       if (lmax < 0 && level > g->n) return fail(BCD_ERR_DEVICE, "forward pass did not terminate");
       chunk = kLevelChunkMax;

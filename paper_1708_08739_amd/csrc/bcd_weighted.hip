@@ -194,7 +194,7 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
   const uint64_t nbase = base + count;
   const uint64_t rend = (uint64_t)(pv.p + 1) * S.capP;
   if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
-  if (S.flags[1] != 0u || nbase > rend) return;
+  if (nbase > rend) return;  // capacity exceeded earlier (workgroup-uniform test): batch is redone
   const int lane = lane_id();
   ull *cur = S.fr + (uint64_t)(level % 3) * GN;
   ull *nxt = S.fr + (uint64_t)((level + 1) % 3) * GN;

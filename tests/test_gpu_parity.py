@@ -92,9 +92,9 @@ def test_multi_source_pass_groups(B, oracle, k):
     g = gg.rmat(11, 8, seed=5)
     src = gg.uniform_vertices(g.n, k, seed=k)
     want = [oracle.source_pass(g, s) for s in src]
-    for items in (1, 2, 4):
-        G = dev(B, g, groups=3, items=items)
-        print("multi k", k, "items", items, flush=True)
+    for items, bu in ((1, 0), (2, -1), (4, 0), (1, 4096), (2, 4096), (4, 4096)):
+        G = dev(B, g, groups=3, items=items, bottom_up=bu)
+        print("multi k", k, "items", items, "bottom_up", bu, flush=True)
         d, sg, dl = G.multi_source_pass(src)
         for i, s in enumerate(src):
             od, osg, odl, ovf, _ = want[i]
@@ -142,6 +142,10 @@ def test_bc_exact_er2000_both_engines(B, oracle):
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=5, items=1),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=5, items=2, block=128),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=3, items=4, grid_mult=1),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=5, bottom_up=0),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=5, bottom_up=4096, items=1),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=7, bottom_up=4096, items=4, block=512),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=2, bottom_up=2, items=2),
                 dict(engine=B.BCD_ENGINE_PLAIN)]:
         print("er2000", cfg, flush=True)
         G = dev(B, g, **cfg)
@@ -151,7 +155,8 @@ def test_bc_exact_er2000_both_engines(B, oracle):
         assert st["traversed_edges"] == ost["te"]
         assert st["reached"] == ost["reached"] and st["dag_arcs"] == ost["dag_arcs"]
         vals.append(got)
-    # batched results do not depend on the batch width or the items per step
+    # batched results do not depend on the batch width, the items per step or
+    # the direction of the level scans
     assert all(v == vals[0] for v in vals[:-1])
 
 
@@ -209,7 +214,8 @@ def test_sigma_overflow(B, oracle):
     assert int(sg[ids["x"][63]]) == 1 << 63
     g64, ids64 = gg.diamond_chain(64)
     for cfg in (dict(engine=B.BCD_ENGINE_BATCHED, items=1), dict(engine=B.BCD_ENGINE_BATCHED, items=2),
-                dict(engine=B.BCD_ENGINE_BATCHED, items=4), dict(engine=B.BCD_ENGINE_PLAIN)):
+                dict(engine=B.BCD_ENGINE_BATCHED, items=4), dict(engine=B.BCD_ENGINE_BATCHED, bottom_up=4096),
+                dict(engine=B.BCD_ENGINE_PLAIN)):
         G = dev(B, g64, **cfg)
         with pytest.raises(B.BcdError) as e:
             G.bc_exact(ids64["x"][40])
@@ -219,8 +225,8 @@ def test_sigma_overflow(B, oracle):
     g40, ids40 = gg.diamond_chain(40)
     src = [ids40["x"][i] for i in (0, 3, 9, 20, 30)] + [ids40["a"][2], ids40["b"][7]]
     want = [oracle.source_pass(g40, s) for s in src]
-    for items in (1, 4):
-        d, sg, dl = dev(B, g40, groups=1, items=items).multi_source_pass(src)
+    for items, bu in ((1, 0), (4, 0), (2, 4096), (4, 4096)):
+        d, sg, dl = dev(B, g40, groups=1, items=items, bottom_up=bu).multi_source_pass(src)
         for i, s in enumerate(src):
             od, osg, odl, ovf, _ = want[i]
             assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (items, s)
@@ -294,6 +300,9 @@ def test_rmat16_sampled_sources_bench_config(B, oracle):
     got, st = G.bc_exact(r)
     want, ost = oracle.bc_exact(g, r)
     assert close(got, want) and st["traversed_edges"] == ost["te"]
+    # heavy levels found bottom-up: the same value bit for bit, and the same counters
+    got0, st0 = dev(B, g, bottom_up=16).bc_exact(r)
+    assert got0 == got and st0["traversed_edges"] == st["traversed_edges"] and st0["dag_arcs"] == st["dag_arcs"]
 
 
 # ------------------------------------------------------------ weighted
