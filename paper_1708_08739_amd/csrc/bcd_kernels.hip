@@ -461,6 +461,48 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
 }
 
+// Sum of psi_b(w) over the out-arcs held by one chunk of lanes whose head w
+// is a shortest-path-DAG successor for lane b (d = lanes of that arc); the
+// chunk holds the arcs of up to K items, 64 / K lanes each, and an arc adds
+// into its item's accumulator.  Bits are taken in lane order, which is arc
+// order within an item, so every item's sum runs in arc order whatever K is.
+// Row loads of up to eight successors are issued before any is consumed.
+template <int K>
+static __device__ __forceinline__ void push_sum_slots(const BatchState &S, uint64_t gbase, uint32_t w, ull d,
+                                                      int lane, double (&acc)[K]) {
+  constexpr int SUB = kLanes / K;
+  ull bits = __ballot(d != 0ull);
+  while (bits != 0ull) {
+    int j[8];
+    int c = 0;
+    for (; c < 8 && bits != 0ull; ++c) {
+      j[c] = __ffsll((long long)bits) - 1;
+      bits &= bits - 1ull;
+    }
+    double x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      x[q] = 0.0;
+      if (q < c) {
+        const uint32_t wq = read_lane(w, j[q]);
+        const ull dq = read_lane64(d, j[q]);
+        const uint64_t gq = read_lane64(gbase, j[q]);
+        if ((dq >> lane) & 1ull) x[q] = S.psi[(gq + wq) * kLanes + lane];
+      }
+    }
+    // adding 0.0 for a lane off the DAG leaves its sum unchanged
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < c) {
+        const int slot = j[q] / SUB;
+#pragma unroll
+        for (int t = 0; t < K; ++t)
+          if (slot == t) acc[t] += x[q];
+      }
+    }
+  }
+}
+
 // One level of the backward pass, Eq.(4) read as
 //   delta(v) = sigma(v) * sum_{w: v in P(w)} psi(w),  psi(w) = (1 + delta(w)) / sigma(w),
 // so psi(v) = 1/sigma(v) + sum psi(w).  Successor w of v is on the DAG for
@@ -468,10 +510,13 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
 // previous (deeper) launch wrote.  Lanes whose nearest target lies at or
 // below this level are skipped (their psi here cannot reach a target), and
 // target vertices report delta on their lanes.  No atomics: every sum runs
-// in arc order, so results are bit-reproducible.
-template <int BLOCK>
+// in arc order, so results are bit-reproducible.  A wavefront takes K items
+// per step, their first 64 / K out-arcs in one chunk of lanes (as in the
+// forward kernel), then longer out-arc lists 64 at a time.
+template <int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, int level, int ntgt,
                                                      int full) {
+  constexpr int SUB = kLanes / K;
   const uint64_t n = (uint64_t)S.n;
   const uint64_t GN = (uint64_t)S.G * n;
   const int P = S.P;
@@ -480,84 +525,111 @@ __global__ __launch_bounds__(BLOCK) void k_bwd_level(DevGraph G, BatchState S, i
   const uint64_t count = S.cnt[(uint64_t)level * P + pv.p];
   if (base + count > (uint64_t)(pv.p + 1) * S.capP) return;
   const int lane = lane_id();
+  const int sl = lane % SUB;
   const LevMask *bt_in = S.bt + (uint64_t)((level + 1) & 1) * GN;
   LevMask *bt_out = S.bt + (uint64_t)(level & 1) * GN;
   const uint32_t E = S.epoch;
   uint64_t c_v = 0, c_a = 0, c_d = 0;
-  const uint64_t wave = pv.wave;
-  const uint64_t nwaves = pv.nwaves;
-  // the next item's id and mask are loaded while this one is processed
-  uint32_t it_next = wave < count ? S.items[base + wave] : 0u;
-  ull mask_next = wave < count ? S.imask[base + wave] : 0ull;
-  for (uint64_t i = wave; i < count; i += nwaves) {
+  const uint64_t step = pv.nwaves * (uint64_t)K;
+  uint64_t ii = pv.wave * (uint64_t)K + (uint64_t)(lane / SUB);  // this lane's item
+  // the next step's ids and masks are loaded while this one is processed
+  uint32_t it_next = ii < count ? S.items[base + ii] : 0u;
+  ull mask_next = ii < count ? S.imask[base + ii] : 0ull;
+  for (uint64_t i0 = pv.wave * (uint64_t)K; i0 < count; i0 += step, ii += step) {
     const uint32_t it = it_next;
     const ull mask = mask_next;
-    if (i + nwaves < count) {
-      it_next = S.items[base + i + nwaves];
-      mask_next = S.imask[base + i + nwaves];
+    if (ii + step < count) {
+      it_next = S.items[base + ii + step];
+      mask_next = S.imask[base + ii + step];
     }
     const uint32_t g = (uint32_t)(it / n);
     const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
     const uint64_t gbase = (uint64_t)g * n;
-    const int32_t tg = S.tgt_of[v];
-    const uint32_t tl = S.tlev[g * kLanes + lane];
-    const bool need = ((mask >> lane) & 1ull) && (full || (uint32_t)level > tl || tg >= 0);
-    const ull em = __ballot(need);
-    if (em == 0ull) continue;
-    const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    const ull sg = need ? S.sig[(uint64_t)it * kLanes + lane] : 1ull;
-    double acc = 0.0;
-    for (int64_t e = e0; e < e1; e += 64) {
-      const int64_t my = e + lane;
-      uint32_t w = 0;
-      ull d = 0ull;
-      if (my < e1) {
-        w = (uint32_t)G.col[my];
-        const LevMask t = bt_in[gbase + w];
-        const ull mw = (t.lev == (uint32_t)(level + 1) && t.epoch == E) ? t.mask : 0ull;
-        d = em & mw;
-      }
-      c_d += (uint64_t)__popcll(d);
-      ull bits = __ballot(d != 0ull);
-      while (bits != 0ull) {
-        int j[8];
-        int c = 0;
-        for (; c < 8 && bits != 0ull; ++c) {
-          j[c] = __ffsll((long long)bits) - 1;
-          bits &= bits - 1ull;
-        }
-        double x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          x[q] = 0.0;
-          if (q < c) {
-            const uint32_t wq = read_lane(w, j[q]);
-            const ull dq = read_lane64(d, j[q]);
-            if ((dq >> lane) & 1ull) x[q] = S.psi[(gbase + wq) * kLanes + lane];
-          }
-        }
-        // arc order is kept, and adding 0.0 for a lane off the DAG leaves acc unchanged
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc += x[q];
-      }
+    int32_t tg = -1;
+    int64_t e0 = 0, e1 = 0;
+    if (mask != 0ull) {
+      tg = S.tgt_of[v];
+      e0 = G.rp[v];
+      e1 = G.rp[v + 1];
     }
-    if (need) {
-      const double s = (double)sg;
-      const double dl = s * acc;
-      S.psi[(uint64_t)it * kLanes + lane] = acc + 1.0 / s;
-      if (S.dout) S.dout[(uint64_t)it * kLanes + lane] = dl;
-      if (tg >= 0 && tg < ntgt)
-        S.res[((uint64_t)tg * S.G + g) * kLanes + lane] = (level > 0) ? dl : 0.0;
+    // lanes of each item that need psi here, and their path counts
+    ull emv[K], my_em = 0ull;
+    ull sg[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int ld = t * SUB;
+      const ull mt = read_lane64(mask, ld);
+      emv[t] = 0ull;
+      sg[t] = 1ull;
+      if (mt == 0ull) continue;
+      const uint32_t gt = read_lane(g, ld);
+      const uint32_t tl = S.tlev[gt * kLanes + lane];
+      const bool need = ((mt >> lane) & 1ull) && (full || (uint32_t)level > tl || (int32_t)read_lane((uint32_t)tg, ld) >= 0);
+      emv[t] = __ballot(need);
+      if (need) sg[t] = S.sig[(uint64_t)read_lane(it, ld) * kLanes + lane];
     }
-    if (lane == 0) {
-      LevMask o;
-      o.mask = em;
-      o.lev = (uint32_t)level;
-      o.epoch = E;
-      bt_out[it] = o;
-      const uint64_t pc = (uint64_t)__popcll(em);
-      c_v += pc;
-      c_a += pc * (uint64_t)(e1 - e0);
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if (lane / SUB == t) my_em = emv[t];
+    // first chunk of every slot's out-arcs
+    const int64_t mo = e0 + sl;
+    uint32_t w = 0;
+    ull d = 0ull;
+    if (my_em != 0ull && mo < e1) {
+      w = (uint32_t)G.col[mo];
+      const LevMask tw = bt_in[gbase + w];
+      const ull mw = (tw.lev == (uint32_t)(level + 1) && tw.epoch == E) ? tw.mask : 0ull;
+      d = my_em & mw;
+    }
+    c_d += (uint64_t)__popcll(d);
+    double acc[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) acc[t] = 0.0;
+    push_sum_slots<K>(S, gbase, w, d, lane, acc);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const ull em = emv[t];
+      if (em == 0ull) continue;
+      const int ld = t * SUB;
+      const uint32_t itt = read_lane(it, ld);
+      const uint32_t gt = read_lane(g, ld);
+      const uint64_t gbt = read_lane64(gbase, ld);
+      const int64_t E0 = (int64_t)read_lane64((ull)e0, ld), E1 = (int64_t)read_lane64((ull)e1, ld);
+      // remaining out-arcs, 64 at a time, still in arc order
+      for (int64_t e = E0 + SUB; e < E1; e += kLanes) {
+        const int64_t my = e + lane;
+        uint32_t ww = 0;
+        ull dd = 0ull;
+        if (my < E1) {
+          ww = (uint32_t)G.col[my];
+          const LevMask tw = bt_in[gbt + ww];
+          const ull mw = (tw.lev == (uint32_t)(level + 1) && tw.epoch == E) ? tw.mask : 0ull;
+          dd = em & mw;
+        }
+        c_d += (uint64_t)__popcll(dd);
+        double a1[1] = {acc[t]};
+        push_sum_slots<1>(S, gbt, ww, dd, lane, a1);
+        acc[t] = a1[0];
+      }
+      const int32_t tgt = (int32_t)read_lane((uint32_t)tg, ld);
+      if ((em >> lane) & 1ull) {
+        const double s = (double)sg[t];
+        const double dl = s * acc[t];
+        S.psi[(uint64_t)itt * kLanes + lane] = acc[t] + 1.0 / s;
+        if (S.dout) S.dout[(uint64_t)itt * kLanes + lane] = dl;
+        if (tgt >= 0 && tgt < ntgt)
+          S.res[((uint64_t)tgt * S.G + gt) * kLanes + lane] = (level > 0) ? dl : 0.0;
+      }
+      if (lane == 0) {
+        LevMask o;
+        o.mask = em;
+        o.lev = (uint32_t)level;
+        o.epoch = E;
+        bt_out[itt] = o;
+        const uint64_t pc = (uint64_t)__popcll(em);
+        c_v += pc;
+        c_a += pc * (uint64_t)(E1 - E0);
+      }
     }
   }
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
@@ -852,9 +924,24 @@ hipError_t launch_fwd_level(const DevGraph &G, const BatchState &S, int level, L
   return hipGetLastError();
 }
 
+template <int K>
+static void launch_bwd_k(const DevGraph &G, const BatchState &S, int level, int ntgt, int full, const Launch &L,
+                         hipStream_t st) {
+  switch (L.block) {
+    case 64: k_bwd_level<64, K><<<dim3(L.grid), dim3(64), 0, st>>>(G, S, level, ntgt, full); break;
+    case 128: k_bwd_level<128, K><<<dim3(L.grid), dim3(128), 0, st>>>(G, S, level, ntgt, full); break;
+    case 512: k_bwd_level<512, K><<<dim3(L.grid), dim3(512), 0, st>>>(G, S, level, ntgt, full); break;
+    default: k_bwd_level<256, K><<<dim3(L.grid), dim3(256), 0, st>>>(G, S, level, ntgt, full); break;
+  }
+}
+
 hipError_t launch_bwd_level(const DevGraph &G, const BatchState &S, int level, int ntgt, int full, Launch L,
                             hipStream_t st) {
-  DISPATCH_BLOCK(L, k_bwd_level, G, S, level, ntgt, full);
+  switch (L.items) {
+    case 2: launch_bwd_k<2>(G, S, level, ntgt, full, L, st); break;
+    case 4: launch_bwd_k<4>(G, S, level, ntgt, full, L, st); break;
+    default: launch_bwd_k<1>(G, S, level, ntgt, full, L, st); break;
+  }
   return hipGetLastError();
 }
 
