@@ -176,7 +176,8 @@ def serve(G, g, args):
                 "distinct_sources_mean": float(np.mean([x["stats"]["distinct_sources"] for x in res]))}, te
     sat, te = run(0.0)
     log(f"[bench] serving saturation: {sat}")
-    out = {"workers": args.workers, "groups": groups, "hbm_budget_gib": args.hbm_budget, "saturation": sat}
+    out = {"workers": args.workers, "groups": groups, "hbm_budget_gib": args.hbm_budget,
+           "query_vertices": [int(v) for v in qs], "saturation": sat}
     for frac in (0.5, 0.9):
         r, _ = run(frac * sat["qps"])
         log(f"[bench] serving at {frac} x saturation: {r}")
@@ -195,7 +196,7 @@ def cpu_baseline(g, r, budget_s: float, threads: int):
     te = 0
     done = 0
     t0 = time.perf_counter()
-    chunk = 256
+    chunk = 4 * threads
     while time.perf_counter() - t0 < budget_s and done < rv.size:
         src = rv[order[done:done + chunk]]
         _, cnt = O.dependencies(g, r, src, threads=threads)
@@ -217,6 +218,10 @@ def main():
     ap.add_argument("--groups", type=int, default=0, help="64-source column groups per batch (0 = library default)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=0)
+    ap.add_argument("--items", type=int, default=0, help="frontier items per wavefront step (0 = library default)")
+    ap.add_argument("--bottom-up", type=int, default=-1,
+                    help="bottom-up threshold denominator for the unweighted forward (0 = off, -1 = library default)")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(cores, 16))")
     ap.add_argument("--plain-sources", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -247,6 +252,10 @@ def main():
         kw["block"] = args.block
     if args.grid_mult:
         kw["grid_mult"] = args.grid_mult
+    if args.items:
+        kw["items"] = args.items
+    if args.bottom_up >= 0:
+        kw["bottom_up"] = args.bottom_up
     cfg = G.set_config(engine=bcd.BCD_ENGINE_BATCHED, **kw)
     log(f"[bench] config groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult}")
 
@@ -269,6 +278,18 @@ def main():
             srv = serve(G, g, args)
             te, wall, lat = srv["saturation"]["gteps"] * 1e9 * srv["saturation"]["wall_s"], srv["saturation"]["wall_s"], [0]
             extra = {"serving": srv}
+        if not args.no_cpu:
+            # the oracle on a bounded sample of one query's sources: for the set,
+            # its largest RV; for serving, the first query vertex
+            if args.workload == "rmat18w":
+                rq = queries[0]
+            elif args.workload == "rmat20set":
+                rq = qs[int(np.argmax(sizes))]
+            else:
+                rq = srv["query_vertices"][0]
+            threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
+            extra["cpu_baseline"] = cpu_baseline(g, rq, args.cpu_budget, threads)
+            log(f"[bench] cpu baseline: {extra['cpu_baseline']}")
         cfg = G.config()
         print(json.dumps({"metric": "GTEPS for RV(r)-pruned BC(r) on one MI355X; p50/p99 query latency",
                           "value": round(te / wall / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
@@ -276,7 +297,8 @@ def main():
                           "latencies_s": [round(x, 4) for x in lat][:16],
                           "config": {"workload": wname, "n": g.n, "m": g.m,
                                      "groups": extra.get("serving", {}).get("groups", cfg.groups),
-                                     "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items},
+                                     "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items,
+                                     "bottom_up": cfg.bottom_up},
                           **extra}), flush=True)
         return
 
@@ -341,7 +363,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        threads = min(os.cpu_count() or 1, 16)
+        threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
         cpu = cpu_baseline(g, queries[0], args.cpu_budget, threads)
         log(f"[bench] cpu baseline: {cpu}")
 
@@ -367,7 +389,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "graph": g.name, "n": g.n, "m": g.m, "queries": [int(q) for q in queries],
                    "engine": "batched", "batch_width": 64 * cfg.groups, "block": cfg.block,
-                   "grid_mult": cfg.grid_mult, "items": cfg.items},
+                   "grid_mult": cfg.grid_mult, "items": cfg.items, "bottom_up": cfg.bottom_up},
         "p50_query_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_query_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "traversed_edges_per_step": te_total // args.steps,
