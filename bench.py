@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--bottom-up", type=int, default=-1,
                     help="bottom-up threshold denominator for the unweighted forward (0 = off, -1 = library default)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(cores, 16))")
+    ap.add_argument("--engine", choices=["auto", "batched", "lds", "plain"], default="auto",
+                    help="per-source engine (auto: the LDS engine for the ER 2k workload, else batched)")
     ap.add_argument("--plain-sources", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -256,7 +258,9 @@ def main():
         kw["items"] = args.items
     if args.bottom_up >= 0:
         kw["bottom_up"] = args.bottom_up
-    cfg = G.set_config(engine=bcd.BCD_ENGINE_BATCHED, **kw)
+    engines = {"batched": bcd.BCD_ENGINE_BATCHED, "lds": bcd.BCD_ENGINE_LDS, "plain": bcd.BCD_ENGINE_PLAIN}
+    ename = args.engine if args.engine != "auto" else ("lds" if args.workload == "er2000" else "batched")
+    cfg = G.set_config(engine=engines[ename], **kw)
     log(f"[bench] config groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult}")
 
     if args.workload in ("rmat18w", "rmat20set", "rmat22serve"):
@@ -335,7 +339,8 @@ def main():
     if not args.no_profile and fwd["launches"] > 0:
         dom, kind = (fwd, "forward") if fwd["total_ms"] >= bwd["total_ms"] else (bwd, "backward")
         achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
-        kname = f"k_{'fwd' if kind == 'forward' else 'bwd'}_level"
+        # the LDS engine runs both passes in one kernel, timed as the forward
+        kname = "k_lds_pass" if ename == "lds" else f"k_{'fwd' if kind == 'forward' else 'bwd'}_level"
         traffic = measured_traffic(kname, wname)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -355,7 +360,7 @@ def main():
         t = time.perf_counter()
         G.dependencies(r, src)
         dt = time.perf_counter() - t
-        G.set_config(engine=bcd.BCD_ENGINE_BATCHED)
+        G.set_config(engine=engines[ename])
         _, cnt = G.dependencies(r, src, counters=True)
         te_p = int(cnt[:, 1].sum())
         plain = {"gteps": round(te_p / dt / 1e9, 3), "sources": int(src.size), "query": int(r)}
@@ -388,7 +393,7 @@ def main():
         "dtype": "u64+f64",
         "data": "synthetic",
         "config": {"workload": wname, "graph": g.name, "n": g.n, "m": g.m, "queries": [int(q) for q in queries],
-                   "engine": "batched", "batch_width": 64 * cfg.groups, "block": cfg.block,
+                   "engine": ename, "batch_width": 64 * cfg.groups if ename == "batched" else 1, "block": cfg.block,
                    "grid_mult": cfg.grid_mult, "items": cfg.items, "bottom_up": cfg.bottom_up},
         "p50_query_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_query_ms": round(float(np.percentile(lat_ms, 99)), 3),

@@ -78,6 +78,9 @@ typedef struct bcd_stats {
 /* Engines for the per-source passes. */
 #define BCD_ENGINE_BATCHED 0 /* 64 sources per wavefront column group, many groups per launch */
 #define BCD_ENGINE_PLAIN 1   /* one source per launch, one launch per BFS level */
+#define BCD_ENGINE_LDS 2     /* small unweighted graphs: a workgroup runs a source's whole pass with its
+                                state in LDS (24 bytes per vertex must fit one workgroup's LDS, n < 2^16);
+                                other graphs return BCD_ERR_UNSUPPORTED.  The server always batches. */
 
 typedef struct bcd_config {
   int32_t engine;     /* BCD_ENGINE_* */

@@ -30,6 +30,7 @@ BCD_ERR_CANCELLED = 9
 
 BCD_ENGINE_BATCHED = 0
 BCD_ENGINE_PLAIN = 1
+BCD_ENGINE_LDS = 2
 
 BCD_EPS_ABSOLUTE = 1
 BCD_K_TRIVIAL = 2

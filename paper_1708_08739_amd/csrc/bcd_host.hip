@@ -43,7 +43,7 @@ static double now_s() {
 
 // ------------------------------------------------------------ device
 
-bcd_status device_check(int *cus) {
+bcd_status device_check(int *cus, size_t *lds_block_bytes) {
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev <= 0) return fail(BCD_ERR_DEVICE, "no HIP device available");
@@ -54,6 +54,7 @@ bcd_status device_check(int *cus) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(BCD_ERR_DEVICE, std::string("libbcd is built for gfx950; device is ") + prop.gcnArchName);
   if (cus) *cus = prop.multiProcessorCount;
+  if (lds_block_bytes) *lds_block_bytes = prop.sharedMemPerBlock;
   return BCD_OK;
 }
 
@@ -102,6 +103,10 @@ Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
   release_weighted();
+  if (lds_dev) (void)hipFree(lds_dev);
+  if (lds_host) (void)hipHostFree(lds_host);
+  lds_dev = lds_host = nullptr;
+  lds_dev_bytes = lds_host_bytes = 0;
   dfree(S.sig);
   dfree(S.psi);
   dfree(S.dout);
@@ -502,7 +507,8 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
     }
   }
   int cus = 0;
-  STCHK(device_check(&cus));
+  size_t lds_block = 0;
+  STCHK(device_check(&cus, &lds_block));
   std::unique_ptr<Graph> g(new (std::nothrow) Graph());
   if (!g) return fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed");
   g->n = n;
@@ -510,6 +516,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->weighted = weight != nullptr;
   g->max_w = (uint32_t)max_w;
   g->cus = cus;
+  g->lds_block_bytes = lds_block;
   g->h_rp.assign(row_ptr, row_ptr + n + 1);
   // transpose by counting sort: rows of R(G) come out sorted
   std::vector<int64_t> irp((size_t)n + 1, 0);
@@ -572,7 +579,7 @@ bcd_status bcd_graph_info(const bcd_graph *gh, int64_t *n, int64_t *m, int32_t *
 bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
   if (!gh || !cfg) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = reinterpret_cast<Graph *>(gh);
-  if (cfg->engine != BCD_ENGINE_BATCHED && cfg->engine != BCD_ENGINE_PLAIN)
+  if (cfg->engine != BCD_ENGINE_BATCHED && cfg->engine != BCD_ENGINE_PLAIN && cfg->engine != BCD_ENGINE_LDS)
     return fail(BCD_ERR_INVALID_ARG, "unknown engine");
   if (cfg->groups < 1 || (uint64_t)cfg->groups * (uint64_t)g->n >= (1ull << 32))
     return fail(BCD_ERR_INVALID_ARG, "groups must be >= 1 with groups * n < 2^32");

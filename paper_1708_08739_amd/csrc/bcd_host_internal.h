@@ -35,7 +35,7 @@ constexpr int kCntStage = (kLevelChunkMax + 2) * kMaxParts;  // pinned slots for
 
 bcd_status fail(bcd_status s, const std::string &msg);
 bcd_status hip_fail(hipError_t e, const char *what);
-bcd_status device_check(int *cus);
+bcd_status device_check(int *cus, size_t *lds_block_bytes = nullptr);
 
 inline int default_groups(int64_t n) {
   // keep the [G][n][64] path-count and psi arrays near 64 GiB (HBM is 288 GB),
@@ -83,6 +83,11 @@ struct Workspace {
   uint64_t *h_misc = nullptr;
   uint64_t *h_ctr = nullptr;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  // LDS engine scratch (bcd_lds.hip), grown on demand
+  void *lds_dev = nullptr;
+  size_t lds_dev_bytes = 0;
+  void *lds_host = nullptr;
+  size_t lds_host_bytes = 0;
 
   ~Workspace();
   void release();
@@ -115,6 +120,7 @@ struct Graph {
   bool weighted = false;
   uint32_t max_w = 1;
   int cus = 1;
+  size_t lds_block_bytes = 0;  // LDS one workgroup may allocate
   std::vector<int64_t> h_rp;
   int64_t *d_rp = nullptr;
   int32_t *d_col = nullptr;
@@ -170,6 +176,17 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
                         const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
 bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t k, uint64_t *dist,
                                       uint64_t *sigma, double *delta);
+// LDS engine (bcd_lds.hip): one workgroup per source at a time, state in LDS.
+size_t lds_bytes_for(int64_t n);
+bool lds_fits(const Graph *g);
+// Single-workgroup reachability (n < 2^16, visited bits and queue in LDS).
+bool lds_reach_fits(const Graph *g);
+hipError_t launch_lds_reach(const Graph *g, const int64_t *rp, const int32_t *col, int32_t root, uint32_t *bitmap,
+                            hipStream_t st);
+bcd_status run_lds(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
+                   bool want_counters, SourceRun &out);
+bcd_status multi_source_pass_lds(Graph *g, Workspace *ws, const int32_t *sources, int64_t k, uint64_t *dist,
+                                 uint64_t *sigma, double *delta);
 // One batch of `k` sources already staged in ws->h_items0 / h_masks0 with
 // ntgt targets installed in ws->S.tgt_of; per-lane target dependencies stay
 // in ws->S.res on the device; per-group overflow lanes go to ovl_out[G].

@@ -5,11 +5,12 @@
 //
 // Batched engine layout: a column group is 64 sources, one per wavefront
 // lane.  A frontier item is (group g, vertex v) with a 64-bit mask of the
-// lanes for which v sits on the current BFS level; one wavefront expands one
-// item, lane b working for source b, so the 64 path counts of v are one
-// coalesced 512-byte row.  Level masks per (g, v) are single 64-bit words,
-// so testing "has source b already settled w" for all 64 sources costs two
-// 8-byte loads per arc.
+// lanes for which v sits on the current BFS level; lane b works for source b,
+// so the 64 path counts of v are one coalesced 512-byte row.  The settled
+// lanes and the rotating level masks of (g, v) share one 64-byte record, so
+// testing "has source b already settled w" for all 64 sources reads one
+// line per arc.  A wavefront takes 1, 2 or 4 items per step (their first
+// arcs in separate slots of lanes) to keep several items' loads in flight.
 #include <algorithm>
 
 #include "bcd_device.h"

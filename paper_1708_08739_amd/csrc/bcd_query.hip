@@ -61,6 +61,17 @@ bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::v
   const int64_t *rp = reverse ? g->d_irp : g->d_rp;
   const int32_t *col = reverse ? g->d_icol : g->d_col;
   Launch L = g->launch();
+  if (!d_lev && lds_reach_fits(g)) {
+    // small graph: the whole traversal in one workgroup, one launch
+    HIPCHK(launch_lds_reach(g, rp, col, root, ws->bitmap, st));
+    HIPCHK(hipMemcpyAsync(ws->h_bitmap, ws->bitmap, words * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bits.assign(ws->h_bitmap, ws->h_bitmap + words);
+    int64_t c = 0;
+    for (size_t i = 0; i < words; ++i) c += __builtin_popcount(bits[i]);
+    *count = c - 1;
+    return BCD_OK;
+  }
   HIPCHK(hipMemsetAsync(ws->bitmap, 0, words * sizeof(uint32_t), st));
   HIPCHK(hipMemsetAsync(ws->rqn, 0, 2 * sizeof(uint32_t), st));
   HIPCHK(launch_reach_init(ws->bitmap, ws->rq[0], &ws->rqn[0], root, st));
@@ -615,6 +626,7 @@ bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned l
 
 bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
                        bool want_counters, SourceRun &out) {
+  if (g->config().engine == BCD_ENGINE_LDS) return run_lds(g, ws, src, tgt, want_counters, out);
   if (g->weighted) return run_weighted(g, ws, src, tgt, want_counters, out);
   if (g->config().engine == BCD_ENGINE_PLAIN) return run_plain(g, ws, src, tgt, want_counters, out);
   return run_batched(g, ws, src, tgt, want_counters, out);
@@ -876,6 +888,13 @@ bcd_status bcd_multi_source_pass(const bcd_graph *gh, const bcd_vid *sources, in
                                  uint64_t *sigma, double *delta) {
   if (!gh || !sources || k <= 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
+  if (g->config().engine == BCD_ENGINE_LDS) {
+    for (int64_t i = 0; i < k; ++i)
+      if (sources[i] < 0 || sources[i] >= g->n) return fail(BCD_ERR_INVALID_ARG, "source out of range");
+    Lease ls(g);
+    STCHK(lease_ws(g, ls));
+    return multi_source_pass_lds(g, ls.w.get(), sources, k, dist, sigma, delta);
+  }
   if (g->weighted) return multi_source_pass_weighted(g, sources, k, dist, sigma, delta);
   const bcd_config cfg = g->config();
   if (k > (int64_t)cfg.groups * kLanes) return fail(BCD_ERR_INVALID_ARG, "k exceeds the batch width");

@@ -49,6 +49,21 @@ def test_rv_matches_oracle(B, oracle):
         assert np.array_equal(got, want), r
 
 
+def test_rv_small_graphs_one_workgroup(B, oracle):
+    """Graphs below 2^16 vertices take the single-workgroup reachability
+    kernel; RV(r) and the sampled bound's forward reach (through K) match."""
+    cases = [(gg.er_2000()[0], None), (gg.rmat(12, 8, seed=31), None), (gg.directed_path(7), None),
+             (gg.Digraph(1, np.array([0, 0]), np.zeros(0, dtype=np.int32)), None)]
+    for g, _ in cases:
+        G = dev(B, g)
+        for r in sorted(set([0, g.n - 1] + gg.uniform_vertices(g.n, min(5, g.n), seed=2))):
+            assert np.array_equal(G.rv(r), oracle.rv(g, r)), (g.name, r)
+            # the reverse pass of RV and the forward pass of #FR both feed the sampled call
+            got, st = G.bc_sampled(r, eps=0.2, seed=5)
+            if st["rv_size"] > 0:  # #FR is only computed when there are sources to draw
+                assert st["fr_size"] == oracle.fr_count(g, r), (g.name, r)
+
+
 def test_rv_buffer_too_small(B):
     import ctypes as C
     g = gg.directed_path(10)
@@ -72,10 +87,10 @@ SMALL = [
 
 
 @pytest.mark.parametrize("name,make", SMALL)
-@pytest.mark.parametrize("engine", ["batched", "plain"])
+@pytest.mark.parametrize("engine", ["batched", "plain", "lds"])
 def test_source_pass_bitexact(B, oracle, name, make, engine):
     g = make()
-    G = dev(B, g, engine=B.BCD_ENGINE_PLAIN if engine == "plain" else B.BCD_ENGINE_BATCHED)
+    G = dev(B, g, engine={"plain": B.BCD_ENGINE_PLAIN, "lds": B.BCD_ENGINE_LDS}.get(engine, B.BCD_ENGINE_BATCHED))
     for s in sorted(set([0, g.n - 1] + gg.uniform_vertices(g.n, min(6, g.n - 2), seed=4, exclude=[0, g.n - 1]))):
         print(name, engine, "s", s, flush=True)
         d, sg, dl = G.source_pass(s)
@@ -100,6 +115,11 @@ def test_multi_source_pass_groups(B, oracle, k):
             od, osg, odl, ovf, _ = want[i]
             assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (k, items, i, s)
             assert close(dl[i], odl), (k, items, i, s)
+    d, sg, dl = dev(B, g, engine=B.BCD_ENGINE_LDS).multi_source_pass(src)
+    for i, s in enumerate(src):
+        od, osg, odl, ovf, _ = want[i]
+        assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), ("lds", k, i, s)
+        assert close(dl[i], odl), ("lds", k, i, s)
 
 
 def test_partition_count_changes_between_batches(B, oracle):
@@ -122,7 +142,7 @@ def test_counters_match_oracle(B, oracle):
     g = gg.rmat(10, 8, seed=3)
     r = gg.top_out_degree(g, 1)[0]
     src = oracle.rv(g, r)[:20]
-    for engine in (B.BCD_ENGINE_BATCHED, B.BCD_ENGINE_PLAIN):
+    for engine in (B.BCD_ENGINE_BATCHED, B.BCD_ENGINE_PLAIN, B.BCD_ENGINE_LDS):
         G = dev(B, g, engine=engine)
         dep, cnt = G.dependencies(r, src, counters=True)
         odep, ocnt = oracle.dependencies(g, r, src)
@@ -146,6 +166,7 @@ def test_bc_exact_er2000_both_engines(B, oracle):
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=5, bottom_up=4096, items=1),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=7, bottom_up=4096, items=4, block=512),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=2, bottom_up=2, items=2),
+                dict(engine=B.BCD_ENGINE_LDS),
                 dict(engine=B.BCD_ENGINE_PLAIN)]:
         print("er2000", cfg, flush=True)
         G = dev(B, g, **cfg)
@@ -156,7 +177,7 @@ def test_bc_exact_er2000_both_engines(B, oracle):
         assert st["reached"] == ost["reached"] and st["dag_arcs"] == ost["dag_arcs"]
         vals.append(got)
     # batched results do not depend on the batch width, the items per step or
-    # the direction of the level scans
+    # the direction of the level scans, and the LDS engine gives the same bits
     assert all(v == vals[0] for v in vals[:-1])
 
 
@@ -215,7 +236,7 @@ def test_sigma_overflow(B, oracle):
     g64, ids64 = gg.diamond_chain(64)
     for cfg in (dict(engine=B.BCD_ENGINE_BATCHED, items=1), dict(engine=B.BCD_ENGINE_BATCHED, items=2),
                 dict(engine=B.BCD_ENGINE_BATCHED, items=4), dict(engine=B.BCD_ENGINE_BATCHED, bottom_up=4096),
-                dict(engine=B.BCD_ENGINE_PLAIN)):
+                dict(engine=B.BCD_ENGINE_PLAIN), dict(engine=B.BCD_ENGINE_LDS)):
         G = dev(B, g64, **cfg)
         with pytest.raises(B.BcdError) as e:
             G.bc_exact(ids64["x"][40])
@@ -232,14 +253,16 @@ def test_sigma_overflow(B, oracle):
             assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (items, s)
             assert close(dl[i], odl), (items, s)
     assert int(want[0][1][ids40["x"][40]]) == 1 << 40
-    G = dev(B, gg.grid_right_down(35, 35))
-    with pytest.raises(B.BcdError) as e:
-        G.source_pass(0)
-    assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW
-    G = dev(B, gg.grid_right_down(34, 34))
-    d, sg, _ = G.source_pass(0)
     import math
-    assert int(sg[33 * 34 + 33]) == math.comb(66, 33)
+    for engine in (B.BCD_ENGINE_BATCHED, B.BCD_ENGINE_LDS):
+        G = dev(B, gg.grid_right_down(35, 35), engine=engine)
+        with pytest.raises(B.BcdError) as e:
+            G.source_pass(0)
+        assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW
+        G = dev(B, gg.grid_right_down(34, 34), engine=engine)
+        d, sg, _ = G.source_pass(0)
+        assert int(sg[33 * 34 + 33]) == math.comb(66, 33)
+    assert dev(B, g, engine=B.BCD_ENGINE_LDS).bc_exact(ids["x"][31])[0] == 9 * 31 * 32
 
 
 def test_bc_set_and_identity(B, oracle):
@@ -257,6 +280,32 @@ def test_bc_set_and_identity(B, oracle):
     allbc, _ = G2.bc_set(list(range(g2.n)))
     obc, _ = oracle.bc_set(g2, list(range(g2.n)))
     assert close(allbc, obc)
+
+
+def test_lds_engine_queries_and_limits(B, oracle):
+    """The LDS engine through the query calls (exact, set, sampled) gives the
+    batched engine's values bit for bit; graphs it cannot hold are refused."""
+    g = gg.rmat(10, 8, seed=23)
+    rs = gg.queries_top_and_random(g, seed=9, top=3, rnd=4)
+    Gb = dev(B, g)
+    Gl = dev(B, g, engine=B.BCD_ENGINE_LDS)
+    sb, stb = Gb.bc_set(rs)
+    sl, stl = Gl.bc_set(rs)
+    assert np.array_equal(sl, sb) and stl["traversed_edges"] == stb["traversed_edges"]
+    assert close(sl, oracle.bc_set(g, rs)[0])
+    for r in rs[:3]:
+        assert Gl.bc_exact(r)[0] == Gb.bc_exact(r)[0]
+        assert Gl.bc_sampled(r, eps=0.05, seed=3)[0] == Gb.bc_sampled(r, eps=0.05, seed=3)[0]
+
+    def with_rv(gx):
+        ind, outd = gx.in_degree(), gx.out_degree()
+        return next(v for v in gg.top_out_degree(gx, 50) if ind[v] > 0 and outd[v] > 0)
+
+    for gx in (gg.with_weights(gg.erdos_renyi(300, 1500, seed=9), seed=19, max_weight=7), gg.rmat16()[0]):
+        Gx = dev(B, gx, engine=B.BCD_ENGINE_LDS)
+        with pytest.raises(B.BcdError) as e:
+            Gx.bc_exact(with_rv(gx))
+        assert e.value.code == B.BCD_ERR_UNSUPPORTED
 
 
 def test_bc_sampled_matches_oracle(B, oracle):
