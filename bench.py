@@ -6,7 +6,10 @@ Default workload (one step): directed R-MAT scale 16, edge factor 8
 self-loops dropped), unweighted; the 8 query vertices are the 4 of largest
 out-degree plus 4 seeded uniform ones; each query is an exact BC(r) call
 (Alg.1) through the C ABI with the batched engine.  The graph is resident
-in HBM before timing starts.
+in HBM before timing starts.  Other workloads (--workload): er2000 (ER
+n=2,000, m=10,000, one exact query; LDS engine), rmat18w (weighted R-MAT
+18), rmat20set (set of 64 vertices on R-MAT 20), rmat22serve (sampled
+queries through the server on R-MAT 22).
 
 value = whole-job GTEPS = sum over queries of traversed arcs (sum of m_s
 over the sources in RV(r)) / wall time of the K timed steps.

@@ -22,7 +22,6 @@ namespace bcd {
 // Level 0: each item is (g, source vertex) with the lanes it is the source
 // of; sigma = 1 on those lanes.
 __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *masks0, const uint32_t *dest0, int k) {
-  const size_t GN = (size_t)S.G * (size_t)S.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     const uint32_t it = items0[i];
     const ull m = masks0[i];
@@ -33,14 +32,15 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
   }
   // level-0 item-list base of every partition of this batch
   if (blockIdx.x == 0 && threadIdx.x < (unsigned)S.P) S.off[threadIdx.x] = (uint64_t)threadIdx.x * S.capP;
-  (void)GN;
 }
 
 // Sum of sigma_b(u) over the in-arcs held by one chunk of lanes whose tail u
 // is on the previous level for lane b (pm = lanes of that arc).  The chunk
 // holds the arcs of up to K items, 64 / K lanes each (arc lane l belongs to
 // the item of slot l / (64 / K), whose group base is in lane l's gbase), and
-// an arc adds into its item's accumulator.  Row loads of up to eight
+// an arc adds into its item's accumulator.  With HIT, hit[t] is also set on
+// every lane that received a count for item t (the bottom-up kernel's test
+// of which lanes reached the level).  Row loads of up to eight
 // predecessors are issued before any of them is consumed; the sums are
 // exact integers, so the order of the adds does not matter, and an
 // unsigned wrap on any add means the true sum exceeds 2^64 - 1.
@@ -145,6 +145,9 @@ static __device__ __forceinline__ void append_chunk(const BatchState &S, uint32_
 // (level+1, being built), prv (level-1, read by the pull) and old (level-2,
 // retired here).  vis lags: the owner of (g, v) ORs cur into vis during this
 // launch, so a reader sees vis | cur, which is the same union either way.
+// With bottom-up levels enabled, step 1 is skipped when the level was found
+// by k_bu_level (which pulled the counts), and step 2 when level+1 will be;
+// the item masks are recorded for the backward either way.
 template <int BLOCK, int K>
 __global__ __launch_bounds__(BLOCK) void k_fwd_level(DevGraph G, BatchState S, int level) {
   constexpr int SUB = kLanes / K;
