@@ -138,10 +138,11 @@ def serve(G, g, args):
     pool = [v for v in gg.uniform_vertices(g.n, 20 * args.queries, seed=105) if ind[v] > 0 and outd[v] > 0]
     qs = pool[: args.queries]
 
-    # largest group count whose workspaces fit in three quarters of the budget
+    # largest group count whose workspaces fit in 85 % of the budget (the rest
+    # holds the queries' result buffers)
     budget = args.hbm_budget << 30
     groups = G.config().groups
-    while groups > 1 and bcd.Server.workspace_bytes(G, groups, args.workers) > budget * 3 // 4:
+    while groups > 1 and bcd.Server.workspace_bytes(G, groups, args.workers) > budget * 85 // 100:
         groups //= 2
     log(f"[bench] serving: {args.workers} workers x {groups} groups, budget {args.hbm_budget} GiB")
 
@@ -234,7 +235,7 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--queries", type=int, default=64, help="serving: number of sampled queries")
     ap.add_argument("--workers", type=int, default=2, help="serving: concurrent batches")
-    ap.add_argument("--hbm-budget", type=int, default=192, help="serving: HBM budget in GiB")
+    ap.add_argument("--hbm-budget", type=int, default=240, help="serving: HBM budget in GiB (288 GB on the GPU)")
     ap.add_argument("--set-size", type=int, default=64)
     ap.add_argument("--probe-bw", action="store_true",
                     help="also run the library's streaming-copy probe (1 GiB copied, known traffic)")

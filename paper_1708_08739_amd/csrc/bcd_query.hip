@@ -178,10 +178,25 @@ bcd_status source_order(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   if (src.size() <= (size_t)kLanes || g->n < 4096) return BCD_OK;
   STCHK(ensure_landmarks(g, ws));
   const uint8_t *sig = g->lm_sig.data();
-  std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
-    const int c = std::memcmp(sig + (size_t)src[a] * kLandmarks, sig + (size_t)src[b] * kLandmarks, kLandmarks);
-    return c != 0 ? c < 0 : src[a] < src[b];
-  });
+  const size_t ns = src.size();
+  // ties keep ascending source order: start from it (the lists are usually
+  // ascending already), then a stable LSD radix sort over the signature
+  // bytes, last byte first, gives the lexicographic signature order
+  if (!std::is_sorted(src.begin(), src.end()))
+    std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return src[a] < src[b]; });
+  std::vector<uint8_t> key(ns * kLandmarks);  // by position in src, contiguous
+  for (size_t i = 0; i < ns; ++i) std::memcpy(&key[i * kLandmarks], sig + (size_t)src[i] * kLandmarks, kLandmarks);
+  std::vector<uint32_t> tmp(ns);
+  for (int byte = kLandmarks - 1; byte >= 0; --byte) {
+    size_t cnt[257] = {0};
+    for (size_t i = 0; i < ns; ++i) ++cnt[(size_t)key[(size_t)ord[i] * kLandmarks + byte] + 1];
+    bool constant = false;  // every key has the same byte here: the pass is the identity
+    for (int d = 1; d <= 256; ++d) constant = constant || cnt[d] == ns;
+    if (constant) continue;
+    for (int d = 1; d <= 256; ++d) cnt[d] += cnt[d - 1];
+    for (size_t i = 0; i < ns; ++i) tmp[cnt[key[(size_t)ord[i] * kLandmarks + byte]]++] = ord[i];
+    ord.swap(tmp);
+  }
   return BCD_OK;
 }
 
