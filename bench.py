@@ -9,7 +9,8 @@ out-degree plus 4 seeded uniform ones; each query is an exact BC(r) call
 in HBM before timing starts.  Other workloads (--workload): er2000 (ER
 n=2,000, m=10,000, one exact query; LDS engine), rmat18w (weighted R-MAT
 18), rmat20set (set of 64 vertices on R-MAT 20), rmat22serve (sampled
-queries through the server on R-MAT 22).
+queries through the server on R-MAT 22), rmat16bcd (the paper's BCD
+procedure and the unpruned sampling baseline on R-MAT 16, per query).
 
 value = whole-job GTEPS = sum over queries of traversed arcs (sum of m_s
 over the sources in RV(r)) / wall time of the K timed steps.
@@ -88,6 +89,9 @@ def workload(name: str):
         return gg.rmat20(), None, "rmat20_ef16_set64_exact"
     if name == "rmat22serve":
         return gg.rmat22(), None, "rmat22_ef16_serving_sampled"
+    if name == "rmat16bcd":
+        g, _ = gg.rmat16()
+        return g, None, "rmat16_ef8_bcd_procedure_64queries"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -189,6 +193,62 @@ def serve(G, g, args):
     return out
 
 
+def bcd_procedure(G, g, args):
+    """The paper's experimental procedure (Section 5) on R-MAT 16: for 64
+    seeded query vertices with in- and out-arcs, BCD with tau = 1000 (exact
+    when |RV(r)| <= tau, else A-BCD with T = tau), reporting t_RV, t, exact or
+    not, and Error% = |BCD - BC| / BC x 100 against the exact value (Eq.(9));
+    then, at equal eps = 0.01 (normalised) and delta = 0.1, A-BCD drawing
+    from RV(r) against the unpruned baseline drawing from V (sample count
+    from Eq.(8) with n - 1 in place of |RV(r)|)."""
+    from paper_1708_08739_amd import bcd, graphgen as gg
+    ind, outd = g.in_degree(), g.out_degree()
+    pool = [v for v in gg.uniform_vertices(g.n, 40 * args.queries, seed=106) if ind[v] > 0 and outd[v] > 0]
+    qs = pool[: args.queries]
+    rows = []
+    te_bcd = 0
+    t_bcd = 0.0
+    for i, r in enumerate(qs):
+        exact, _ = G.bc_exact(r)
+        t0 = time.perf_counter()
+        v, st = G.bc_bcd(r, tau=1000, seed=1000 + i)
+        dt = time.perf_counter() - t0
+        te_bcd += st["traversed_edges"]
+        t_bcd += dt
+        err = abs(v - exact) / exact * 100.0 if exact != 0 else (0.0 if v == 0 else float("inf"))
+        row = {"r": int(r), "rv": int(st["rv_size"]), "exact": bool(st["ran_exact"]), "t_rv_ms": round(st["t_rv_s"] * 1e3, 3),
+               "t_ms": round(st["t_bc_s"] * 1e3, 3), "error_pct": round(err, 4)}
+        if st["rv_size"] > 1000:
+            # equal eps, delta: pruned draws from RV(r), unpruned from V
+            a, sa = G.bc_sampled(r, eps=0.01, delta=0.1, seed=2000 + i, flags=bcd.BCD_NO_EXACT_FALLBACK)
+            b, sb = G.bc_sampled(r, eps=0.01, delta=0.1, seed=2000 + i, flags=bcd.BCD_SAMPLE_ALL_VERTICES)
+            row["pruned"] = {"T": int(sa["samples"]), "t_ms": round(sa["t_bc_s"] * 1e3, 3),
+                             "error_pct": round(abs(a - exact) / exact * 100.0, 4) if exact else None}
+            row["unpruned"] = {"T": int(sb["samples"]), "t_ms": round(sb["t_bc_s"] * 1e3, 3),
+                               "error_pct": round(abs(b - exact) / exact * 100.0, 4) if exact else None}
+        rows.append(row)
+        log(f"[bench] bcd query {i + 1}/{len(qs)}: {row}")
+    ex = [x for x in rows if x["exact"]]
+    ap_ = [x for x in rows if not x["exact"]]
+    big = [x for x in rows if "pruned" in x]
+    summary = {
+        "queries": len(rows), "pct_exact": round(100.0 * len(ex) / max(len(rows), 1), 2),
+        "mean_error_pct_sampled": round(float(np.mean([x["error_pct"] for x in ap_])), 4) if ap_ else None,
+        "max_error_pct_sampled": round(float(np.max([x["error_pct"] for x in ap_])), 4) if ap_ else None,
+        "mean_t_rv_ms": round(float(np.mean([x["t_rv_ms"] for x in rows])), 3),
+        "mean_t_ms": round(float(np.mean([x["t_ms"] for x in rows])), 3),
+        "pruned_vs_unpruned": {
+            "mean_T": [round(float(np.mean([x["pruned"]["T"] for x in big])), 1),
+                       round(float(np.mean([x["unpruned"]["T"] for x in big])), 1)] if big else None,
+            "mean_t_ms": [round(float(np.mean([x["pruned"]["t_ms"] for x in big])), 3),
+                          round(float(np.mean([x["unpruned"]["t_ms"] for x in big])), 3)] if big else None,
+            "mean_error_pct": [round(float(np.mean([x["pruned"]["error_pct"] for x in big])), 4),
+                               round(float(np.mean([x["unpruned"]["error_pct"] for x in big])), 4)] if big else None,
+        },
+    }
+    return te_bcd, t_bcd, summary, rows
+
+
 def cpu_baseline(g, r, budget_s: float, threads: int):
     """The oracle as it stands, on a bounded sample of the same work: the
     per-source passes of seeded sources of RV(r), in chunks until about
@@ -267,7 +327,7 @@ def main():
     cfg = G.set_config(engine=engines[ename], **kw)
     log(f"[bench] config groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult}")
 
-    if args.workload in ("rmat18w", "rmat20set", "rmat22serve"):
+    if args.workload in ("rmat18w", "rmat20set", "rmat22serve", "rmat16bcd"):
         extra = {}
         if args.workload == "rmat18w":
             te, wall, lat = run_weighted(G, g, queries, args)
@@ -282,6 +342,10 @@ def main():
             wall = time.perf_counter() - t0
             te, lat = st["traversed_edges"], [wall]
             extra = {"set_size": len(qs), "rv_sizes": sizes, "distinct_sources": st["distinct_sources"]}
+        elif args.workload == "rmat16bcd":
+            te, wall, summary, rows = bcd_procedure(G, g, args)
+            lat = [x["t_ms"] / 1e3 for x in rows]
+            extra = {"bcd_procedure": summary, "per_query": rows}
         else:
             srv = serve(G, g, args)
             te, wall, lat = srv["saturation"]["gteps"] * 1e9 * srv["saturation"]["wall_s"], srv["saturation"]["wall_s"], [0]
@@ -293,6 +357,8 @@ def main():
                 rq = queries[0]
             elif args.workload == "rmat20set":
                 rq = qs[int(np.argmax(sizes))]
+            elif args.workload == "rmat16bcd":
+                rq = max(rows, key=lambda x: x["rv"])["r"]
             else:
                 rq = srv["query_vertices"][0]
             threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
