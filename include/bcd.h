@@ -141,14 +141,17 @@ bcd_status bcd_graph_info(const bcd_graph *g, int64_t *n, int64_t *m, int32_t *w
 bcd_status bcd_set_config(bcd_graph *g, const bcd_config *cfg);
 bcd_status bcd_get_config(const bcd_graph *g, bcd_config *cfg);
 
-/* Autotuner for the batched engine: times the per-source passes of a fixed
- * seeded sample of RV(r) (at most max_sources sources) under each candidate
- * (groups in {1,2,4,...,max_groups}, block in {256,512}, grid_mult in
- * {4,8,16}), keeps the configuration with the highest traversed arcs per
- * second, installs it on the graph and returns it in *best (and its rate in
- * *gteps, may be NULL).  Results of later calls do not depend on the choice
- * (batch composition never changes a per-source value).  Errors:
- * INVALID_ARG (r out of range, RV(r) empty, max_groups < 1). */
+/* Autotuner: times the per-source passes of a fixed seeded sample of RV(r)
+ * (at most max_sources sources) under each candidate and keeps the one with
+ * the highest traversed arcs per second: first the batched engine with
+ * groups in {1,2,4,...,max_groups} x grid_mult in {8,16,32} (block 256, 2
+ * items per step, top-down), then around the best block 512 and, on
+ * unweighted graphs, items 1 and 4 and bottom-up levels (16, 4), then the
+ * LDS engine when the graph fits it.  Installs the choice on the graph and
+ * returns it in *best (and its rate in *gteps, may be NULL).  Results of
+ * later calls do not depend on the choice (every engine and setting gives
+ * the same per-source values).  Errors: INVALID_ARG (r out of range, RV(r)
+ * empty, max_groups < 1). */
 bcd_status bcd_autotune(bcd_graph *g, bcd_vid r, int32_t max_groups, int64_t max_sources, bcd_config *best,
                         double *gteps);
 

@@ -181,6 +181,29 @@ def test_bc_exact_er2000_both_engines(B, oracle):
     assert all(v == vals[0] for v in vals[:-1])
 
 
+def test_autotune_installs_choice_and_keeps_values(B, oracle):
+    """The autotuner times engines and settings on a sample of RV(r), installs
+    the fastest, and no choice changes a value: BC before and after are equal
+    bit for bit (unweighted, where the LDS engine competes, and weighted)."""
+    cases = [(gg.er_2000()[0], gg.er_2000()[1][0]),
+             (gg.rmat(11, 8, seed=41, weighted=True, max_weight=9), None)]
+    for g, r in cases:
+        if r is None:
+            r = gg.top_out_degree(g, 1)[0]
+        G = dev(B, g)
+        before, _ = G.bc_exact(r)
+        cfg, rate = G.autotune(r, max_groups=4, max_sources=512)
+        print("autotune", g.name, cfg.engine, cfg.groups, cfg.block, cfg.grid_mult, cfg.items, cfg.bottom_up, rate,
+              flush=True)
+        assert rate > 0
+        now = G.config()
+        assert (now.engine, now.groups, now.block, now.grid_mult, now.items, now.bottom_up) == \
+            (cfg.engine, cfg.groups, cfg.block, cfg.grid_mult, cfg.items, cfg.bottom_up)
+        after, _ = G.bc_exact(r)
+        assert after == before
+        assert close(after, oracle.bc_exact(g, r)[0])
+
+
 def test_bc_exact_repeatable(B):
     g = gg.rmat(12, 8, seed=8)
     G = dev(B, g)
