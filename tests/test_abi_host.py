@@ -4,6 +4,8 @@ device is touched behaves as documented."""
 import ctypes as C
 import os
 import re
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -123,3 +125,13 @@ def test_valid_graph_without_device_reports_device_error():
     g = gg.directed_path(5)
     rc, h = _load(g.n, g.m, g.row_ptr, g.col)
     assert rc == bcd.BCD_ERR_DEVICE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before
+    touching a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
