@@ -97,6 +97,19 @@ static __device__ __forceinline__ void stage_one(uint32_t *buf, int &nbuf, bool 
   nbuf += 1;
 }
 
+// Append the value of every lane where `pred` holds (lane order kept).
+template <int CAP>
+static __device__ __forceinline__ void stage_lanes(uint32_t *buf, int &nbuf, bool pred, uint32_t value, uint32_t *tail,
+                                                   uint32_t *dst, uint64_t dst_base, uint64_t dst_end,
+                                                   uint32_t *overflow_flag) {
+  const ull m = __ballot(pred);
+  if (m == 0ull) return;
+  const int c = __popcll(m);
+  if (nbuf + c > CAP) stage_flush(buf, nbuf, tail, dst, dst_base, dst_end, overflow_flag);
+  if (pred) buf[nbuf + lanes_below(m)] = value;
+  nbuf += c;
+}
+
 // This workgroup's share of a partitioned item list (see BatchState).
 struct PartView {
   int p;              // partition served

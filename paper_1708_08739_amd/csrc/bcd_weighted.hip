@@ -102,6 +102,10 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) dw[q] = (q < c && live) ? S.wd[(gbase + wq[q]) * kLanes + lane] : 0u;
+      // lane q takes the flags of arc q of the chunk, so the eight arcs'
+      // flag atomics are in flight together
+      ull my_im = 0ull;
+      uint32_t my_w = 0u;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         if (q >= c) break;
@@ -113,18 +117,18 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
           __hip_atomic_fetch_min(&S.wd[(gbase + wq[q]) * kLanes + lane], nd[q], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
         const ull im = __ballot(imp);
-        if (im != 0ull) {
-          bool fq = false, fr = false;
-          if (lane == 0) {
-            fq = atomicOr(&cnxt[gbase + wq[q]], im) == 0ull;
-            fr = atomicOr(&S.vis[gbase + wq[q]], im) == 0ull;
-          }
-          fq = __builtin_amdgcn_readfirstlane((int)fq) != 0;
-          fr = __builtin_amdgcn_readfirstlane((int)fr) != 0;
-          stage_one<kCap>(qst, nq, fq, (uint32_t)(gbase + wq[q]), qout_n, qout, 0, GN, nullptr);
-          stage_one<kCap>(rst, nr, fr, (uint32_t)(gbase + wq[q]), S.rln, S.rl, 0, GN, nullptr);
+        if (lane == q) {
+          my_im = im;
+          my_w = wq[q];
         }
       }
+      bool fq = false, fr = false;
+      if (my_im != 0ull) {
+        fq = atomicOr(&cnxt[gbase + my_w], my_im) == 0ull;
+        fr = atomicOr(&S.vis[gbase + my_w], my_im) == 0ull;
+      }
+      stage_lanes<kCap>(qst, nq, fq, (uint32_t)(gbase + my_w), qout_n, qout, 0, GN, nullptr);
+      stage_lanes<kCap>(rst, nr, fr, (uint32_t)(gbase + my_w), S.rln, S.rl, 0, GN, nullptr);
     }
   }
   stage_flush(qst, nq, qout_n, qout, 0, GN, nullptr);
@@ -255,6 +259,10 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
           co[q] = atomicSub(&S.wc[row], 1u);
         }
       }
+      // lane q takes the ready flags of arc q's head, so the chunk's flag
+      // atomics are in flight together
+      ull my_rm = 0ull;
+      uint32_t my_w = 0u;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         if (q >= c) break;
@@ -264,13 +272,14 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
           atomicOr(&S.ovl[g], 1ull << lane);
         }
         const ull rm = __ballot(dag && co[q] == 1u);
-        if (rm != 0ull) {
-          bool first = false;
-          if (lane == 0) first = atomicOr(&nxt[gbase + wq[q]], rm) == 0ull;
-          first = __builtin_amdgcn_readfirstlane((int)first) != 0;
-          stage_one<kCap>(stg, nst, first, (uint32_t)(gbase + wq[q]), next_cnt, S.items, nbase, rend, &S.flags[1]);
+        if (lane == q) {
+          my_rm = rm;
+          my_w = wq[q];
         }
       }
+      bool first = false;
+      if (my_rm != 0ull) first = atomicOr(&nxt[gbase + my_w], my_rm) == 0ull;
+      stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + my_w), next_cnt, S.items, nbase, rend, &S.flags[1]);
     }
   }
   stage_flush(stg, nst, next_cnt, S.items, nbase, rend, &S.flags[1]);
