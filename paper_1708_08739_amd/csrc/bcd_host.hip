@@ -405,6 +405,15 @@ bcd_config Graph::config() const {
   return cfg;
 }
 
+void Graph::trim_pool() {
+  std::vector<std::unique_ptr<Workspace>> idle;
+  {
+    std::lock_guard<std::mutex> lk(pool_mu);
+    idle.swap(pool);
+  }
+  // destroyed here, outside the lock
+}
+
 std::unique_ptr<Workspace> Graph::acquire() {
   {
     std::lock_guard<std::mutex> lk(pool_mu);

@@ -146,6 +146,7 @@ struct Graph {
   bcd_config config() const;
   std::unique_ptr<Workspace> acquire();
   void release(std::unique_ptr<Workspace> w);
+  void trim_pool();  // free the device memory of idle pooled workspaces
   void add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
                    uint64_t items = 0);
   int64_t outdeg(int64_t v) const { return h_rp[(size_t)v + 1] - h_rp[(size_t)v]; }
@@ -176,6 +177,8 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
                         const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out);
 bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t k, uint64_t *dist,
                                       uint64_t *sigma, double *delta);
+// Device bytes of one batch workspace of `groups` column groups (bcd_server.hip).
+uint64_t batch_workspace_bytes(const Graph *g, int groups);
 // LDS engine (bcd_lds.hip): one workgroup per source at a time, state in LDS.
 size_t lds_bytes_for(int64_t n);
 bool lds_fits(const Graph *g);

@@ -1,6 +1,8 @@
 // libbcd query layer: RV(r), batches of per-source passes, and the ABI
 // calls built on them (Alg.1, the set form of Section 4.2, Alg.2, and the
 // verification hooks).
+#include <memory>
+#include <thread>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -430,6 +432,38 @@ static void add_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr) {
   g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb, p.items[1]);
 }
 
+// The batches b = first, first + stride, ... of the ordered source list on
+// one workspace (the targets installed there); each source's dependencies
+// go to its own position in dep, so stripes on different workspaces never
+// write the same element.
+static bcd_status run_batch_stripe(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
+                                   const std::vector<uint32_t> &ord, const std::vector<int32_t> &tgt, size_t first,
+                                   size_t stride, std::vector<double> &dep, ProfAcc &prof, bool &ovf) {
+  const int ntgt = (int)tgt.size();
+  const size_t G64 = (size_t)ws->G * kLanes;
+  const size_t ns = src.size();
+  TargetMap tm;
+  STCHK(tm.install(ws, tgt));
+  std::vector<int32_t> bsrc(G64);
+  for (size_t b0 = first * G64; b0 < ns; b0 += stride * G64) {
+    const int k = (int)std::min(G64, ns - b0);
+    for (int i = 0; i < k; ++i) bsrc[(size_t)i] = src[ord[b0 + i]];
+    ws->stage_sources(bsrc.data(), k);
+    STCHK(run_one_batch(g, ws, k, ntgt, false, nullptr, &prof, &ovf));
+    for (int i = 0; i < k; ++i)
+      for (int t = 0; t < ntgt; ++t) dep[(size_t)ord[b0 + i] * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
+  }
+  return BCD_OK;
+}
+
+// A second workspace runs every other batch on its own stream from a helper
+// thread, so one batch's host steps (result copy, staging, the level-count
+// checks) and its small tail levels overlap the other's kernels.  It is taken
+// from the graph's pool if one is there with the same width, else allocated
+// only when HBM keeps kPipelineHeadroom free beside it (the pair then stays
+// pooled with the graph; a server releases idle pooled workspaces).
+constexpr uint64_t kPipelineHeadroom = 16ull << 30;
+
 static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
                               const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out) {
   const bcd_config cfg = g->config();
@@ -437,8 +471,6 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
   const int ntgt = (int)tgt.size();
   const size_t G64 = (size_t)ws->G * kLanes;
   STCHK(ws->ensure_res((size_t)std::max(ntgt, 1) * G64));
-  TargetMap tm;
-  STCHK(tm.install(ws, tgt));
   const size_t ns = src.size();
   out.dep.assign(ns * (size_t)std::max(ntgt, 0), 0.0);
   if (want_counters) out.counters.assign(ns * 3, 0);
@@ -446,10 +478,62 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
   ProfAcc prof;
   bool ovf = false;
   uint64_t tot[C_COUNT] = {0};
-  const size_t per = want_counters ? 1 : G64;  // counters per source need one source per batch
   std::vector<uint32_t> ord;
   STCHK(source_order(g, ws, src, ord));
-  for (size_t b0 = 0; b0 < ns; b0 += per) {
+  if (!want_counters) {
+    std::unique_ptr<Lease> ls2;
+    Workspace *ws2 = nullptr;
+    if (ns > G64) {
+      ls2.reset(new (std::nothrow) Lease(g));
+      bool room = ls2 && ls2->ok() && (*ls2)->batch_ready && (*ls2)->G == ws->G;
+      if (!room && ls2 && ls2->ok()) {
+        size_t free_b = 0, total_b = 0;
+        room = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+               (uint64_t)free_b >= batch_workspace_bytes(g, cfg.groups) + kPipelineHeadroom;
+      }
+      if (room && (*ls2)->init_common(g) == BCD_OK && (*ls2)->ensure_batch(cfg.groups) == BCD_OK &&
+          (*ls2)->ensure_res((size_t)std::max(ntgt, 1) * G64) == BCD_OK && (*ls2)->G == ws->G)
+        ws2 = ls2->w.get();
+      else
+        (void)hipGetLastError();  // run on one workspace
+    }
+    if (ws2) {
+      bcd_status rc2 = BCD_OK;
+      std::string err2;
+      ProfAcc prof2;
+      bool ovf2 = false;
+      std::thread helper;
+      try {
+        helper = std::thread([&] {
+          rc2 = run_batch_stripe(g, ws2, src, ord, tgt, 1, 2, out.dep, prof2, ovf2);
+          if (rc2 != BCD_OK) err2 = bcd_last_error();
+        });
+      } catch (...) {
+        ws2 = nullptr;
+      }
+      if (ws2) {
+        const bcd_status rc1 = run_batch_stripe(g, ws, src, ord, tgt, 0, 2, out.dep, prof, ovf);
+        helper.join();
+        STCHK(rc1);
+        if (rc2 != BCD_OK) return fail(rc2, err2);
+        for (int kd = 0; kd < 2; ++kd) {
+          prof.launches[kd] += prof2.launches[kd];
+          prof.ms[kd] += prof2.ms[kd];
+          prof.items[kd] += prof2.items[kd];
+        }
+        ovf = ovf || ovf2;
+        uint64_t t2[C_COUNT] = {0};
+        STCHK(collect_counters(ws2, t2, ws2->S.acc));
+        for (int j = 0; j < C_COUNT; ++j) tot[j] += t2[j];
+      }
+    }
+    if (!ws2) STCHK(run_batch_stripe(g, ws, src, ord, tgt, 0, 1, out.dep, prof, ovf));
+  }
+  // counters per source need one source per batch
+  TargetMap tm;
+  if (want_counters) STCHK(tm.install(ws, tgt));
+  for (size_t b0 = 0; want_counters && b0 < ns; b0 += 1) {
+    const size_t per = 1;
     const int k = (int)std::min(per, ns - b0);
     std::vector<int32_t> bsrc((size_t)k);
     for (int i = 0; i < k; ++i) bsrc[(size_t)i] = src[ord[b0 + i]];
@@ -466,7 +550,11 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
       for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
     }
   }
-  if (!want_counters) STCHK(collect_counters(ws, tot, ws->S.acc));
+  if (!want_counters) {
+    uint64_t t1[C_COUNT] = {0};
+    STCHK(collect_counters(ws, t1, ws->S.acc));
+    for (int j = 0; j < C_COUNT; ++j) tot[j] += t1[j];
+  }
   out.te = tot[C_FWD_APAIRS];
   out.reached = tot[C_FWD_VPAIRS];
   out.dag = tot[C_FWD_DPAIRS];

@@ -418,16 +418,14 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
 
 using namespace bcd;
 
-extern "C" {
-
-double bcd_server_now(void) { return steady_now(); }
+namespace bcd {
 
 // Device bytes of one worker's batch workspace of `groups` column groups:
 // 64-bit path-count and psi rows, backward level masks, initial item lists
 // of 16 entries per (g, v), the per-vertex target map, and the engine's own
 // arrays (weighted: distances, DAG in-arc counters, round masks; unweighted:
 // level records).
-static uint64_t workspace_bytes(const Graph *g, int groups) {
+uint64_t batch_workspace_bytes(const Graph *g, int groups) {
   const uint64_t GN = (uint64_t)groups * (uint64_t)g->n;
   uint64_t b = GN * kLanes * 16 + GN * 2 * sizeof(LevMask) + GN * 16 * 12 + (uint64_t)g->n * 24;
   if (g->weighted) b += GN * kLanes * 8 + GN * 28 + GN * 4 * 8;
@@ -435,12 +433,18 @@ static uint64_t workspace_bytes(const Graph *g, int groups) {
   return b;
 }
 
+}  // namespace bcd
+
+extern "C" {
+
+double bcd_server_now(void) { return steady_now(); }
+
 bcd_status bcd_server_workspace_bytes(const bcd_graph *gh, int32_t groups, int32_t workers, uint64_t *bytes) {
   if (!gh || !bytes) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   const Graph *g = reinterpret_cast<const Graph *>(gh);
   if (groups <= 0) groups = g->config().groups;
   if (workers <= 0) workers = 2;
-  *bytes = workspace_bytes(g, groups) * (uint64_t)workers;
+  *bytes = batch_workspace_bytes(g, groups) * (uint64_t)workers;
   return BCD_OK;
 }
 
@@ -458,11 +462,14 @@ bcd_status bcd_server_create(const bcd_graph *gh, const bcd_server_config *cfg, 
   if (S->cfg.queue_capacity <= 0) S->cfg.queue_capacity = 4096;
   if ((uint64_t)S->cfg.groups * (uint64_t)g->n >= (1ull << 32))
     return fail(BCD_ERR_INVALID_ARG, "groups * n must stay below 2^32");
-  const uint64_t fixed = workspace_bytes(g, S->cfg.groups) * (uint64_t)S->cfg.workers;
+  const uint64_t fixed = batch_workspace_bytes(g, S->cfg.groups) * (uint64_t)S->cfg.workers;
   if (fixed >= S->cfg.hbm_budget_bytes)
     return fail(BCD_ERR_OUT_OF_MEMORY, "HBM budget smaller than the batch workspaces (" + std::to_string(fixed) +
                                            " bytes); lower groups or workers");
   S->budget_q = (size_t)(S->cfg.hbm_budget_bytes - fixed);
+  // the server brings its own workspaces: idle ones pooled by earlier calls
+  // on this graph give their memory back first
+  g->trim_pool();
   S->plan_ws.reset(new (std::nothrow) Workspace());
   if (!S->plan_ws) return fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed");
   STCHK(S->plan_ws->init_common(g));
