@@ -231,6 +231,9 @@ typedef struct bcd_kernel_profile {
   uint64_t items;        /* work items: one per (64-source column group, vertex,
                             level) with a nonempty lane mask (0 for the
                             weighted engine) */
+  double union_ms;       /* wall time during which at least one of these launches
+                            ran: launches overlapping on concurrent streams
+                            (pipelined batches) count once */
 } bcd_kernel_profile;
 
 bcd_status bcd_profile_enable(bcd_graph *g, int32_t on);

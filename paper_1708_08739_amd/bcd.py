@@ -63,7 +63,7 @@ class SampleParams(C.Structure):
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double),
                 ("vertex_pairs", C.c_uint64), ("arc_pairs", C.c_uint64), ("dag_pairs", C.c_uint64),
-                ("items", C.c_uint64)]
+                ("items", C.c_uint64), ("union_ms", C.c_double)]
 
 
 class ServerConfig(C.Structure):

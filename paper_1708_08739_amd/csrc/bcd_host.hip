@@ -364,6 +364,7 @@ std::pair<hipEvent_t, hipEvent_t> Workspace::event_pair(size_t i) {
 
 Graph::~Graph() {
   pool.clear();
+  if (prof_ref) (void)hipEventDestroy(prof_ref);
   dfree(d_rp);
   dfree(d_col);
   dfree(d_w);
@@ -433,8 +434,15 @@ void Graph::release(std::unique_ptr<Workspace> w) {
   pool.push_back(std::move(w));
 }
 
+bcd_status Graph::mark_profile_origin() {
+  if (!prof_ref) HIPCHK(hipEventCreate(&prof_ref));
+  HIPCHK(hipEventRecord(prof_ref, nullptr));
+  HIPCHK(hipEventSynchronize(prof_ref));
+  return BCD_OK;
+}
+
 void Graph::add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
-                        uint64_t items) {
+                        uint64_t items, const std::vector<std::pair<double, double>> *intervals) {
   std::lock_guard<std::mutex> lk(prof_mu);
   bcd_kernel_profile &p = prof[kind];
   p.launches += launches;
@@ -444,6 +452,10 @@ void Graph::add_profile(int kind, int64_t launches, double ms, const uint64_t *c
   p.arc_pairs += c3[1];
   p.dag_pairs += c3[2];
   p.items += items;
+  if (intervals && !intervals->empty())
+    prof_iv[kind].insert(prof_iv[kind].end(), intervals->begin(), intervals->end());
+  else
+    prof_solo_ms[kind] += ms;
 }
 
 }  // namespace bcd
@@ -614,7 +626,12 @@ bcd_status bcd_get_config(const bcd_graph *gh, bcd_config *cfg) {
 
 bcd_status bcd_profile_enable(bcd_graph *gh, int32_t on) {
   if (!gh) return fail(BCD_ERR_INVALID_ARG, "graph is NULL");
-  reinterpret_cast<Graph *>(gh)->profiling.store(on != 0);
+  Graph *g = reinterpret_cast<Graph *>(gh);
+  if (on) {
+    std::lock_guard<std::mutex> lk(g->prof_mu);
+    STCHK(g->mark_profile_origin());
+  }
+  g->profiling.store(on != 0);
   return BCD_OK;
 }
 
@@ -623,6 +640,23 @@ bcd_status bcd_profile_get(const bcd_graph *gh, int32_t kind, bcd_kernel_profile
   const Graph *g = reinterpret_cast<const Graph *>(gh);
   std::lock_guard<std::mutex> lk(g->prof_mu);
   *out = g->prof[kind];
+  // measure of the union of the launch intervals (sweep over sorted starts)
+  std::vector<std::pair<double, double>> iv = g->prof_iv[kind];
+  std::sort(iv.begin(), iv.end());
+  double u = 0.0, a = 0.0, b = -1.0;
+  bool open = false;
+  for (const auto &x : iv) {
+    if (!open || x.first > b) {
+      if (open) u += b - a;
+      a = x.first;
+      b = x.second;
+      open = true;
+    } else {
+      b = std::max(b, x.second);
+    }
+  }
+  if (open) u += b - a;
+  out->union_ms = u + g->prof_solo_ms[kind];
   return BCD_OK;
 }
 
@@ -631,6 +665,11 @@ bcd_status bcd_profile_reset(bcd_graph *gh) {
   Graph *g = reinterpret_cast<Graph *>(gh);
   std::lock_guard<std::mutex> lk(g->prof_mu);
   std::memset(g->prof, 0, sizeof(g->prof));
+  for (int k = 0; k < 2; ++k) {
+    g->prof_iv[k].clear();
+    g->prof_solo_ms[k] = 0.0;
+  }
+  if (g->profiling.load()) STCHK(g->mark_profile_origin());
   return BCD_OK;
 }
 

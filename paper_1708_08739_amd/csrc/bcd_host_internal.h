@@ -138,6 +138,10 @@ struct Graph {
   std::vector<uint8_t> lm_sig;     // [n][16] BFS distance to each hub, 255 = unreachable
   mutable std::mutex prof_mu;
   bcd_kernel_profile prof[2]{};
+  hipEvent_t prof_ref = nullptr;                      // origin of the launch intervals below
+  std::vector<std::pair<double, double>> prof_iv[2];  // launch [start, end], ms after prof_ref
+  double prof_solo_ms[2] = {0, 0};                    // launches timed without an interval
+  bcd_status mark_profile_origin();
 
   ~Graph();
   DevGraph dev() const;
@@ -148,7 +152,7 @@ struct Graph {
   void release(std::unique_ptr<Workspace> w);
   void trim_pool();  // free the device memory of idle pooled workspaces
   void add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
-                   uint64_t items = 0);
+                   uint64_t items = 0, const std::vector<std::pair<double, double>> *intervals = nullptr);
   int64_t outdeg(int64_t v) const { return h_rp[(size_t)v + 1] - h_rp[(size_t)v]; }
 };
 

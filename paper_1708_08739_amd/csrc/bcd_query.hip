@@ -245,6 +245,7 @@ struct ProfAcc {
   int64_t launches[2] = {0, 0};
   double ms[2] = {0, 0};
   uint64_t items[2] = {0, 0};
+  std::vector<std::pair<double, double>> iv[2];  // launch intervals after the graph's profile origin
 };
 
 // One batch: `k` sources already staged in ws->h_items0 / h_masks0 (lane i
@@ -399,6 +400,12 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
         const int kind = i < fwd_events ? 0 : 1;
         prof->ms[kind] += ms;
         prof->launches[kind] += 1;
+        float t0 = 0, t1 = 0;
+        if (g->prof_ref && hipEventElapsedTime(&t0, g->prof_ref, ws->events[i].first) == hipSuccess &&
+            hipEventElapsedTime(&t1, g->prof_ref, ws->events[i].second) == hipSuccess)
+          prof->iv[kind].emplace_back((double)t0, (double)t1);
+        else
+          (void)hipGetLastError();
       }
       for (int l = 0; l < levels; ++l)
         for (int p = 0; p < P; ++p) {
@@ -428,8 +435,8 @@ static void add_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr) {
   //   backward: 32 per (source, vertex) + 8 per (source, arc) + 8 per (source, DAG arc)
   const double fb = 32.0 * ctr[C_FWD_VPAIRS] + 8.0 * ctr[C_FWD_APAIRS] + 8.0 * ctr[C_FWD_DPAIRS];
   const double bb = 32.0 * ctr[C_BWD_VPAIRS] + 8.0 * ctr[C_BWD_APAIRS] + 8.0 * ctr[C_BWD_DPAIRS];
-  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb, p.items[0]);
-  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb, p.items[1]);
+  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb, p.items[0], &p.iv[0]);
+  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb, p.items[1], &p.iv[1]);
 }
 
 // The batches b = first, first + stride, ... of the ordered source list on
@@ -520,6 +527,7 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
           prof.launches[kd] += prof2.launches[kd];
           prof.ms[kd] += prof2.ms[kd];
           prof.items[kd] += prof2.items[kd];
+          prof.iv[kd].insert(prof.iv[kd].end(), prof2.iv[kd].begin(), prof2.iv[kd].end());
         }
         ovf = ovf || ovf2;
         uint64_t t2[C_COUNT] = {0};

@@ -377,6 +377,32 @@ def test_rmat16_sampled_sources_bench_config(B, oracle):
     assert got0 == got and st0["traversed_edges"] == st["traversed_edges"] and st0["dag_arcs"] == st["dag_arcs"]
 
 
+def test_profile_union_of_launch_intervals(B, oracle):
+    """Kernel profile on a query split into many batches (run two at a time on
+    two streams when HBM has room): the busy time (union of the launch
+    intervals) is positive and never above the summed launch durations, the
+    per-kind pair counts match the query's own counters, and profiling leaves
+    the value unchanged."""
+    g, q = gg.rmat16()
+    r = q[0]
+    G = dev(B, g, groups=2)
+    want, _ = G.bc_exact(r)
+    G.profile_reset()
+    G.profile_enable(True)
+    got, st = G.bc_exact(r)
+    G.profile_enable(False)
+    assert got == want
+    f, b = G.profile(0), G.profile(1)
+    print("profile fwd", f, "bwd", b, flush=True)
+    for p in (f, b):
+        assert p["launches"] > 0 and p["total_ms"] > 0
+        assert 0 < p["union_ms"] <= p["total_ms"] * (1 + 1e-9) + 1e-6
+    assert f["arc_pairs"] == st["traversed_edges"]
+    G.profile_reset()
+    z = G.profile(0)
+    assert z["launches"] == 0 and z["union_ms"] == 0.0 and z["total_ms"] == 0.0
+
+
 # ------------------------------------------------------------ weighted
 
 WSMALL = [
