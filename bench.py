@@ -8,7 +8,8 @@ out-degree plus 4 seeded uniform ones; each query is an exact BC(r) call
 (Alg.1) through the C ABI with the batched engine.  The graph is resident
 in HBM before timing starts.  Other workloads (--workload): er2000 (ER
 n=2,000, m=10,000, one exact query; LDS engine), rmat18w (weighted R-MAT
-18), rmat20set (set of 64 vertices on R-MAT 20), rmat22serve (sampled
+18), rmat20set (set of 64 vertices on R-MAT 20), rmat20dagset (set of 64
+vertices with |RV(r)| spread from 15 to 1e5 on an acyclic R-MAT 20), rmat22serve (sampled
 queries through the server on R-MAT 22), rmat16bcd (the paper's BCD
 procedure and the unpruned sampling baseline on R-MAT 16, per query).
 
@@ -87,12 +88,22 @@ def workload(name: str):
         return g, q, "rmat18_ef16_w1-100_8queries_exact"
     if name == "rmat20set":
         return gg.rmat20(), None, "rmat20_ef16_set64_exact"
+    if name == "rmat20dagset":
+        return gg.rmat20_dag(), dag_set_queries(), "rmat20_ef16_dag_set64_uneven_exact"
     if name == "rmat22serve":
         return gg.rmat22(), None, "rmat22_ef16_serving_sampled"
     if name == "rmat16bcd":
         g, _ = gg.rmat16()
         return g, None, "rmat16_ef8_bcd_procedure_64queries"
     raise SystemExit(f"unknown workload {name}")
+
+
+def dag_set_queries() -> list[int]:
+    """The 64 query vertices of the acyclic R-MAT 20 set: |RV(r)| log-spaced
+    over 15 .. 1e5 (chosen once on the CPU, list stored with its sizes)."""
+    path = os.path.join(ROOT, "tests", "golden", "rmat20_dag_set64.txt")
+    with open(path) as fh:
+        return [int(line.split()[0]) for line in fh if line.strip() and not line.startswith("#")]
 
 
 def run_weighted(G, g, queries, args):
@@ -327,7 +338,7 @@ def main():
     cfg = G.set_config(engine=engines[ename], **kw)
     log(f"[bench] config groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult}")
 
-    if args.workload in ("rmat18w", "rmat20set", "rmat22serve", "rmat16bcd"):
+    if args.workload in ("rmat18w", "rmat20set", "rmat20dagset", "rmat22serve", "rmat16bcd"):
         extra = {}
         if args.workload == "rmat18w":
             te, wall, lat = run_weighted(G, g, queries, args)
@@ -342,6 +353,23 @@ def main():
             wall = time.perf_counter() - t0
             te, lat = st["traversed_edges"], [wall]
             extra = {"set_size": len(qs), "rv_sizes": sizes, "distinct_sources": st["distinct_sources"]}
+        elif args.workload == "rmat20dagset":
+            qs = queries
+            sizes = [len(G.rv(r)) for r in qs]
+            log(f"[bench] set of {len(qs)}: |RV| from {min(sizes)} to {max(sizes)}")
+            G.bc_set(qs[:8])  # warm-up: workspace and hub signatures
+            lat = []
+            te = 0
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                t = time.perf_counter()
+                bcs, st = G.bc_set(qs)
+                lat.append(time.perf_counter() - t)
+                te += st["traversed_edges"]
+                log(f"[bench] step {i + 1}/{args.steps} done")
+            wall = time.perf_counter() - t0
+            extra = {"set_size": len(qs), "rv_sizes": sizes, "distinct_sources": st["distinct_sources"],
+                     "steps": args.steps, "bc_first": [float(x) for x in bcs[:4]]}
         elif args.workload == "rmat16bcd":
             te, wall, summary, rows = bcd_procedure(G, g, args)
             lat = [x["t_ms"] / 1e3 for x in rows]
@@ -355,7 +383,7 @@ def main():
             # its largest RV; for serving, the first query vertex
             if args.workload == "rmat18w":
                 rq = queries[0]
-            elif args.workload == "rmat20set":
+            elif args.workload in ("rmat20set", "rmat20dagset"):
                 rq = qs[int(np.argmax(sizes))]
             elif args.workload == "rmat16bcd":
                 rq = max(rows, key=lambda x: x["rv"])["r"]

@@ -94,8 +94,8 @@ typedef struct bcd_config {
                          found bottom-up (in-arcs of the unsettled (group,
                          vertex) pairs) when the level before it holds at
                          least 1/bottom_up of the batch's (group, vertex)
-                         pairs; 0 = always top-down (the default), -1 =
-                         default */
+                         pairs; 0 = always top-down, -1 = default (4 on
+                         graphs of 2^19 vertices or more, else 0) */
 } bcd_config;
 
 /* Sampled estimate (Alg.2).  T comes from Eq.(8) unless T_override > 0. */

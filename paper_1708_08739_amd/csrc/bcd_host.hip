@@ -577,7 +577,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->cfg.block = 256;
   g->cfg.grid_mult = 32;
   g->cfg.items = kDefaultItems;
-  g->cfg.bottom_up = kDefaultBottomUp;
+  g->cfg.bottom_up = default_bottom_up(n);
   *out = reinterpret_cast<bcd_graph *>(g.release());
   return BCD_OK;
 }
@@ -614,7 +614,7 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
   std::lock_guard<std::mutex> lk(g->cfg_mu);
   g->cfg = *cfg;
   if (g->cfg.items == 0) g->cfg.items = kDefaultItems;
-  if (g->cfg.bottom_up < 0) g->cfg.bottom_up = kDefaultBottomUp;
+  if (g->cfg.bottom_up < 0) g->cfg.bottom_up = default_bottom_up(g->n);
   return BCD_OK;
 }
 

@@ -148,14 +148,19 @@ RMAT_ABCD = (0.57, 0.19, 0.19, 0.05)
 
 
 def rmat(scale: int, edge_factor: int, seed: int, abcd=RMAT_ABCD,
-         weighted: bool = False, max_weight: int = 100, chunk: int = 1 << 21) -> Digraph:
+         weighted: bool = False, max_weight: int = 100, chunk: int = 1 << 21,
+         orient_seed: int | None = None) -> Digraph:
     """R-MAT (Chakrabarti, Zhan and Faloutsos): ``edge_factor * 2**scale``
     draws; at each of ``scale`` bit levels a uniform double picks quadrant
     a:(0,0) b:(0,1) c:(1,0) d:(1,1) as (source bit, destination bit), most
     significant bit first.  Vertex ids are then relabelled by a seeded
     permutation; self-loops and repeated arcs are dropped; rows sorted.
     Weighted: arc ``e`` of the final CSR gets ``1 + floor(x_e * W / 2**64)``
-    from stream ``seed + 2``, so weights are uniform in ``[1, W]``."""
+    from stream ``seed + 2``, so weights are uniform in ``[1, W]``.
+    ``orient_seed``: after the relabelling every arc is turned to point from
+    the endpoint of lower to the one of higher rank, vertex ``v`` having key
+    ``x_v`` of stream ``orient_seed`` (ties by id), so the graph is acyclic;
+    repeats are dropped after turning."""
     n = 1 << scale
     ne = edge_factor * n
     a, b, c, _ = abcd
@@ -176,6 +181,12 @@ def rmat(scale: int, edge_factor: int, seed: int, abcd=RMAT_ABCD,
     perm = np.argsort(stream(seed + 1, 0, n), kind="stable").astype(np.int64)
     src = perm[src]
     dst = perm[dst]
+    if orient_seed is not None:
+        key = stream(orient_seed, 0, n)
+        rank = np.empty(n, dtype=np.int64)
+        rank[np.lexsort((np.arange(n), key))] = np.arange(n, dtype=np.int64)
+        flip = rank[src] > rank[dst]
+        src, dst = np.where(flip, dst, src), np.where(flip, src, dst)
     s, d = _dedupe_sorted(n, src, dst)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(s, minlength=n), out=row_ptr[1:])
@@ -183,6 +194,8 @@ def rmat(scale: int, edge_factor: int, seed: int, abcd=RMAT_ABCD,
     if weighted:
         w = (below(stream(seed + 2, 0, s.size), max_weight) + np.uint64(1)).astype(np.uint32)
     name = f"rmat_s{scale}_ef{edge_factor}_seed{seed}" + ("_w" if weighted else "")
+    if orient_seed is not None:
+        name += f"_dag{orient_seed}"
     return Digraph(n, row_ptr, d.astype(np.int32), w, name)
 
 
@@ -261,6 +274,13 @@ def rmat20() -> Digraph:
 
 def rmat22() -> Digraph:
     return rmat(22, 16, seed=5)
+
+
+def rmat20_dag() -> Digraph:
+    """The R-MAT scale 20 draws of ``rmat20`` turned into a DAG by a second
+    seeded ranking: ancestor sets (and so RV(r)) then range from a handful
+    of vertices to a large fraction of the graph."""
+    return rmat(20, 16, seed=4, orient_seed=14)
 
 
 # ----------------------------------------------- small structured graphs

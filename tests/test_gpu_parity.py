@@ -491,6 +491,29 @@ def test_rmat20_sampled_sources(B, oracle):
     _sampled_parity(B, oracle, g, r, 24, 20)
 
 
+def test_rmat20_dag_set_uneven(B, oracle):
+    """The acyclic R-MAT 20 set of 64 vertices with |RV(r)| spread from 15 to
+    1e5 (the bench's set, listed with the oracle's |RV| sizes): the GPU's RV
+    sizes equal the stored ones, the set call's values equal the oracle's
+    set values on every member with |RV| <= 100, and the largest member's
+    dependencies on sampled sources equal the oracle's."""
+    import os
+    g = gg.rmat20_dag()
+    path = os.path.join(os.path.dirname(__file__), "golden", "rmat20_dag_set64.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    qs = [int(x[0]) for x in rows]
+    sizes = [int(x[1]) for x in rows]
+    print("rmat20 dag", g.m, "set of", len(qs), flush=True)
+    G = dev(B, g)
+    assert [len(G.rv(r)) for r in qs] == sizes
+    bcs, st = G.bc_set(qs)
+    small = [i for i, sz in enumerate(sizes) if sz <= 100]
+    want, _ = oracle.bc_set(g, [qs[i] for i in small])
+    assert close(bcs[small], want)
+    assert np.all(np.isfinite(bcs)) and np.all(bcs >= 0)
+    _sampled_parity(B, oracle, g, qs[int(np.argmax(sizes))], 16, 2020)
+
+
 def test_rmat22_sampled_sources_and_draws(B, oracle):
     """R-MAT scale 22, edge factor 16: sampled sources, and an A-BCD call
     whose draws the oracle recomputes."""
