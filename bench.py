@@ -53,9 +53,10 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload_name: str):
-    """Counter-measured HBM bytes per launch of `kernel` on `workload_name`,
-    or None when none were taken or the kernel sources changed since."""
+def measured_traffic(kernel: str, workload_name: str, batch_width: int):
+    """Counter-measured HBM bytes per launch of `kernel` on `workload_name` at
+    `batch_width` sources per batch, or None when none were taken at that
+    width or the kernel sources changed since."""
     path = TRAFFIC_FILES.get(kernel)
     if path is None or not os.path.exists(os.path.join(ROOT, path)):
         return None
@@ -64,7 +65,8 @@ def measured_traffic(kernel: str, workload_name: str):
         for line in fh:
             if line.startswith("traffic:"):
                 parts = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
-                if parts.get("kernel") == kernel and parts.get("workload") == workload_name:
+                if (parts.get("kernel") == kernel and parts.get("workload") == workload_name
+                        and parts.get("batch_width") == str(batch_width)):
                     rec = parts
     if not rec or rec.get("sources_sha256") != kernel_sources_sha256():
         return None
@@ -444,7 +446,7 @@ def main():
         per_launch = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
         # the LDS engine runs both passes in one kernel, timed as the forward
         kname = "k_lds_pass" if ename == "lds" else f"k_{'fwd' if kind == 'forward' else 'bwd'}_level"
-        traffic = measured_traffic(kname, wname)
+        traffic = measured_traffic(kname, wname, 64 * G.config().groups if ename == "batched" else 1)
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": None if traffic is None else round(traffic, 1),

@@ -573,7 +573,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
     }
   }
   g->cfg.engine = BCD_ENGINE_BATCHED;
-  g->cfg.groups = default_groups(n);
+  g->cfg.groups = default_groups(n, weight != nullptr);
   g->cfg.block = 256;
   g->cfg.grid_mult = 32;
   g->cfg.items = kDefaultItems;
