@@ -2,6 +2,7 @@
 #pragma once
 
 #include <atomic>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -179,6 +180,63 @@ struct SourceRun {
   uint64_t te = 0, reached = 0, dag = 0;
   int32_t width = 0;
 };
+
+struct TargetMap {
+  Workspace *ws;
+  int32_t *d_verts = nullptr;
+  int k = 0;
+  bool set = false;
+  ~TargetMap() {
+    if (set) {
+      (void)launch_scatter_targets(ws->S.tgt_of, d_verts, k, 0, ws->stream);
+      (void)hipStreamSynchronize(ws->stream);
+    }
+    if (d_verts) (void)hipFree(d_verts);
+  }
+  bcd_status install(Workspace *w, const std::vector<int32_t> &tgt) {
+    ws = w;
+    k = (int)tgt.size();
+    if (k == 0) return BCD_OK;
+    if (hipMalloc((void **)&d_verts, (size_t)k * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      d_verts = nullptr;
+      return fail(BCD_ERR_OUT_OF_MEMORY, "target list allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(d_verts, tgt.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream));
+    HIPCHK(launch_scatter_targets(ws->S.tgt_of, d_verts, k, 1, ws->stream));
+    set = true;
+    return BCD_OK;
+  }
+};
+
+// Launch timings of one run, per kind (0 forward, 1 backward), gathered while
+// the graph's profiling is on.
+struct ProfAcc {
+  int64_t launches[2] = {0, 0};
+  double ms[2] = {0, 0};
+  uint64_t items[2] = {0, 0};
+  std::vector<std::pair<double, double>> iv[2];  // launch intervals after the graph's profile origin
+  void merge(const ProfAcc &o) {
+    for (int k = 0; k < 2; ++k) {
+      launches[k] += o.launches[k];
+      ms[k] += o.ms[k];
+      items[k] += o.items[k];
+      iv[k].insert(iv[k].end(), o.iv[k].begin(), o.iv[k].end());
+    }
+  }
+  // one launch bracketed by the event pair (a, b)
+  void add(const Graph *g, int kind, hipEvent_t a, hipEvent_t b);
+};
+
+// Batches b = first, first + stride, ... of one run on workspace `ws`
+// (ws's own stream; results to their own positions).
+using StripeFn = std::function<bcd_status(Workspace *ws, size_t first, size_t stride, ProfAcc &prof, bool &ovf)>;
+// Runs `stripe` over all batches; when the run has more than one batch and a
+// second workspace can be had (`prepare` readies it), every other batch goes
+// to that workspace on a helper thread.  The second workspace's counters are
+// added to `tot`.
+bcd_status run_pipelined(Graph *g, Workspace *ws, size_t nbatches, const std::function<bcd_status(Workspace *)> &prepare,
+                         const StripeFn &stripe, ProfAcc &prof, bool &ovf, uint64_t *tot);
 
 // Query layer (bcd_query.hip).
 bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::vector<uint32_t> &bits,

@@ -204,33 +204,6 @@ bcd_status source_order(Graph *g, Workspace *ws, const std::vector<int32_t> &src
 
 // --------------------------------------------------------- targets
 
-struct TargetMap {
-  Workspace *ws;
-  int32_t *d_verts = nullptr;
-  int k = 0;
-  bool set = false;
-  ~TargetMap() {
-    if (set) {
-      (void)launch_scatter_targets(ws->S.tgt_of, d_verts, k, 0, ws->stream);
-      (void)hipStreamSynchronize(ws->stream);
-    }
-    if (d_verts) (void)hipFree(d_verts);
-  }
-  bcd_status install(Workspace *w, const std::vector<int32_t> &tgt) {
-    ws = w;
-    k = (int)tgt.size();
-    if (k == 0) return BCD_OK;
-    if (hipMalloc((void **)&d_verts, (size_t)k * sizeof(int32_t)) != hipSuccess) {
-      (void)hipGetLastError();
-      d_verts = nullptr;
-      return fail(BCD_ERR_OUT_OF_MEMORY, "target list allocation failed");
-    }
-    HIPCHK(hipMemcpyAsync(d_verts, tgt.data(), (size_t)k * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream));
-    HIPCHK(launch_scatter_targets(ws->S.tgt_of, d_verts, k, 1, ws->stream));
-    set = true;
-    return BCD_OK;
-  }
-};
 
 // -------------------------------------------------- batched engine
 
@@ -239,13 +212,6 @@ struct BatchExport {
   unsigned long long *sigma = nullptr;
   double *delta = nullptr;
   int64_t k = 0;
-};
-
-struct ProfAcc {
-  int64_t launches[2] = {0, 0};
-  double ms[2] = {0, 0};
-  uint64_t items[2] = {0, 0};
-  std::vector<std::pair<double, double>> iv[2];  // launch intervals after the graph's profile origin
 };
 
 // One batch: `k` sources already staged in ws->h_items0 / h_masks0 (lane i
@@ -395,17 +361,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     HIPCHK(hipStreamSynchronize(st));
     if (profiling && prof) {
       for (size_t i = 0; i < ev; ++i) {
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ws->events[i].first, ws->events[i].second));
-        const int kind = i < fwd_events ? 0 : 1;
-        prof->ms[kind] += ms;
-        prof->launches[kind] += 1;
-        float t0 = 0, t1 = 0;
-        if (g->prof_ref && hipEventElapsedTime(&t0, g->prof_ref, ws->events[i].first) == hipSuccess &&
-            hipEventElapsedTime(&t1, g->prof_ref, ws->events[i].second) == hipSuccess)
-          prof->iv[kind].emplace_back((double)t0, (double)t1);
-        else
-          (void)hipGetLastError();
+        prof->add(g, i < fwd_events ? 0 : 1, ws->events[i].first, ws->events[i].second);
       }
       for (int l = 0; l < levels; ++l)
         for (int p = 0; p < P; ++p) {
@@ -471,6 +427,69 @@ static bcd_status run_batch_stripe(Graph *g, Workspace *ws, const std::vector<in
 // pooled with the graph; a server releases idle pooled workspaces).
 constexpr uint64_t kPipelineHeadroom = 16ull << 30;
 
+void ProfAcc::add(const Graph *g, int kind, hipEvent_t a, hipEvent_t b) {
+  float ms = 0, t0 = 0, t1 = 0;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  this->ms[kind] += ms;
+  launches[kind] += 1;
+  if (g->prof_ref && hipEventElapsedTime(&t0, g->prof_ref, a) == hipSuccess &&
+      hipEventElapsedTime(&t1, g->prof_ref, b) == hipSuccess)
+    iv[kind].emplace_back((double)t0, (double)t1);
+  else
+    (void)hipGetLastError();
+}
+
+bcd_status run_pipelined(Graph *g, Workspace *ws, size_t nbatches, const std::function<bcd_status(Workspace *)> &prepare,
+                         const StripeFn &stripe, ProfAcc &prof, bool &ovf, uint64_t *tot) {
+  std::unique_ptr<Lease> ls2;
+  Workspace *ws2 = nullptr;
+  if (nbatches > 1) {
+    ls2.reset(new (std::nothrow) Lease(g));
+    bool room = ls2 && ls2->ok() && (*ls2)->batch_ready && (*ls2)->G == ws->G &&
+                (!g->weighted || (*ls2)->weighted_ready);
+    if (!room && ls2 && ls2->ok()) {
+      size_t free_b = 0, total_b = 0;
+      room = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+             (uint64_t)free_b >= batch_workspace_bytes(g, ws->G) + kPipelineHeadroom;
+    }
+    if (room && (*ls2)->init_common(g) == BCD_OK && prepare(ls2->w.get()) == BCD_OK && (*ls2)->G == ws->G)
+      ws2 = ls2->w.get();
+    else
+      (void)hipGetLastError();  // run on one workspace
+  }
+  if (ws2) {
+    bcd_status rc2 = BCD_OK;
+    std::string err2;
+    ProfAcc prof2;
+    bool ovf2 = false;
+    std::thread helper;
+    try {
+      helper = std::thread([&] {
+        rc2 = stripe(ws2, 1, 2, prof2, ovf2);
+        if (rc2 != BCD_OK) err2 = bcd_last_error();
+      });
+    } catch (...) {
+      ws2 = nullptr;
+    }
+    if (ws2) {
+      const bcd_status rc1 = stripe(ws, 0, 2, prof, ovf);
+      helper.join();
+      STCHK(rc1);
+      if (rc2 != BCD_OK) return fail(rc2, err2);
+      prof.merge(prof2);
+      ovf = ovf || ovf2;
+      uint64_t t2[C_COUNT] = {0};
+      STCHK(collect_counters(ws2, t2, ws2->S.acc));
+      for (int j = 0; j < C_COUNT; ++j) tot[j] += t2[j];
+      return BCD_OK;
+    }
+  }
+  return stripe(ws, 0, 1, prof, ovf);
+}
+
 static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
                               const std::vector<int32_t> &tgt, bool want_counters, SourceRun &out) {
   const bcd_config cfg = g->config();
@@ -488,54 +507,14 @@ static bcd_status run_batched(Graph *g, Workspace *ws, const std::vector<int32_t
   std::vector<uint32_t> ord;
   STCHK(source_order(g, ws, src, ord));
   if (!want_counters) {
-    std::unique_ptr<Lease> ls2;
-    Workspace *ws2 = nullptr;
-    if (ns > G64) {
-      ls2.reset(new (std::nothrow) Lease(g));
-      bool room = ls2 && ls2->ok() && (*ls2)->batch_ready && (*ls2)->G == ws->G;
-      if (!room && ls2 && ls2->ok()) {
-        size_t free_b = 0, total_b = 0;
-        room = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
-               (uint64_t)free_b >= batch_workspace_bytes(g, cfg.groups) + kPipelineHeadroom;
-      }
-      if (room && (*ls2)->init_common(g) == BCD_OK && (*ls2)->ensure_batch(cfg.groups) == BCD_OK &&
-          (*ls2)->ensure_res((size_t)std::max(ntgt, 1) * G64) == BCD_OK && (*ls2)->G == ws->G)
-        ws2 = ls2->w.get();
-      else
-        (void)hipGetLastError();  // run on one workspace
-    }
-    if (ws2) {
-      bcd_status rc2 = BCD_OK;
-      std::string err2;
-      ProfAcc prof2;
-      bool ovf2 = false;
-      std::thread helper;
-      try {
-        helper = std::thread([&] {
-          rc2 = run_batch_stripe(g, ws2, src, ord, tgt, 1, 2, out.dep, prof2, ovf2);
-          if (rc2 != BCD_OK) err2 = bcd_last_error();
-        });
-      } catch (...) {
-        ws2 = nullptr;
-      }
-      if (ws2) {
-        const bcd_status rc1 = run_batch_stripe(g, ws, src, ord, tgt, 0, 2, out.dep, prof, ovf);
-        helper.join();
-        STCHK(rc1);
-        if (rc2 != BCD_OK) return fail(rc2, err2);
-        for (int kd = 0; kd < 2; ++kd) {
-          prof.launches[kd] += prof2.launches[kd];
-          prof.ms[kd] += prof2.ms[kd];
-          prof.items[kd] += prof2.items[kd];
-          prof.iv[kd].insert(prof.iv[kd].end(), prof2.iv[kd].begin(), prof2.iv[kd].end());
-        }
-        ovf = ovf || ovf2;
-        uint64_t t2[C_COUNT] = {0};
-        STCHK(collect_counters(ws2, t2, ws2->S.acc));
-        for (int j = 0; j < C_COUNT; ++j) tot[j] += t2[j];
-      }
-    }
-    if (!ws2) STCHK(run_batch_stripe(g, ws, src, ord, tgt, 0, 1, out.dep, prof, ovf));
+    auto prepare = [&](Workspace *w) -> bcd_status {
+      STCHK(w->ensure_batch(cfg.groups));
+      return w->ensure_res((size_t)std::max(ntgt, 1) * G64);
+    };
+    auto stripe = [&](Workspace *w, size_t first, size_t stride, ProfAcc &p, bool &o) -> bcd_status {
+      return run_batch_stripe(g, w, src, ord, tgt, first, stride, out.dep, p, o);
+    };
+    STCHK(run_pipelined(g, ws, (ns + G64 - 1) / G64, prepare, stripe, prof, ovf, tot));
   }
   // counters per source need one source per batch
   TargetMap tm;

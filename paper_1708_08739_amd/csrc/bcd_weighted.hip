@@ -513,8 +513,8 @@ struct WExport {
 };
 
 // One batch of the weighted engine; `k` sources staged in h_items0/h_masks0.
-static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool full, WExport *ex,
-                                 double *ms_fwd, double *ms_bwd, int64_t *l_fwd, int64_t *l_bwd, bool *sigma_overflow,
+static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool full, WExport *ex, ProfAcc *prof,
+                                 bool *sigma_overflow,
                                  bool copy_res = true, unsigned long long *ovl_out = nullptr) {
   hipStream_t st = ws->stream;
   const DevGraph D = g->dev();
@@ -634,39 +634,26 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     HIPCHK(launch_ctr_fold(S.ctr, kCtrSlots, S.acc, st));
     HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * P * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
-    if (profiling) {
-      for (size_t i = 0; i < ev; ++i) {
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ws->events[i].first, ws->events[i].second));
-        if (i < fwd_events) {
-          *ms_fwd += ms;
-          *l_fwd += 1;
-        } else {
-          *ms_bwd += ms;
-          *l_bwd += 1;
-        }
-      }
-    }
+    if (profiling && prof)
+      for (size_t i = 0; i < ev; ++i) prof->add(g, i < fwd_events ? 0 : 1, ws->events[i].first, ws->events[i].second);
     return BCD_OK;
   }
 }
 
 static bcd_status wcounters(Workspace *ws, uint64_t *c) { return collect_counters(ws, c, ws->S.acc); }
 
-static void wprofile(Graph *g, double msf, double msb, int64_t lf, int64_t lb, const uint64_t *c) {
+static void wprofile(Graph *g, const ProfAcc &p, const uint64_t *c) {
   const double fb = 32.0 * c[C_FWD_VPAIRS] + 8.0 * c[C_FWD_APAIRS] + 8.0 * c[C_FWD_DPAIRS];
   const double bb = 32.0 * c[C_BWD_VPAIRS] + 8.0 * c[C_BWD_APAIRS] + 8.0 * c[C_BWD_DPAIRS];
-  g->add_profile(0, lf, msf, c + C_FWD_VPAIRS, fb);
-  g->add_profile(1, lb, msb, c + C_BWD_VPAIRS, bb);
+  g->add_profile(0, p.launches[0], p.ms[0], c + C_FWD_VPAIRS, fb, 0, &p.iv[0]);
+  g->add_profile(1, p.launches[1], p.ms[1], c + C_BWD_VPAIRS, bb, 0, &p.iv[1]);
 }
 
 bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
   if ((uint64_t)g->n * (uint64_t)g->max_w >= 0xFFFFFFFFull)
     return fail(BCD_ERR_UNSUPPORTED, "n * max weight must stay below 2^32 - 1 for 32-bit distances");
   STCHK(ws->ensure_weighted());
-  double a = 0, b = 0;
-  int64_t c = 0, d = 0;
-  return run_one_wbatch(g, ws, k, ntgt, false, nullptr, &a, &b, &c, &d, ovf, false, ovl_out);
+  return run_one_wbatch(g, ws, k, ntgt, false, nullptr, nullptr, ovf, false, ovl_out);
 }
 
 bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
@@ -679,13 +666,6 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   const int ntgt = (int)tgt.size();
   const size_t G64 = (size_t)ws->G * kLanes;
   STCHK(ws->ensure_res((size_t)std::max(ntgt, 1) * G64));
-  std::vector<int32_t> tv(tgt);
-  int32_t *d_t = nullptr;
-  if (ntgt > 0) {
-    STCHK(walloc(&d_t, (size_t)ntgt));
-    HIPCHK(hipMemcpyAsync(d_t, tv.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream));
-    HIPCHK(launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 1, ws->stream));
-  }
   const size_t ns = src.size();
   out.dep.assign(ns * (size_t)ntgt, 0.0);
   if (want_counters) out.counters.assign(ns * 3, 0);
@@ -695,40 +675,50 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   out.width = (int32_t)per;
   std::vector<uint32_t> ord;
   STCHK(source_order(g, ws, src, ord));
-  double msf = 0, msb = 0;
-  int64_t lf = 0, lb = 0;
+  ProfAcc prof;
   bool ovf = false;
   uint64_t tot[C_COUNT] = {0};
-  bcd_status rc = BCD_OK;
-  for (size_t b0 = 0; b0 < ns && rc == BCD_OK; b0 += per) {
-    const int k = (int)std::min(per, ns - b0);
-    std::vector<int32_t> bsrc((size_t)k);
-    for (int i = 0; i < k; ++i) bsrc[(size_t)i] = src[ord[b0 + i]];
-    ws->stage_sources(bsrc.data(), k);
-    rc = run_one_wbatch(g, ws, k, ntgt, false, nullptr, &msf, &msb, &lf, &lb, &ovf);
-    if (rc != BCD_OK) break;
-    for (int i = 0; i < k; ++i)
-      for (int t = 0; t < ntgt; ++t) out.dep[(size_t)ord[b0 + i] * ntgt + t] = ws->h_res[(size_t)t * G64 + i];
-    if (want_counters) {
-      uint64_t c[C_COUNT];
-      rc = wcounters(ws, c);
-      out.counters[(size_t)ord[b0] * 3 + 0] = c[C_FWD_VPAIRS];
-      out.counters[(size_t)ord[b0] * 3 + 1] = c[C_FWD_APAIRS];
-      out.counters[(size_t)ord[b0] * 3 + 2] = c[C_FWD_DPAIRS];
-      for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
+  // batches b = first, first + stride, ... on workspace w; each source's
+  // dependencies go to its own position
+  auto stripe = [&](Workspace *w, size_t first, size_t stride, ProfAcc &p, bool &o) -> bcd_status {
+    TargetMap tm;
+    STCHK(tm.install(w, tgt));
+    std::vector<int32_t> bsrc(per);
+    for (size_t b0 = first * per; b0 < ns; b0 += stride * per) {
+      const int k = (int)std::min(per, ns - b0);
+      for (int i = 0; i < k; ++i) bsrc[(size_t)i] = src[ord[b0 + i]];
+      w->stage_sources(bsrc.data(), k);
+      STCHK(run_one_wbatch(g, w, k, ntgt, false, nullptr, &p, &o));
+      for (int i = 0; i < k; ++i)
+        for (int t = 0; t < ntgt; ++t) out.dep[(size_t)ord[b0 + i] * ntgt + t] = w->h_res[(size_t)t * G64 + i];
+      if (want_counters) {
+        uint64_t c[C_COUNT];
+        STCHK(wcounters(w, c));
+        out.counters[(size_t)ord[b0] * 3 + 0] = c[C_FWD_VPAIRS];
+        out.counters[(size_t)ord[b0] * 3 + 1] = c[C_FWD_APAIRS];
+        out.counters[(size_t)ord[b0] * 3 + 2] = c[C_FWD_DPAIRS];
+        for (int j = 0; j < C_COUNT; ++j) tot[j] += c[j];
+      }
     }
+    return BCD_OK;
+  };
+  if (one) {
+    STCHK(stripe(ws, 0, 1, prof, ovf));
+  } else {
+    auto prepare = [&](Workspace *w) -> bcd_status {
+      STCHK(w->ensure_batch(cfg.groups));
+      STCHK(w->ensure_weighted());
+      return w->ensure_res((size_t)std::max(ntgt, 1) * G64);
+    };
+    STCHK(run_pipelined(g, ws, (ns + per - 1) / per, prepare, stripe, prof, ovf, tot));
+    uint64_t t1[C_COUNT];
+    STCHK(wcounters(ws, t1));
+    for (int j = 0; j < C_COUNT; ++j) tot[j] += t1[j];
   }
-  if (ntgt > 0) {
-    (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
-    (void)hipStreamSynchronize(ws->stream);
-    (void)hipFree(d_t);
-  }
-  if (rc != BCD_OK) return rc;
-  if (!want_counters) STCHK(wcounters(ws, tot));
   out.te = tot[C_FWD_APAIRS];
   out.reached = tot[C_FWD_VPAIRS];
   out.dag = tot[C_FWD_DPAIRS];
-  if (g->profiling.load()) wprofile(g, msf, msb, lf, lb, tot);
+  if (g->profiling.load()) wprofile(g, prof, tot);
   if (ovf) return fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return BCD_OK;
 }
@@ -773,9 +763,7 @@ bcd_status multi_source_pass_weighted(Graph *g, const int32_t *sources, int64_t 
   bool ovf = false;
   if (rc == BCD_OK) {
     ws->stage_sources(sources, (int)k);
-    double a = 0, b = 0;
-    int64_t c = 0, d = 0;
-    rc = run_one_wbatch(g, ws, (int)k, 0, true, &ex, &a, &b, &c, &d, &ovf);
+    rc = run_one_wbatch(g, ws, (int)k, 0, true, &ex, nullptr, &ovf);
   }
   if (rc == BCD_OK) {
     e = hipSuccess;

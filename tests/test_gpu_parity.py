@@ -447,6 +447,29 @@ def test_weighted_bc_and_counters(B, oracle):
     assert dev(B, g1).bc_exact(r)[0] == dev(B, g0).bc_exact(r)[0] or close(dev(B, g1).bc_exact(r)[0], dev(B, g0).bc_exact(r)[0])
 
 
+def test_weighted_many_batches_two_streams(B, oracle):
+    """A weighted query split into many one-group batches (run two at a time
+    on two workspaces and streams when HBM has room): the same value and
+    counters as one wide batch, bit for bit, and the oracle's value; the
+    kernel profile's busy time stays within the summed launch times."""
+    g = gg.with_weights(gg.rmat(11, 8, seed=13), seed=5, max_weight=100)
+    r = gg.top_out_degree(g, 1)[0]
+    wide, stw = dev(B, g).bc_exact(r)
+    G = dev(B, g, groups=1)
+    G.profile_reset()
+    G.profile_enable(True)
+    got, st = G.bc_exact(r)
+    G.profile_enable(False)
+    want, ost = oracle.bc_exact(g, r)
+    print("weighted batches", st["rv_size"], got, want, flush=True)
+    assert got == wide and close(got, want)
+    assert st["traversed_edges"] == stw["traversed_edges"] == ost["te"]
+    rs = gg.top_out_degree(g, 3)
+    assert np.array_equal(G.bc_set(rs)[0], dev(B, g).bc_set(rs)[0])
+    for p in (G.profile(0), G.profile(1)):
+        assert p["launches"] > 0 and 0 < p["union_ms"] <= p["total_ms"] * (1 + 1e-9) + 1e-6
+
+
 def test_bcd_procedure_and_unpruned_sampling(B, oracle):
     g = gg.rmat(12, 8, seed=7)
     G = dev(B, g)
