@@ -229,8 +229,8 @@ typedef struct bcd_kernel_profile {
   uint64_t arc_pairs;    /* (source, arc) pairs scanned */
   uint64_t dag_pairs;    /* (source, shortest-path-DAG arc) pairs used */
   uint64_t items;        /* work items: one per (64-source column group, vertex,
-                            level) with a nonempty lane mask (0 for the
-                            weighted engine) */
+                            level) with a nonempty lane mask (weighted engine:
+                            topological round in place of level) */
   double union_ms;       /* wall time during which at least one of these launches
                             ran: launches overlapping on concurrent streams
                             (pipelined batches) count once */

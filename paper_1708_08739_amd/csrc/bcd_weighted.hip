@@ -634,8 +634,15 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     HIPCHK(launch_ctr_fold(S.ctr, kCtrSlots, S.acc, st));
     HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)lmax + 2) * P * sizeof(uint32_t), st));
     HIPCHK(hipStreamSynchronize(st));
-    if (profiling && prof)
+    if (profiling && prof) {
       for (size_t i = 0; i < ev; ++i) prof->add(g, i < fwd_events ? 0 : 1, ws->events[i].first, ws->events[i].second);
+      // work items: one per (group, vertex, topological round) with ready lanes
+      for (size_t l = 0; l * P < cntp.size(); ++l)
+        for (int p = 0; p < P; ++p) {
+          prof->items[0] += cntp[l * P + p];
+          if (stop >= 0 && (int)l >= stop) prof->items[1] += cntp[l * P + p];
+        }
+    }
     return BCD_OK;
   }
 }
@@ -645,8 +652,8 @@ static bcd_status wcounters(Workspace *ws, uint64_t *c) { return collect_counter
 static void wprofile(Graph *g, const ProfAcc &p, const uint64_t *c) {
   const double fb = 32.0 * c[C_FWD_VPAIRS] + 8.0 * c[C_FWD_APAIRS] + 8.0 * c[C_FWD_DPAIRS];
   const double bb = 32.0 * c[C_BWD_VPAIRS] + 8.0 * c[C_BWD_APAIRS] + 8.0 * c[C_BWD_DPAIRS];
-  g->add_profile(0, p.launches[0], p.ms[0], c + C_FWD_VPAIRS, fb, 0, &p.iv[0]);
-  g->add_profile(1, p.launches[1], p.ms[1], c + C_BWD_VPAIRS, bb, 0, &p.iv[1]);
+  g->add_profile(0, p.launches[0], p.ms[0], c + C_FWD_VPAIRS, fb, p.items[0], &p.iv[0]);
+  g->add_profile(1, p.launches[1], p.ms[1], c + C_BWD_VPAIRS, bb, p.items[1], &p.iv[1]);
 }
 
 bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
