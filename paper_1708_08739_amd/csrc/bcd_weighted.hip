@@ -52,9 +52,41 @@ __global__ void k_w_init(BatchState S, const uint32_t *items0, const ull *masks0
   }
 }
 
+// Lane compaction for one work item: the A lanes of `em` are renumbered
+// 0..A-1 in lane order; lane L of the wavefront then serves source lane
+// `src` (the one of number L mod A) on arc slot L / A of `slots` = 64 / A
+// (slot >= slots: idle).  With few lanes per item the wavefront thus covers
+// `slots` arcs of every source at once instead of one.  Wave-uniform `em`.
+struct Compact {
+  int A, slots, j, slot, src;
+};
+constexpr int kWU = 8;  // arcs per slot per step
+
+// Orders this wavefront's LDS accesses before and after the call (lanes of
+// one wavefront exchanging values through LDS).
+static __device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+static __device__ __forceinline__ Compact compact_lanes(ull em, bool mine) {
+  Compact c;
+  const int lane = lane_id();
+  c.A = __popcll(em);
+  c.slots = kLanes / c.A;
+  // lane of number r learns its lane id (push: a bijection of all 64 lanes)
+  const int rk = mine ? lanes_below(em) : c.A + lanes_below(~em);
+  const int id = __builtin_amdgcn_ds_permute(rk * 4, lane);
+  c.j = lane % c.A;
+  c.slot = lane / c.A;
+  c.src = __shfl(id, c.j);
+  return c;
+}
+
 // One relaxation round.  Input: queue bq[round&1] (length bqn[round%3]) with
 // changed-lane masks chg[round&1]; output: bq[(round+1)&1], chg[(round+1)&1],
 // length bqn[(round+1)%3]; bqn[(round+2)%3] is zeroed for the round after.
+// Lanes are compacted per item (compact_lanes).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int round) {
   const uint64_t n = (uint64_t)S.n;
@@ -75,6 +107,12 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
   __shared__ uint32_t rst_all[(BLOCK / 64) * kCap];
   uint32_t *qst = qst_all + (threadIdx.x >> 6) * kCap;
   uint32_t *rst = rst_all + (threadIdx.x >> 6) * kCap;
+  // per slot: the lanes that improved the slot's head in this step, combined
+  // so that the head's flags take one atomic per step, not one per source
+  __shared__ ull cm_all[BLOCK];
+  ull *cm = cm_all + (threadIdx.x & ~63u);
+  cm[lane] = 0ull;
+  wave_lds_sync();
   int nq = 0, nr = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = qin[i];
@@ -83,52 +121,58 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
     const uint64_t gbase = (uint64_t)g * n;
     const ull mask = ccur[it];
     if (lane == 0) ccur[it] = 0ull;  // the owner retires its flag; others write cnxt only
-    const bool act = (mask >> lane) & 1ull;
-    const uint32_t dv = act ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
-    const bool live = act && dv != kInf;
+    if (mask == 0ull) continue;
+    const Compact cp = compact_lanes(mask, (mask >> lane) & 1ull);
+    const bool on = cp.slot < cp.slots;
+    const uint32_t dv = on ? S.wd[(uint64_t)it * kLanes + (uint32_t)cp.src] : kInf;
+    const bool live = on && dv != kInf;
+    const ull bit = 1ull << cp.src;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    if (lane == 0) c_r += (uint64_t)__popcll(mask) * (uint64_t)(e1 - e0);
-    for (int64_t e = e0; e < e1; e += 8) {
-      const int c = (int)((e1 - e) < 8 ? (e1 - e) : 8);
-      uint32_t wq[8], nd[8], dw[8];
+    if (lane == 0) c_r += (uint64_t)cp.A * (uint64_t)(e1 - e0);
+    const int64_t stepw = (int64_t)cp.slots * kWU;
+    for (int64_t e = e0; e < e1; e += stepw) {
+      uint32_t wq[kWU], nd[kWU], dw[kWU];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        wq[q] = 0u;
-        nd[q] = kInf;
-        if (q < c) {
-          wq[q] = (uint32_t)G.col[e + q];
-          nd[q] = dv + G.w[e + q];
+      for (int u = 0; u < kWU; ++u) {
+        const int64_t ea = e + (int64_t)u * cp.slots + cp.slot;
+        wq[u] = 0u;
+        nd[u] = kInf;
+        if (live && ea < e1) {
+          wq[u] = (uint32_t)G.col[ea];
+          nd[u] = dv + G.w[ea];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) dw[q] = (q < c && live) ? S.wd[(gbase + wq[q]) * kLanes + lane] : 0u;
-      // lane q takes the flags of arc q of the chunk, so the eight arcs'
-      // flag atomics are in flight together
-      ull my_im = 0ull;
-      uint32_t my_w = 0u;
+      for (int u = 0; u < kWU; ++u) dw[u] = nd[u] != kInf ? S.wd[(gbase + wq[u]) * kLanes + (uint32_t)cp.src] : 0u;
+      // a lower tentative distance: lower it (the minimum wins whatever the
+      // order) and flag the vertex for the next round; a flag raised by a
+      // value another wavefront has already beaten only costs a re-scan
+      bool imp[kWU];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (q >= c) break;
-        // a lower tentative distance: lower it (the minimum wins whatever the
-        // order) and flag the vertex for the next round; a flag raised by a
-        // value another wavefront has already beaten only costs a re-scan
-        const bool imp = live && nd[q] < dw[q];
-        if (imp)
-          __hip_atomic_fetch_min(&S.wd[(gbase + wq[q]) * kLanes + lane], nd[q], __ATOMIC_RELAXED,
+      for (int u = 0; u < kWU; ++u) {
+        imp[u] = nd[u] != kInf && nd[u] < dw[u];
+        if (imp[u])
+          __hip_atomic_fetch_min(&S.wd[(gbase + wq[u]) * kLanes + (uint32_t)cp.src], nd[u], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
-        const ull im = __ballot(imp);
-        if (lane == q) {
-          my_im = im;
-          my_w = wq[q];
+      }
+#pragma unroll
+      for (int u = 0; u < kWU; ++u) {
+        if (imp[u]) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        wave_lds_sync();
+        ull m = 0ull;
+        if (cp.j == 0 && on) {
+          m = cm[cp.slot];
+          cm[cp.slot] = 0ull;
         }
+        wave_lds_sync();
+        bool fq = false, fr = false;
+        if (m != 0ull) {
+          fq = atomicOr(&cnxt[gbase + wq[u]], m) == 0ull;
+          fr = atomicOr(&S.vis[gbase + wq[u]], m) == 0ull;
+        }
+        stage_lanes<kCap>(qst, nq, fq, (uint32_t)(gbase + wq[u]), qout_n, qout, 0, GN, nullptr);
+        stage_lanes<kCap>(rst, nr, fr, (uint32_t)(gbase + wq[u]), S.rln, S.rl, 0, GN, nullptr);
       }
-      bool fq = false, fr = false;
-      if (my_im != 0ull) {
-        fq = atomicOr(&cnxt[gbase + my_w], my_im) == 0ull;
-        fr = atomicOr(&S.vis[gbase + my_w], my_im) == 0ull;
-      }
-      stage_lanes<kCap>(qst, nq, fq, (uint32_t)(gbase + my_w), qout_n, qout, 0, GN, nullptr);
-      stage_lanes<kCap>(rst, nr, fr, (uint32_t)(gbase + my_w), S.rln, S.rl, 0, GN, nullptr);
     }
   }
   stage_flush(qst, nq, qout_n, qout, 0, GN, nullptr);
@@ -186,7 +230,8 @@ __global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
 // One topological round: items whose lanes became ready push sigma along
 // their DAG out-arcs; a lane of w whose last DAG in-arc pushed is ready next
 // round.  Level lists, rotation of the mask arrays and target bookkeeping
-// mirror the unweighted forward kernel.
+// mirror the unweighted forward kernel.  Lanes are compacted per item
+// (compact_lanes).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int level) {
   const uint64_t n = (uint64_t)S.n;
@@ -224,62 +269,60 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
     const ull mask = cur[it];
     if (lane == 0) S.imask[base + i] = mask;
     const bool act = (mask >> lane) & 1ull;
-    const ull sv = act ? S.sig[(uint64_t)it * kLanes + lane] : 0ull;
-    const uint32_t dv = act ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
     if (S.tgt_of[v] >= 0) {
       if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
       if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
     }
+    if (mask == 0ull) continue;
+    const Compact cp = compact_lanes(mask, act);
+    const bool on = cp.slot < cp.slots;
+    const uint64_t vrow = (uint64_t)it * kLanes + (uint32_t)cp.src;
+    const ull sv = on ? S.sig[vrow] : 0ull;
+    const uint32_t dv = on ? S.wd[vrow] : kInf;
+    const ull bit = 1ull << cp.src;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    for (int64_t e = e0; e < e1; e += 8) {
-      const int c = (int)((e1 - e) < 8 ? (e1 - e) : 8);
-      uint32_t wq[8], nd[8], dw[8];
+    const int64_t stepw = (int64_t)cp.slots * kWU;
+    for (int64_t e = e0; e < e1; e += stepw) {
+      uint32_t wq[kWU], nd[kWU], dw[kWU];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        wq[q] = 0u;
-        nd[q] = kInf;
-        if (q < c) {
-          wq[q] = (uint32_t)G.col[e + q];
-          nd[q] = dv + G.w[e + q];
+      for (int u = 0; u < kWU; ++u) {
+        const int64_t ea = e + (int64_t)u * cp.slots + cp.slot;
+        wq[u] = 0u;
+        nd[u] = kInf;
+        if (on && ea < e1) {
+          wq[u] = (uint32_t)G.col[ea];
+          nd[u] = dv + G.w[ea];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) dw[q] = (q < c && act) ? S.wd[(gbase + wq[q]) * kLanes + lane] : kInf - 1u;
+      for (int u = 0; u < kWU; ++u) dw[u] = nd[u] != kInf ? S.wd[(gbase + wq[u]) * kLanes + (uint32_t)cp.src] : kInf - 1u;
       // DAG arcs of the batch: push sigma and count down, all atomics issued
       // before any result is used
-      ull so[8];
-      uint32_t co[8];
+      ull so[kWU];
+      uint32_t co[kWU];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        so[q] = 0ull;
-        co[q] = 0u;
-        if (q < c && act && dw[q] == nd[q]) {
-          const uint64_t row = (gbase + wq[q]) * kLanes + lane;
-          so[q] = atomicAdd(&S.sig[row], sv);
-          co[q] = atomicSub(&S.wc[row], 1u);
+      for (int u = 0; u < kWU; ++u) {
+        so[u] = 0ull;
+        co[u] = 0u;
+        if (nd[u] != kInf && dw[u] == nd[u]) {
+          const uint64_t row = (gbase + wq[u]) * kLanes + (uint32_t)cp.src;
+          so[u] = atomicAdd(&S.sig[row], sv);
+          co[u] = atomicSub(&S.wc[row], 1u);
         }
       }
-      // lane q takes the ready flags of arc q's head, so the chunk's flag
-      // atomics are in flight together
-      ull my_rm = 0ull;
-      uint32_t my_w = 0u;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (q >= c) break;
-        const bool dag = act && dw[q] == nd[q];
-        if (dag && so[q] + sv < so[q]) {
+      for (int u = 0; u < kWU; ++u) {
+        const bool dag = nd[u] != kInf && dw[u] == nd[u];
+        if (dag && so[u] + sv < so[u]) {
           ovf = true;
-          atomicOr(&S.ovl[g], 1ull << lane);
+          atomicOr(&S.ovl[g], bit);
         }
-        const ull rm = __ballot(dag && co[q] == 1u);
-        if (lane == q) {
-          my_rm = rm;
-          my_w = wq[q];
-        }
+        // the lane whose push completed the head's in-arcs marks it ready;
+        // the first mark of the head appends it to the next round
+        bool first = false;
+        if (dag && co[u] == 1u) first = atomicOr(&nxt[gbase + wq[u]], bit) == 0ull;
+        stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + wq[u]), next_cnt, S.items, nbase, rend, &S.flags[1]);
       }
-      bool first = false;
-      if (my_rm != 0ull) first = atomicOr(&nxt[gbase + my_w], my_rm) == 0ull;
-      stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + my_w), next_cnt, S.items, nbase, rend, &S.flags[1]);
     }
   }
   stage_flush(stg, nst, next_cnt, S.items, nbase, rend, &S.flags[1]);
@@ -288,7 +331,10 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
 
 // Backward over topological round `level`: psi(v) = 1/sigma(v) + sum of
 // psi(w) over DAG out-arcs (v, w) of the lane; lanes pruned as in the
-// unweighted kernel.
+// unweighted kernel.  Lanes are compacted (compact_lanes) and each step
+// covers kWU arcs per slot; every source's sum still runs in arc order
+// (slot-ordered reads through lane shuffles), so the result does not depend
+// on how many lanes an item has.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int level, int ntgt, int full) {
   const uint64_t n = (uint64_t)S.n;
@@ -312,46 +358,53 @@ __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int l
     const bool need = ((mask >> lane) & 1ull) && (full || (uint32_t)level > tl || tg >= 0);
     const ull em = __ballot(need);
     if (em == 0ull) continue;
-    const uint32_t dv = need ? S.wd[(uint64_t)it * kLanes + lane] : kInf;
+    const Compact cp = compact_lanes(em, need);
+    const bool on = cp.slot < cp.slots;
+    const uint64_t vrow = (uint64_t)it * kLanes + (uint32_t)cp.src;
+    const uint32_t dv = on ? S.wd[vrow] : kInf;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
+    const int64_t stepw = (int64_t)cp.slots * kWU;
     double acc = 0.0;
-    for (int64_t e = e0; e < e1; e += 8) {
-      const int c = (int)((e1 - e) < 8 ? (e1 - e) : 8);
-      uint32_t wq[8], nd[8], dw[8];
+    for (int64_t e = e0; e < e1; e += stepw) {
+      uint32_t wq[kWU], nd[kWU], dw[kWU];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        wq[q] = 0u;
-        nd[q] = kInf;
-        if (q < c) {
-          wq[q] = (uint32_t)G.col[e + q];
-          nd[q] = dv + G.w[e + q];
+      for (int u = 0; u < kWU; ++u) {
+        const int64_t ea = e + (int64_t)u * cp.slots + cp.slot;
+        wq[u] = 0u;
+        nd[u] = kInf;
+        if (on && ea < e1) {
+          wq[u] = (uint32_t)G.col[ea];
+          nd[u] = dv + G.w[ea];
         }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) dw[q] = (q < c && need) ? S.wd[(gbase + wq[q]) * kLanes + lane] : kInf - 1u;
-      double x[8];
+      for (int u = 0; u < kWU; ++u) dw[u] = nd[u] != kInf ? S.wd[(gbase + wq[u]) * kLanes + (uint32_t)cp.src] : kInf - 1u;
+      double x[kWU];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        x[q] = 0.0;
-        if (q < c && need && dw[q] == nd[q]) {
-          x[q] = S.psi[(gbase + wq[q]) * kLanes + lane];
+      for (int u = 0; u < kWU; ++u) {
+        x[u] = 0.0;
+        if (nd[u] != kInf && dw[u] == nd[u]) {
+          x[u] = S.psi[(gbase + wq[u]) * kLanes + (uint32_t)cp.src];
           ++c_d;
         }
       }
-      // arc order is kept; 0.0 for arcs off the lane's DAG leaves acc unchanged
+      // arc e + u * slots + t is in slot t of step u: add in that order; 0.0
+      // for arcs off the lane's DAG (or past the row) leaves acc unchanged
 #pragma unroll
-      for (int q = 0; q < 8; ++q) acc += x[q];
+      for (int u = 0; u < kWU; ++u)
+        for (int t = 0; t < cp.slots; ++t) acc += __shfl(x[u], t * cp.A + cp.j);
     }
-    if (need) {
-      const double s = (double)S.sig[(uint64_t)it * kLanes + lane];
+    if (lane < cp.A) {
+      const uint64_t row = (uint64_t)it * kLanes + (uint32_t)cp.src;
+      const double s = (double)S.sig[row];
       const double dl = s * acc;
-      S.psi[(uint64_t)it * kLanes + lane] = acc + 1.0 / s;
-      if (S.dout) S.dout[(uint64_t)it * kLanes + lane] = dl;
-      if (tg >= 0 && tg < ntgt) S.res[((uint64_t)tg * S.G + g) * kLanes + lane] = (level > 0) ? dl : 0.0;
+      S.psi[row] = acc + 1.0 / s;
+      if (S.dout) S.dout[row] = dl;
+      if (tg >= 0 && tg < ntgt) S.res[((uint64_t)tg * S.G + g) * kLanes + (uint32_t)cp.src] = (level > 0) ? dl : 0.0;
     }
     if (lane == 0) {
-      c_v += (uint64_t)__popcll(em);
-      c_a += (uint64_t)__popcll(em) * (uint64_t)(e1 - e0);
+      c_v += (uint64_t)cp.A;
+      c_a += (uint64_t)cp.A * (uint64_t)(e1 - e0);
     }
   }
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
