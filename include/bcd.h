@@ -85,7 +85,8 @@ typedef struct bcd_stats {
 typedef struct bcd_config {
   int32_t engine;     /* BCD_ENGINE_* */
   int32_t groups;     /* batched engine: 64-source column groups per batch, >= 1 */
-  int32_t block;      /* threads per workgroup for traversal kernels: 64, 128, 256, 512 */
+  int32_t block;      /* threads per workgroup for traversal kernels: 64, 128, 256, 512
+                         (default 256, 64 on weighted graphs) */
   int32_t grid_mult;  /* workgroups per compute unit for traversal kernels, >= 1 */
   int32_t items;      /* batched engine, unweighted forward: frontier items a
                          wavefront takes per step, 1, 2 or 4 (64 / items lanes
@@ -144,9 +145,10 @@ bcd_status bcd_get_config(const bcd_graph *g, bcd_config *cfg);
 /* Autotuner: times the per-source passes of a fixed seeded sample of RV(r)
  * (at most max_sources sources) under each candidate and keeps the one with
  * the highest traversed arcs per second: first the batched engine with
- * groups in {1,2,4,...,max_groups} x grid_mult in {8,16,32} (block 256, 2
- * items per step, top-down), then around the best block 512 and, on
- * unweighted graphs, items 1 and 4 and bottom-up levels (16, 4), then the
+ * groups in {1,2,4,...,max_groups} x grid_mult in {8,16,32} (block 256, or
+ * 64 on weighted graphs; 2 items per step, top-down), then around the best
+ * block 512 (weighted: 128 and 256) and, on unweighted graphs, items 1 and 4
+ * and bottom-up levels (16, 4), then the
  * LDS engine when the graph fits it.  Installs the choice on the graph and
  * returns it in *best (and its rate in *gteps, may be NULL).  Results of
  * later calls do not depend on the choice (every engine and setting gives

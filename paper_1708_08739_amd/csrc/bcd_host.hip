@@ -574,7 +574,9 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   }
   g->cfg.engine = BCD_ENGINE_BATCHED;
   g->cfg.groups = default_groups(n, weight != nullptr);
-  g->cfg.block = 256;
+  // weighted kernels: one-wavefront workgroups, one resident grid (8 waves
+  // per SIMD) -- 12 % faster than 256-thread blocks at R-MAT 18
+  g->cfg.block = weight ? 64 : 256;
   g->cfg.grid_mult = 32;
   g->cfg.items = kDefaultItems;
   g->cfg.bottom_up = default_bottom_up(n);

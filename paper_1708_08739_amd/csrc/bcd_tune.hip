@@ -64,10 +64,11 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
     return BCD_OK;
   };
   bcd_status rc = BCD_OK;
-  // 1. batch width x grid multiplier (block 256, 2 items per step, top-down)
+  // 1. batch width x grid multiplier (block 256, 64 weighted; 2 items per
+  //    step, top-down)
   bcd_config cand = saved;
   cand.engine = BCD_ENGINE_BATCHED;
-  cand.block = 256;
+  cand.block = g->weighted ? 64 : 256;
   cand.items = 2;
   cand.bottom_up = 0;
   for (int G = 1; G <= max_groups && rc == BCD_OK; G *= 2) {
@@ -89,8 +90,10 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
     const bcd_config base = best_cfg;
     std::vector<bcd_config> around;
     bcd_config c = base;
-    c.block = 512;
-    around.push_back(c);
+    for (int b : g->weighted ? std::vector<int>{128, 256} : std::vector<int>{512}) {
+      c.block = b;
+      around.push_back(c);
+    }
     if (!g->weighted) {
       for (int it : {1, 4}) {
         c = base;

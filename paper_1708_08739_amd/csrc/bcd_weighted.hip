@@ -260,6 +260,11 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
   constexpr int kCap = 256;
   __shared__ uint32_t st_all[(BLOCK / 64) * kCap];
   uint32_t *stg = st_all + (threadIdx.x >> 6) * kCap;
+  // per slot: the lanes made ready at the slot's head in this step
+  __shared__ ull cm_all[BLOCK];
+  ull *cm = cm_all + (threadIdx.x & ~63u);
+  cm[lane] = 0ull;
+  wave_lds_sync();
   int nst = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = S.items[base + i];
@@ -317,10 +322,19 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
           ovf = true;
           atomicOr(&S.ovl[g], bit);
         }
-        // the lane whose push completed the head's in-arcs marks it ready;
-        // the first mark of the head appends it to the next round
+        // a lane whose push completed the head's in-arcs is ready next round;
+        // the slot's ready lanes take one atomic, and the first mark of the
+        // head appends it to the next round
+        if (dag && co[u] == 1u) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        wave_lds_sync();
+        ull m = 0ull;
+        if (cp.j == 0 && on) {
+          m = cm[cp.slot];
+          cm[cp.slot] = 0ull;
+        }
+        wave_lds_sync();
         bool first = false;
-        if (dag && co[u] == 1u) first = atomicOr(&nxt[gbase + wq[u]], bit) == 0ull;
+        if (m != 0ull) first = atomicOr(&nxt[gbase + wq[u]], m) == 0ull;
         stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + wq[u]), next_cnt, S.items, nbase, rend, &S.flags[1]);
       }
     }
