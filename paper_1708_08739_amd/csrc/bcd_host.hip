@@ -304,8 +304,9 @@ bcd_status Workspace::grow_items() {
   return BCD_OK;
 }
 
-// Full reset after an aborted batch (item list overflow): the sparse cleanup
-// cannot see items that were never stored.
+// Full reset after an aborted batch (item list overflow, or a host exception
+// in a server worker): the sparse cleanup cannot see items that were never
+// stored.
 bcd_status Workspace::reset_batch_dense() {
   const size_t GN = (size_t)G * (size_t)n;
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
@@ -315,6 +316,13 @@ bcd_status Workspace::reset_batch_dense() {
   HIPCHK(hipMemsetAsync(S.cnt, 0, ((size_t)n + kLevelChunkMax + 4) * kMaxParts * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));
+  if (weighted_ready) {
+    HIPCHK(hipMemsetAsync(S.wd, 0xFF, GN * kLanes * sizeof(uint32_t), stream));
+    HIPCHK(hipMemsetAsync(S.wc, 0, GN * kLanes * sizeof(uint32_t), stream));
+    HIPCHK(hipMemsetAsync(S.chg, 0, 2 * GN * sizeof(unsigned long long), stream));
+    HIPCHK(hipMemsetAsync(S.bqn, 0, 4 * sizeof(uint32_t), stream));
+    HIPCHK(hipMemsetAsync(S.rln, 0, sizeof(uint32_t), stream));
+  }
   HIPCHK(hipStreamSynchronize(stream));
   return BCD_OK;
 }
@@ -485,6 +493,7 @@ const char *bcd_status_string(bcd_status s) {
 const char *bcd_last_error(void) { return t_last_error.c_str(); }
 
 bcd_status bcd_sample_count(double eps_abs, double delta, double K, int64_t rv_size, int64_t *T) {
+  BCD_GUARD_BEGIN
   if (!T) return fail(BCD_ERR_INVALID_ARG, "T is NULL");
   if (!(eps_abs > 0.0) || !std::isfinite(eps_abs)) return fail(BCD_ERR_INVALID_ARG, "eps must be > 0");
   if (!(delta > 0.0 && delta < 1.0)) return fail(BCD_ERR_INVALID_ARG, "delta must be in (0,1)");
@@ -499,10 +508,12 @@ bcd_status bcd_sample_count(double eps_abs, double delta, double K, int64_t rv_s
   if (!(c >= 1.0L)) c = 1.0L;
   *T = (c >= 9.2e18L) ? INT64_MAX : (int64_t)c;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col,
                               const uint32_t *weight, bcd_graph **out) {
+  BCD_GUARD_BEGIN
   if (!out) return fail(BCD_ERR_INVALID_ARG, "out is NULL");
   if (n <= 0 || n >= (1ll << 31)) return fail(BCD_ERR_INVALID_ARG, "n must be in [1, 2^31)");
   if (m < 0 || m >= (1ll << 32)) return fail(BCD_ERR_INVALID_ARG, "m must be in [0, 2^32)");
@@ -582,24 +593,30 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->cfg.bottom_up = default_bottom_up(n);
   *out = reinterpret_cast<bcd_graph *>(g.release());
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_graph_free(bcd_graph *g) {
+  BCD_GUARD_BEGIN
   if (!g) return BCD_OK;
   delete reinterpret_cast<Graph *>(g);
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_graph_info(const bcd_graph *gh, int64_t *n, int64_t *m, int32_t *weighted) {
+  BCD_GUARD_BEGIN
   if (!gh) return fail(BCD_ERR_INVALID_ARG, "graph is NULL");
   const Graph *g = reinterpret_cast<const Graph *>(gh);
   if (n) *n = g->n;
   if (m) *m = g->m;
   if (weighted) *weighted = g->weighted ? 1 : 0;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
+  BCD_GUARD_BEGIN
   if (!gh || !cfg) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = reinterpret_cast<Graph *>(gh);
   if (cfg->engine != BCD_ENGINE_BATCHED && cfg->engine != BCD_ENGINE_PLAIN && cfg->engine != BCD_ENGINE_LDS)
@@ -618,15 +635,19 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
   if (g->cfg.items == 0) g->cfg.items = kDefaultItems;
   if (g->cfg.bottom_up < 0) g->cfg.bottom_up = default_bottom_up(g->n);
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_get_config(const bcd_graph *gh, bcd_config *cfg) {
+  BCD_GUARD_BEGIN
   if (!gh || !cfg) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   *cfg = reinterpret_cast<const Graph *>(gh)->config();
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_profile_enable(bcd_graph *gh, int32_t on) {
+  BCD_GUARD_BEGIN
   if (!gh) return fail(BCD_ERR_INVALID_ARG, "graph is NULL");
   Graph *g = reinterpret_cast<Graph *>(gh);
   if (on) {
@@ -635,9 +656,11 @@ bcd_status bcd_profile_enable(bcd_graph *gh, int32_t on) {
   }
   g->profiling.store(on != 0);
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_profile_get(const bcd_graph *gh, int32_t kind, bcd_kernel_profile *out) {
+  BCD_GUARD_BEGIN
   if (!gh || !out || kind < 0 || kind > 1) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   const Graph *g = reinterpret_cast<const Graph *>(gh);
   std::lock_guard<std::mutex> lk(g->prof_mu);
@@ -660,9 +683,11 @@ bcd_status bcd_profile_get(const bcd_graph *gh, int32_t kind, bcd_kernel_profile
   if (open) u += b - a;
   out->union_ms = u + g->prof_solo_ms[kind];
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_profile_reset(bcd_graph *gh) {
+  BCD_GUARD_BEGIN
   if (!gh) return fail(BCD_ERR_INVALID_ARG, "graph is NULL");
   Graph *g = reinterpret_cast<Graph *>(gh);
   std::lock_guard<std::mutex> lk(g->prof_mu);
@@ -673,9 +698,11 @@ bcd_status bcd_profile_reset(bcd_graph *gh) {
   }
   if (g->profiling.load()) STCHK(g->mark_profile_origin());
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
+  BCD_GUARD_BEGIN
   if (bytes < 1024 || reps < 1 || !gbps) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   STCHK(device_check(nullptr));
   const int64_t count = bytes / 8;
@@ -713,6 +740,7 @@ bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
   dfree(b);
   if (rc == BCD_OK) *gbps = best;
   return rc;
+  BCD_GUARD_END
 }
 
 }  // extern "C"

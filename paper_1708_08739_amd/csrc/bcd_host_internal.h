@@ -5,6 +5,7 @@
 #include <functional>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <utility>
 #include <vector>
@@ -24,6 +25,18 @@
     bcd_status _s = (expr);      \
     if (_s != BCD_OK) return _s; \
   } while (0)
+
+// Body of every exported call: a C++ exception (an allocation failure in
+// host code) becomes a status with its message; none crosses the C ABI.
+#define BCD_GUARD_BEGIN try {
+#define BCD_GUARD_END                                                   \
+  }                                                                     \
+  catch (const std::bad_alloc &) {                                      \
+    return bcd::fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed"); \
+  }                                                                     \
+  catch (...) {                                                         \
+    return bcd::fail(BCD_ERR_DEVICE, "unexpected host exception");     \
+  }
 
 namespace bcd {
 

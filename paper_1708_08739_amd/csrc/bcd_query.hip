@@ -468,14 +468,28 @@ bcd_status run_pipelined(Graph *g, Workspace *ws, size_t nbatches, const std::fu
     std::thread helper;
     try {
       helper = std::thread([&] {
-        rc2 = stripe(ws2, 1, 2, prof2, ovf2);
-        if (rc2 != BCD_OK) err2 = bcd_last_error();
+        try {
+          rc2 = stripe(ws2, 1, 2, prof2, ovf2);
+          if (rc2 != BCD_OK) err2 = bcd_last_error();
+        } catch (const std::bad_alloc &) {
+          rc2 = BCD_ERR_OUT_OF_MEMORY;
+          err2 = "host allocation failed";
+        } catch (...) {
+          rc2 = BCD_ERR_DEVICE;
+          err2 = "unexpected host exception";
+        }
       });
     } catch (...) {
       ws2 = nullptr;
     }
     if (ws2) {
-      const bcd_status rc1 = stripe(ws, 0, 2, prof, ovf);
+      bcd_status rc1 = BCD_OK;
+      try {
+        rc1 = stripe(ws, 0, 2, prof, ovf);
+      } catch (...) {  // the helper is joined before the exception goes on
+        helper.join();
+        throw;
+      }
       helper.join();
       STCHK(rc1);
       if (rc2 != BCD_OK) return fail(rc2, err2);
@@ -736,6 +750,7 @@ static bcd_status lease_ws(Graph *g, Lease &ls) {
 extern "C" {
 
 bcd_status bcd_rv(const bcd_graph *gh, bcd_vid r, bcd_vid *out, int64_t cap, int64_t *count) {
+  BCD_GUARD_BEGIN
   if (!gh || !count) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
@@ -756,9 +771,11 @@ bcd_status bcd_rv(const bcd_graph *gh, bcd_vid r, bcd_vid *out, int64_t cap, int
   }
   *count = k;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_bc_exact(const bcd_graph *gh, bcd_vid r, double *bc, bcd_stats *st) {
+  BCD_GUARD_BEGIN
   if (!gh || !bc) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
@@ -794,9 +811,11 @@ bcd_status bcd_bc_exact(const bcd_graph *gh, bcd_vid r, double *bc, bcd_stats *s
   *bc = v;
   if (st) *st = s;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_bc_set(const bcd_graph *gh, const bcd_vid *rs, int64_t l, double *bc, bcd_stats *st) {
+  BCD_GUARD_BEGIN
   if (!gh || !rs || !bc || l <= 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   for (int64_t i = 0; i < l; ++i)
@@ -842,9 +861,11 @@ bcd_status bcd_bc_set(const bcd_graph *gh, const bcd_vid *rs, int64_t l, double 
     *st = s;
   }
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_params *p, double *bc, bcd_stats *st) {
+  BCD_GUARD_BEGIN
   if (!gh || !p || !bc) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
@@ -938,19 +959,23 @@ bcd_status bcd_bc_sampled(const bcd_graph *gh, bcd_vid r, const bcd_sample_param
   s.t_bc_s = now_s() - t1;
   if (st) *st = s;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_bc_bcd(const bcd_graph *gh, bcd_vid r, int64_t tau, uint64_t seed, double *bc, bcd_stats *st) {
+  BCD_GUARD_BEGIN
   if (tau < 1) return fail(BCD_ERR_INVALID_ARG, "tau must be >= 1");
   // T = tau draws, and the exact sum whenever |RV(r)| <= tau (T >= |RV| fallback)
   bcd_sample_params p{};
   p.seed = seed;
   p.T_override = tau;
   return bcd_bc_sampled(gh, r, &p, bc, st);
+  BCD_GUARD_END
 }
 
 bcd_status bcd_dependencies(const bcd_graph *gh, bcd_vid r, const bcd_vid *sources, int64_t k, double *dep,
                             uint64_t *counters) {
+  BCD_GUARD_BEGIN
   if (!gh || (k > 0 && (!sources || !dep)) || k < 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
@@ -972,10 +997,12 @@ bcd_status bcd_dependencies(const bcd_graph *gh, bcd_vid r, const bcd_vid *sourc
       for (int j = 0; j < 3; ++j) counters[i * 3 + j] = run.counters[u * 3 + j];
   }
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_multi_source_pass(const bcd_graph *gh, const bcd_vid *sources, int64_t k, uint64_t *dist,
                                  uint64_t *sigma, double *delta) {
+  BCD_GUARD_BEGIN
   if (!gh || !sources || k <= 0) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   if (g->config().engine == BCD_ENGINE_LDS) {
@@ -1047,9 +1074,11 @@ bcd_status bcd_multi_source_pass(const bcd_graph *gh, const bcd_vid *sources, in
   if (rc == BCD_OK) rc = collect_counters(ws, c, ws->S.acc);
   if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return rc;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_source_pass(const bcd_graph *gh, bcd_vid s, uint64_t *dist, uint64_t *sigma, double *delta) {
+  BCD_GUARD_BEGIN
   if (!gh) return fail(BCD_ERR_INVALID_ARG, "graph is NULL");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   if (s < 0 || s >= g->n) return fail(BCD_ERR_INVALID_ARG, "s out of range");
@@ -1089,6 +1118,7 @@ bcd_status bcd_source_pass(const bcd_graph *gh, bcd_vid s, uint64_t *dist, uint6
   if (rc == BCD_OK) rc = collect_counters(ws, c, ws->P.acc);
   if (rc == BCD_OK && ovf) rc = fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return rc;
+  BCD_GUARD_END
 }
 
 }  // extern "C"

@@ -210,8 +210,15 @@ static void planner_loop(bcd_server *S) {
       S->submitted.pop_front();
     }
     const double t0 = steady_now();
-    bcd_status rc = plan_query(S, ws, *q);
-    if (rc == BCD_OK) rc = source_order(S->g, ws, q->sources, q->order);
+    bcd_status rc = BCD_OK;
+    try {
+      rc = plan_query(S, ws, *q);
+      if (rc == BCD_OK) rc = source_order(S->g, ws, q->sources, q->order);
+    } catch (const std::bad_alloc &) {
+      rc = fail(BCD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+      rc = fail(BCD_ERR_DEVICE, "unexpected host exception");
+    }
     q->res.stats.t_rv_s = steady_now() - t0;
     const size_t cells = q->sources.size() * q->targets.size();
     q->bytes = std::max<size_t>(cells, 1) * sizeof(double);
@@ -285,6 +292,7 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
   for (;;) {
     std::vector<Lane> lanes;
     std::vector<int32_t> tg;  // distinct targets of the batch
+    bcd_status rc = BCD_OK;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] {
@@ -294,82 +302,111 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
         return false;
       });
       if (S->stop) return;
-      std::unordered_map<int32_t, size_t> where;
-      for (auto &q : S->active) {
-        while (q->next < q->sources.size() && lanes.size() < width) {
-          const uint32_t slot = q->order[q->next];
-          const int32_t s = q->sources[slot];
-          auto it = where.find(s);
-          if (it == where.end()) {
-            where.emplace(s, lanes.size());
-            lanes.push_back(Lane{s, {}});
-            it = where.find(s);
+      // an exception here (host allocation) fails the lanes taken so far
+      try {
+        std::unordered_map<int32_t, size_t> where;
+        for (auto &q : S->active) {
+          while (q->next < q->sources.size() && lanes.size() < width) {
+            const uint32_t slot = q->order[q->next];
+            const int32_t s = q->sources[slot];
+            auto it = where.find(s);
+            if (it == where.end()) {
+              where.emplace(s, lanes.size());
+              lanes.push_back(Lane{s, {}});
+              it = where.find(s);
+            }
+            lanes[it->second].users.emplace_back(q, slot);
+            q->next++;
           }
-          lanes[it->second].users.emplace_back(q, slot);
-          q->next++;
+          if (lanes.size() >= width) break;
         }
-        if (lanes.size() >= width) break;
+        for (auto &ln : lanes)
+          for (auto &u : ln.users)
+            for (int32_t t : u.first->targets) tg.push_back(t);
+      } catch (const std::bad_alloc &) {
+        rc = BCD_ERR_OUT_OF_MEMORY;
+      } catch (...) {
+        rc = BCD_ERR_DEVICE;
       }
-      for (auto &ln : lanes)
-        for (auto &u : ln.users)
-          for (int32_t t : u.first->targets) tg.push_back(t);
     }
-    std::sort(tg.begin(), tg.end());
-    tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
-    // stage the batch
     const int k = (int)lanes.size();
-    {
-      std::vector<int32_t> bsrc((size_t)k);
-      for (int i = 0; i < k; ++i) bsrc[(size_t)i] = lanes[(size_t)i].vertex;
-      ws->stage_sources(bsrc.data(), k);
-    }
-    const int ntgt = (int)tg.size();
-    bcd_status rc = ws->ensure_res((size_t)std::max(ntgt, 1) * width);
     int32_t *d_t = nullptr;
     ResultRoute *d_routes = nullptr;
-    std::vector<ResultRoute> routes;
-    for (int i = 0; i < k; ++i)
-      for (auto &u : lanes[(size_t)i].users) {
-        SQuery &q = *u.first;
-        const size_t nt = q.targets.size();
-        for (size_t ti = 0; ti < nt; ++ti) {
-          const size_t t = (size_t)(std::lower_bound(tg.begin(), tg.end(), q.targets[ti]) - tg.begin());
-          ResultRoute rr;
-          rr.dst = q.dres + (size_t)u.second * nt + ti;
-          rr.src = (uint32_t)(t * width + (size_t)i);
-          rr.pad = 0;
-          routes.push_back(rr);
-        }
-      }
-    if (rc == BCD_OK && (hipMalloc((void **)&d_t, (size_t)std::max(ntgt, 1) * sizeof(int32_t)) != hipSuccess ||
-                         hipMalloc((void **)&d_routes, std::max<size_t>(routes.size(), 1) * sizeof(ResultRoute)) !=
-                             hipSuccess)) {
-      (void)hipGetLastError();
-      rc = BCD_ERR_OUT_OF_MEMORY;
-    }
-    if (rc == BCD_OK) {
-      hipError_t e = hipMemcpyAsync(d_t, tg.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(d_routes, routes.data(), routes.size() * sizeof(ResultRoute), hipMemcpyHostToDevice,
-                           ws->stream);
-      if (e == hipSuccess) e = launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 1, ws->stream);
-      if (e != hipSuccess) rc = BCD_ERR_DEVICE;
-    }
     bool ovf = false;
-    if (rc == BCD_OK) rc = run_staged_batch(g, ws, k, ntgt, ovl.data(), &ovf);
-    if (rc == BCD_OK) {
-      hipError_t e = launch_route_results(ws->S.res, d_routes, (int)routes.size(), ws->stream);
-      if (e == hipSuccess) e = hipStreamSynchronize(ws->stream);
-      if (e != hipSuccess) rc = BCD_ERR_DEVICE;
-    }
-    if (d_t) {
-      (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
-      (void)hipStreamSynchronize(ws->stream);
-      (void)hipFree(d_t);
-    }
-    if (d_routes) (void)hipFree(d_routes);
     uint64_t ctr[C_COUNT] = {0};
-    if (rc == BCD_OK) rc = collect_counters(ws, ctr, ws->S.acc);
+    int ntgt = 0;
+    bool threw = false;
+    try {
+      if (rc == BCD_OK) {
+        std::sort(tg.begin(), tg.end());
+        tg.erase(std::unique(tg.begin(), tg.end()), tg.end());
+        // stage the batch
+        {
+          std::vector<int32_t> bsrc((size_t)k);
+          for (int i = 0; i < k; ++i) bsrc[(size_t)i] = lanes[(size_t)i].vertex;
+          ws->stage_sources(bsrc.data(), k);
+        }
+        ntgt = (int)tg.size();
+        rc = ws->ensure_res((size_t)std::max(ntgt, 1) * width);
+        std::vector<ResultRoute> routes;
+        for (int i = 0; i < k; ++i)
+          for (auto &u : lanes[(size_t)i].users) {
+            SQuery &q = *u.first;
+            const size_t nt = q.targets.size();
+            for (size_t ti = 0; ti < nt; ++ti) {
+              const size_t t = (size_t)(std::lower_bound(tg.begin(), tg.end(), q.targets[ti]) - tg.begin());
+              ResultRoute rr;
+              rr.dst = q.dres + (size_t)u.second * nt + ti;
+              rr.src = (uint32_t)(t * width + (size_t)i);
+              rr.pad = 0;
+              routes.push_back(rr);
+            }
+          }
+        if (rc == BCD_OK && (hipMalloc((void **)&d_t, (size_t)std::max(ntgt, 1) * sizeof(int32_t)) != hipSuccess ||
+                             hipMalloc((void **)&d_routes, std::max<size_t>(routes.size(), 1) * sizeof(ResultRoute)) !=
+                                 hipSuccess)) {
+          (void)hipGetLastError();
+          rc = BCD_ERR_OUT_OF_MEMORY;
+        }
+        if (rc == BCD_OK) {
+          hipError_t e = hipMemcpyAsync(d_t, tg.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(d_routes, routes.data(), routes.size() * sizeof(ResultRoute), hipMemcpyHostToDevice,
+                               ws->stream);
+          if (e == hipSuccess) e = launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 1, ws->stream);
+          if (e != hipSuccess) rc = BCD_ERR_DEVICE;
+        }
+        if (rc == BCD_OK) rc = run_staged_batch(g, ws, k, ntgt, ovl.data(), &ovf);
+        if (rc == BCD_OK) {
+          hipError_t e = launch_route_results(ws->S.res, d_routes, (int)routes.size(), ws->stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(ws->stream);
+          if (e != hipSuccess) rc = BCD_ERR_DEVICE;
+        }
+        if (d_t) {
+          (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
+          (void)hipStreamSynchronize(ws->stream);
+          (void)hipFree(d_t);
+        }
+        if (d_routes) (void)hipFree(d_routes);
+        d_t = nullptr;
+        d_routes = nullptr;
+        if (rc == BCD_OK) rc = collect_counters(ws, ctr, ws->S.acc);
+      }
+    } catch (const std::bad_alloc &) {
+      rc = BCD_ERR_OUT_OF_MEMORY;
+      threw = true;
+    } catch (...) {
+      rc = BCD_ERR_DEVICE;
+      threw = true;
+    }
+    if (threw) {  // leave the workspace as a finished batch would
+      (void)hipStreamSynchronize(ws->stream);
+      if (d_t) (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
+      (void)ws->reset_batch_dense();
+      (void)hipStreamSynchronize(ws->stream);
+      if (d_t) (void)hipFree(d_t);
+      if (d_routes) (void)hipFree(d_routes);
+    }
     // account
     std::vector<std::shared_ptr<SQuery>> complete;
     {
@@ -440,15 +477,18 @@ extern "C" {
 double bcd_server_now(void) { return steady_now(); }
 
 bcd_status bcd_server_workspace_bytes(const bcd_graph *gh, int32_t groups, int32_t workers, uint64_t *bytes) {
+  BCD_GUARD_BEGIN
   if (!gh || !bytes) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   const Graph *g = reinterpret_cast<const Graph *>(gh);
   if (groups <= 0) groups = g->config().groups;
   if (workers <= 0) workers = 2;
   *bytes = batch_workspace_bytes(g, groups) * (uint64_t)workers;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_server_create(const bcd_graph *gh, const bcd_server_config *cfg, bcd_server **out) {
+  BCD_GUARD_BEGIN
   if (!gh || !out) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = const_cast<Graph *>(reinterpret_cast<const Graph *>(gh));
   std::unique_ptr<bcd_server> S(new (std::nothrow) bcd_server());
@@ -499,9 +539,11 @@ bcd_status bcd_server_create(const bcd_graph *gh, const bcd_server_config *cfg, 
   }
   *out = S.release();
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_server_submit(bcd_server *S, const bcd_query *q, uint64_t *ticket) {
+  BCD_GUARD_BEGIN
   if (!S || !q || !ticket) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   Graph *g = S->g;
   if (q->kind == BCD_QUERY_EXACT || q->kind == BCD_QUERY_SAMPLED) {
@@ -535,9 +577,11 @@ bcd_status bcd_server_submit(bcd_server *S, const bcd_query *q, uint64_t *ticket
   S->cv_plan.notify_all();
   *ticket = sq->ticket;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_server_poll(bcd_server *S, bcd_result *out, int32_t cap, int32_t *n_out, int64_t timeout_ns) {
+  BCD_GUARD_BEGIN
   if (!S || !out || cap <= 0 || !n_out) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   std::unique_lock<std::mutex> lk(S->mu);
   if (S->finished.empty() && timeout_ns != 0) {
@@ -553,16 +597,20 @@ bcd_status bcd_server_poll(bcd_server *S, bcd_result *out, int32_t cap, int32_t 
   *n_out = k;
   if (k == 0) return fail(BCD_ERR_AGAIN, "no result ready");
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_server_get_stats(bcd_server *S, bcd_server_stats *out) {
+  BCD_GUARD_BEGIN
   if (!S || !out) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
   *out = S->stats;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 bcd_status bcd_server_destroy(bcd_server *S) {
+  BCD_GUARD_BEGIN
   if (!S) return BCD_OK;
   {
     std::lock_guard<std::mutex> lk(S->mu);
@@ -581,6 +629,7 @@ bcd_status bcd_server_destroy(bcd_server *S) {
   S->submitted.clear();
   delete S;
   return BCD_OK;
+  BCD_GUARD_END
 }
 
 }  // extern "C"

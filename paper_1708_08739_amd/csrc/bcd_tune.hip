@@ -13,6 +13,7 @@ using namespace bcd;
 
 extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups, int64_t max_sources,
                                    bcd_config *best, double *gteps) {
+  BCD_GUARD_BEGIN
   if (!gh || !best || max_groups < 1 || max_sources < 1) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   Graph *g = reinterpret_cast<Graph *>(gh);
   if (r < 0 || r >= g->n) return fail(BCD_ERR_INVALID_ARG, "r out of range");
@@ -131,4 +132,5 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
   *best = best_cfg;
   if (gteps) *gteps = best_rate;
   return BCD_OK;
+  BCD_GUARD_END
 }
