@@ -73,6 +73,38 @@ def measured_traffic(kernel: str, workload_name: str, batch_width: int):
     return float(rec["bytes_per_launch"])
 
 
+def roofline_from_profile(G, fwd: dict, bwd: dict, ename: str, wname: str):
+    """HBM roofline of the dominant pass from the library's kernel profile:
+    algorithmic bytes over the busy time of its launches."""
+    if fwd["launches"] == 0:
+        return None
+    dom, kind = (fwd, "forward") if fwd["total_ms"] >= bwd["total_ms"] else (bwd, "backward")
+    # Pipelined batches run launches of this kernel on two streams at once, so their
+    # event durations overlap: the rate is taken over the union of the launch intervals
+    # (each instant counted once); the per-launch average is kept beside it.
+    busy_ms = dom["union_ms"] if dom["union_ms"] > 0 else dom["total_ms"]
+    achieved = dom["alg_bytes"] / (busy_ms * 1e-3) / 1e9
+    per_launch = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+    if G.info()[2]:
+        # weighted engine: the forward is three kernels (relaxation rounds, DAG
+        # in-degrees, topological rounds), profiled together
+        kname = "k_w_relax+k_w_count+k_w_sigma" if kind == "forward" else "k_w_bwd"
+    elif ename == "lds":
+        kname = "k_lds_pass"  # both passes in one kernel, timed as the forward
+    else:
+        kname = f"k_{'fwd' if kind == 'forward' else 'bwd'}_level"
+    traffic = measured_traffic(kname, wname, 64 * G.config().groups if ename == "batched" else 1)
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic, 1),
+            "kernel": kname,
+            "launches": dom["launches"], "avg_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2),
+            "alg_bytes_per_launch": round(dom["alg_bytes"] / dom["launches"], 1),
+            "launch_union_ms": round(busy_ms, 3), "launch_sum_ms": round(dom["total_ms"], 3),
+            "per_launch_achieved": round(per_launch, 2),
+            "lanes_per_item": round(dom["vertex_pairs"] / dom["items"], 2) if dom["items"] else None}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -116,6 +148,7 @@ def run_weighted(G, g, queries, args):
     if args.autotune:
         cfg, rate = G.autotune(queries[0], max_groups=8, max_sources=2048)
         log(f"[bench] autotune: groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult} ({rate:.2f} GTEPS)")
+        G.profile_reset()
     t0 = time.perf_counter()
     bcs, st = G.bc_set(queries[:4])
     te = st["traversed_edges"]
@@ -342,6 +375,9 @@ def main():
 
     if args.workload in ("rmat18w", "rmat20set", "rmat20dagset", "rmat22serve", "rmat16bcd"):
         extra = {}
+        if not args.no_profile and args.workload != "rmat22serve":
+            G.profile_reset()
+            G.profile_enable(True)
         if args.workload == "rmat18w":
             te, wall, lat = run_weighted(G, g, queries, args)
         elif args.workload == "rmat20set":
@@ -350,6 +386,7 @@ def main():
             if args.autotune:
                 c2, rate = G.autotune(qs[int(np.argmax(sizes))], max_groups=8, max_sources=2048)
                 log(f"[bench] autotune: groups={c2.groups} ({rate:.2f} GTEPS)")
+                G.profile_reset()
             t0 = time.perf_counter()
             bcs, st = G.bc_set(qs)
             wall = time.perf_counter() - t0
@@ -360,6 +397,7 @@ def main():
             sizes = [len(G.rv(r)) for r in qs]
             log(f"[bench] set of {len(qs)}: |RV| from {min(sizes)} to {max(sizes)}")
             G.bc_set(qs[:8])  # warm-up: workspace and hub signatures
+            G.profile_reset()
             lat = []
             te = 0
             t0 = time.perf_counter()
@@ -380,6 +418,10 @@ def main():
             srv = serve(G, g, args)
             te, wall, lat = srv["saturation"]["gteps"] * 1e9 * srv["saturation"]["wall_s"], srv["saturation"]["wall_s"], [0]
             extra = {"serving": srv}
+        if not args.no_profile and args.workload != "rmat22serve":
+            G.profile_enable(False)
+            extra["roofline"] = roofline_from_profile(G, G.profile(0), G.profile(1), ename, wname)
+            log(f"[bench] roofline: {extra['roofline']}")
         if not args.no_cpu:
             # the oracle on a bounded sample of one query's sources: for the set,
             # its largest RV; for serving, the first query vertex
@@ -435,26 +477,7 @@ def main():
     fwd = G.profile(0)
     bwd = G.profile(1)
 
-    roofline = None
-    if not args.no_profile and fwd["launches"] > 0:
-        dom, kind = (fwd, "forward") if fwd["total_ms"] >= bwd["total_ms"] else (bwd, "backward")
-        # Pipelined batches run launches of this kernel on two streams at once, so their
-        # event durations overlap: the rate is taken over the union of the launch intervals
-        # (each instant counted once); the per-launch average is kept beside it.
-        busy_ms = dom["union_ms"] if dom["union_ms"] > 0 else dom["total_ms"]
-        achieved = dom["alg_bytes"] / (busy_ms * 1e-3) / 1e9
-        per_launch = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
-        # the LDS engine runs both passes in one kernel, timed as the forward
-        kname = "k_lds_pass" if ename == "lds" else f"k_{'fwd' if kind == 'forward' else 'bwd'}_level"
-        traffic = measured_traffic(kname, wname, 64 * G.config().groups if ename == "batched" else 1)
-        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None if traffic is None else round(traffic, 1),
-                    "kernel": kname,
-                    "launches": dom["launches"], "avg_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2),
-                    "alg_bytes_per_launch": round(dom["alg_bytes"] / dom["launches"], 1),
-                    "launch_union_ms": round(busy_ms, 3), "launch_sum_ms": round(dom["total_ms"], 3),
-                    "per_launch_achieved": round(per_launch, 2)}
+    roofline = None if args.no_profile else roofline_from_profile(G, fwd, bwd, ename, wname)
 
     # plain one-source-per-launch form on a sample of the same sources
     plain = None

@@ -210,6 +210,12 @@ class Graph:
     def from_digraph(cls, g):
         return cls(g.n, g.row_ptr, g.col, g.weight)
 
+    def info(self) -> tuple[int, int, bool]:
+        """(n, m, weighted) as the library holds them (``bcd_graph_info``)."""
+        n, m, w = C.c_int64(), C.c_int64(), C.c_int32()
+        check(load().bcd_graph_info(self.h, C.byref(n), C.byref(m), C.byref(w)), "bcd_graph_info")
+        return n.value, m.value, bool(w.value)
+
     def close(self):
         if getattr(self, "h", None):
             load().bcd_graph_free(self.h)
