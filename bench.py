@@ -207,8 +207,11 @@ def serve(G, g, args):
         tickets = {}
         for i, r in enumerate(qs):
             arrive += gaps[i]
-            while time.perf_counter() - t0 < arrive:
-                time.sleep(min(0.001, arrive - (time.perf_counter() - t0)))
+            while True:
+                rem = arrive - (time.perf_counter() - t0)
+                if rem <= 0:
+                    break
+                time.sleep(min(0.001, rem))
             tickets[S.submit(bcd.BCD_QUERY_SAMPLED, r=r, eps=0.01, delta=0.1, seed=305 + i)] = r
         res = []
         while len(res) < len(qs):
