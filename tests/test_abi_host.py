@@ -135,3 +135,38 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_bench_roofline_uses_busy_time():
+    """The benchmark's roofline divides algorithmic bytes by the union of the
+    launch intervals (overlapping launches on two streams count once), keeps
+    the per-launch average beside it, and names the weighted forward by its
+    three kernels."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class Stub:
+        def __init__(self, weighted):
+            self.w = weighted
+
+        def info(self):
+            return 10, 20, self.w
+
+        def config(self):
+            return bcd.Config(engine=bcd.BCD_ENGINE_BATCHED, groups=2, block=256, grid_mult=32, items=2,
+                              bottom_up=0)
+
+    fwd = {"launches": 4, "total_ms": 8.0, "union_ms": 5.0, "alg_bytes": 4e10, "vertex_pairs": 300, "items": 100}
+    bwd = {"launches": 4, "total_ms": 2.0, "union_ms": 1.5, "alg_bytes": 1e10, "vertex_pairs": 0, "items": 0}
+    r = bench.roofline_from_profile(Stub(False), fwd, bwd, "batched", "no-such-workload")
+    assert r["kernel"] == "k_fwd_level" and r["traffic"] is None
+    assert r["achieved"] == pytest.approx(4e10 / 5e-3 / 1e9)
+    assert r["per_launch_achieved"] == pytest.approx(4e10 / 8e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
+    assert r["avg_launch_us"] == pytest.approx(2000.0) and r["lanes_per_item"] == pytest.approx(3.0)
+    w = bench.roofline_from_profile(Stub(True), fwd, bwd, "batched", "no-such-workload")
+    assert w["kernel"] == "k_w_relax+k_w_count+k_w_sigma"
+    # the backward dominates when its launches took longer
+    b = bench.roofline_from_profile(Stub(False), bwd, fwd, "batched", "no-such-workload")
+    assert b["kernel"] == "k_bwd_level"
+    assert bench.roofline_from_profile(Stub(False), dict(fwd, launches=0), bwd, "batched", "x") is None
