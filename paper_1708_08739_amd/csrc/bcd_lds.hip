@@ -6,10 +6,13 @@
 // (the graph itself is read from L2).  Workgroups take sources in turn, so
 // one launch serves a whole source list.
 //
-// LDS per workgroup, for n vertices: sigma u64[n], psi f64[n], level u32[n],
-// the BFS queue u16[n] (vertices in level order) and the level starts
-// u16[n + 2]: 24 n bytes plus a little, so n is bounded by what one
-// workgroup may allocate (and below 2^16).
+// LDS per workgroup, for n vertices: sigma u64[n] (overwritten in place by
+// psi f64[n] in the backward: psi(v) is written only after sigma(v) has been
+// read, and only successors' psi are read), level u32[n], the BFS queue
+// u16[n] (vertices in level order) and the level starts u16[n + 2]: 16 n
+// bytes plus a little, so n is bounded by what one workgroup may allocate
+// (and below 2^16).  Sharing the sigma and psi words lets a CU hold five
+// workgroups of a 2,000-vertex graph instead of three.
 //
 // The graph stays in global memory (it is small enough to sit in L2): a
 // copy into each workgroup's LDS was measured slower, since it halves the
@@ -37,7 +40,7 @@ namespace bcd {
 constexpr uint32_t kUnseen = 0xFFFFFFFFu;
 constexpr int kLdsBlock = 256;
 
-size_t lds_bytes_for(int64_t n) { return (size_t)24 * (size_t)n + 64; }
+size_t lds_bytes_for(int64_t n) { return (size_t)16 * (size_t)n + 64; }
 
 bool lds_fits(const Graph *g) {
   return !g->weighted && g->n >= 1 && g->n < 65536 && lds_bytes_for(g->n) <= g->lds_block_bytes;
@@ -61,11 +64,12 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_lds_pass(DevGraph G, LdsArgs A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t n = (uint32_t)G.n;
+  // sigma, then (from the backward on) the bits of psi: one array of words,
+  // so no two pointer types alias
   ull *sig = reinterpret_cast<ull *>(smem);
-  double *psi = reinterpret_cast<double *>(smem + 8 * (size_t)n);
-  uint32_t *dist = reinterpret_cast<uint32_t *>(smem + 16 * (size_t)n);
-  uint16_t *queue = reinterpret_cast<uint16_t *>(smem + 20 * (size_t)n);
-  uint16_t *lstart = reinterpret_cast<uint16_t *>(smem + 22 * (size_t)n);  // [n + 2]
+  uint32_t *dist = reinterpret_cast<uint32_t *>(smem + 8 * (size_t)n);
+  uint16_t *queue = reinterpret_cast<uint16_t *>(smem + 12 * (size_t)n);
+  uint16_t *lstart = reinterpret_cast<uint16_t *>(smem + 14 * (size_t)n);  // [n + 2]
   __shared__ uint32_t s_tail, s_ovf, s_stop;
   __shared__ unsigned long long s_m, s_a;
   const uint32_t tid = threadIdx.x;
@@ -159,6 +163,14 @@ __global__ __launch_bounds__(BLOCK) void k_lds_pass(DevGraph G, LdsArgs A) {
       A.ovf[i] = s_ovf;
     }
     const uint32_t stop = s_stop;
+    if (A.xdist) {  // exports of the forward state, before psi takes sigma's words
+      for (uint32_t v = tid; v < n; v += BLOCK) {
+        const uint32_t d = dist[v];
+        A.xdist[(size_t)i * n + v] = d == kUnseen ? ~0ull : (uint64_t)d;
+        A.xsig[(size_t)i * n + v] = sig[v];
+      }
+    }
+    __syncthreads();
 
     // backward, deepest level first: psi(v) = 1/sigma(v) + sum of psi(w) over
     // out-arcs (v, w) with w one level deeper, in arc order
@@ -175,10 +187,10 @@ __global__ __launch_bounds__(BLOCK) void k_lds_pass(DevGraph G, LdsArgs A) {
             for (int j = 0; j < 4; ++j) wq[j] = (e + j < e1) ? (uint32_t)G.col[e + j] : kUnseen;
 #pragma unroll
             for (int j = 0; j < 4; ++j)  // arc order
-              if (wq[j] != kUnseen && dist[wq[j]] == (uint32_t)lv + 1u) acc += psi[wq[j]];
+              if (wq[j] != kUnseen && dist[wq[j]] == (uint32_t)lv + 1u) acc += __longlong_as_double((long long)sig[wq[j]]);
           }
           const double sv = (double)sig[v];
-          psi[v] = acc + 1.0 / sv;
+          sig[v] = (ull)__double_as_longlong(acc + 1.0 / sv);  // psi(v)
           const double dl = sv * acc;
           if (A.xdel) A.xdel[(size_t)i * n + v] = dl;
           if (A.ntgt > 0) {
@@ -187,13 +199,6 @@ __global__ __launch_bounds__(BLOCK) void k_lds_pass(DevGraph G, LdsArgs A) {
           }
         }
         __syncthreads();
-      }
-    }
-    if (A.xdist) {
-      for (uint32_t v = tid; v < n; v += BLOCK) {
-        const uint32_t d = dist[v];
-        A.xdist[(size_t)i * n + v] = d == kUnseen ? ~0ull : (uint64_t)d;
-        A.xsig[(size_t)i * n + v] = sig[v];
       }
     }
     __syncthreads();  // the next source overwrites the LDS state

@@ -320,6 +320,15 @@ def test_lds_engine_queries_and_limits(B, oracle):
         assert Gl.bc_exact(r)[0] == Gb.bc_exact(r)[0]
         assert Gl.bc_sampled(r, eps=0.05, seed=3)[0] == Gb.bc_sampled(r, eps=0.05, seed=3)[0]
 
+    # 8,000 vertices fit only because sigma and psi share their LDS words
+    # (16 n bytes per workgroup rather than 24 n)
+    g8 = gg.erdos_renyi(8000, 40000, seed=31)
+    r8 = gg.max_in_degree(g8)
+    got8, st8 = dev(B, g8, engine=B.BCD_ENGINE_LDS).bc_exact(r8)
+    want8, stw8 = dev(B, g8).bc_exact(r8)
+    print("lds n=8000", st8["rv_size"], got8, flush=True)
+    assert got8 == want8 and st8["traversed_edges"] == stw8["traversed_edges"]
+
     def with_rv(gx):
         ind, outd = gx.in_degree(), gx.out_degree()
         return next(v for v in gg.top_out_degree(gx, 50) if ind[v] > 0 and outd[v] > 0)
