@@ -23,7 +23,8 @@ struct __align__(16) LevMask {
 struct __align__(64) MaskRec {
   unsigned long long vis;    // lanes settled on a level < current (lagging, see the forward kernel)
   unsigned long long fr[4];  // rotating level masks: current, next, previous, retiring
-  unsigned long long pad[3];
+  unsigned long long dn;     // lanes on whose shortest-path DAG the vertex is a target or lies below one
+  unsigned long long pad[2];
 };
 
 // Counters accumulated per workgroup slot (no atomics), reduced on the host.

@@ -97,6 +97,22 @@ static __device__ __forceinline__ void pull_slots(const BatchState &S, uint64_t 
   }
 }
 
+// OR of x over the lanes of each item slot (lane l in slot l / (64 / K)),
+// into wave-uniform out[]; x must be set on every lane.
+template <int K>
+static __device__ __forceinline__ void or_slots(ull x, ull (&out)[K]) {
+  constexpr int SUB = kLanes / K;
+  ull b = __ballot(x != 0ull);
+  while (b != 0ull) {
+    const int j = __ffsll((long long)b) - 1;
+    b &= b - 1ull;
+    const ull v = read_lane64(x, j);
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if (j / SUB == t) out[t] |= v;
+  }
+}
+
 // Discovered heads are staged in a per-wavefront LDS buffer and copied to
 // the next level's list in blocks: one counter atomic per block instead of
 // one per out-arc chunk, which keeps the partition's tail counter cold.
@@ -260,7 +276,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
       lov[t] = false;
     }
     c_d += (uint64_t)__popcll(pm);
+    // a DAG tail's lanes that are a target or below one: the same record
+    // line as its level mask, loaded beside the predecessor rows
+    const ull pdn = pm != 0ull ? rec[gbase + u].dn : 0ull;
     pull_slots<K>(S, gbase, u, pm, lane, acc, lov, lov);
+    ull dnacc[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) dnacc[t] = 0ull;
+    or_slots<K>(pm & pdn, dnacc);
     append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, w, enq);
     // per item: the remaining arcs with the whole wavefront, then the path
     // counts and target levels of its lanes
@@ -277,10 +300,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
       for (int64_t e = F0 + SUB; e < F1; e += kLanes) {
         const int64_t my = e + lane;
         uint32_t uu = 0;
-        ull pp = 0ull;
+        ull pp = 0ull, pd = 0ull;
         if (my < F1) {
           uu = (uint32_t)G.icol[my];
           pp = rec[gbt + uu].fr[kp] & mt;
+          if (pp != 0ull) pd = rec[gbt + uu].dn;
         }
         c_d += (uint64_t)__popcll(pp);
         ull a1[1] = {acc[t]};
@@ -288,6 +312,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
         pull_slots<1>(S, gbt, uu, pp, lane, a1, l1, l1);
         acc[t] = a1[0];
         lov[t] = l1[0];
+        ull d1[1] = {0ull};
+        or_slots<1>(pp & pd, d1);
+        dnacc[t] |= d1[0];
       }
       for (int64_t e = E0 + SUB; e < E1; e += kLanes) {
         const int64_t my = e + lane;
@@ -303,10 +330,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
       }
       if (!pull) continue;
       const bool act = (mt >> lane) & 1ull;
-      if ((int32_t)read_lane((uint32_t)tg, ld) >= 0) {
-        if (act) atomicMin(&S.tlev[gt * kLanes + lane], (uint32_t)level);
-        if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
-      }
+      const bool is_tgt = (int32_t)read_lane((uint32_t)tg, ld) >= 0;
+      if (is_tgt && lane == 0) atomicMin(S.tmin, (uint32_t)level);
+      // the backward needs psi only on these lanes (a target's dependency
+      // depends only on what lies below it)
+      const ull dnt = dnacc[t] | (is_tgt ? mt : 0ull);
+      if (dnt != 0ull && lane == 0) rec[itt].dn = rec[itt].dn | dnt;
       if (level > 0) {
         if (act) S.sig[(uint64_t)itt * kLanes + lane] = acc[t];
         if (lov[t]) {
@@ -401,10 +430,11 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
       // first chunk of every slot's in-arcs
       const int64_t mi = F0 + sl;
       uint32_t u = 0;
-      ull pfr = 0ull;
+      ull pfr = 0ull, pdn = 0ull;
       if (mi < F1) {
         u = (uint32_t)G.icol[mi];
         pfr = rec[gbase + u].fr[kp];
+        pdn = rec[gbase + u].dn;
       }
       const ull pm = pfr & un;
       ull acc[K];
@@ -417,6 +447,10 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
       }
       c_d += (uint64_t)__popcll(pm);
       pull_slots<K, true>(S, gbase, u, pm, lane, acc, lov, hit);
+      ull dnacc[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) dnacc[t] = 0ull;
+      or_slots<K>(pm & pdn, dnacc);
 #pragma unroll
       for (int t = 0; t < K; ++t) {
         if (jc[t] < 0) continue;
@@ -425,10 +459,11 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
         for (int64_t e = G0 + SUB; e < G1; e += kLanes) {
           const int64_t my = e + lane;
           uint32_t uu = 0;
-          ull pp = 0ull;
+          ull pp = 0ull, pd = 0ull;
           if (my < G1) {
             uu = (uint32_t)G.icol[my];
             pp = rec[gbase + uu].fr[kp] & ut;
+            pd = rec[gbase + uu].dn;
           }
           c_d += (uint64_t)__popcll(pp);
           ull a1[1] = {acc[t]};
@@ -437,6 +472,9 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
           acc[t] = a1[0];
           lov[t] = l1[0];
           hit[t] = h1[0];
+          ull d1[1] = {0ull};
+          or_slots<1>(pp & pd, d1);
+          dnacc[t] |= d1[0];
         }
         const ull nm = __ballot(hit[t]);  // lanes of w on this level
         if (nm == 0ull) continue;
@@ -450,17 +488,16 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
           ovf = true;
           atomicOr(&S.ovl[g], 1ull << lane);
         }
+        const ull dnt = (dnacc[t] & nm) | (tg >= 0 ? nm : 0ull);
         if (lane == 0) {
           rec[it].fr[kc] = nm;
           rec[it].vis = rec[it].vis | nm;
+          if (dnt != 0ull) rec[it].dn = rec[it].dn | dnt;
           const uint64_t pc = (uint64_t)__popcll(nm);
           c_v += pc;
           c_a += pc * (uint64_t)(e1 - e0);
         }
-        if (tg >= 0) {
-          if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
-          if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
-        }
+        if (tg >= 0 && lane == 0) atomicMin(S.tmin, (uint32_t)level);
         append_chunk(S, stage, nst, cnt_here, base, rend, gbase, wt, lane == 0);
       }
     }
@@ -572,9 +609,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
       emv[t] = 0ull;
       sg[t] = 1ull;
       if (mt == 0ull) continue;
-      const uint32_t gt = read_lane(g, ld);
-      const uint32_t tl = S.tlev[gt * kLanes + lane];
-      const bool need = ((mt >> lane) & 1ull) && (full || (uint32_t)level > tl || (int32_t)read_lane((uint32_t)tg, ld) >= 0);
+      // lanes where v is a target or lies below one on the lane's DAG: a
+      // target's dependency reads psi only there
+      const ull dnt = S.rec[read_lane(it, ld)].dn;
+      const bool need = ((mt >> lane) & 1ull) && (full || ((dnt >> lane) & 1ull) || (int32_t)read_lane((uint32_t)tg, ld) >= 0);
       emv[t] = __ballot(need);
       if (need) sg[t] = S.sig[(uint64_t)read_lane(it, ld) * kLanes + lane];
     }
@@ -658,6 +696,7 @@ __global__ void k_batch_cleanup(BatchState S, PartTotals tot) {
       const uint32_t it = items[i];
       MaskRec &R = S.rec[it];
       R.vis = 0ull;
+      R.dn = 0ull;
 #pragma unroll
       for (int k = 0; k < 4; ++k) R.fr[k] = 0ull;
     }
