@@ -322,6 +322,7 @@ bcd_status Workspace::reset_batch_dense() {
     HIPCHK(hipMemsetAsync(S.chg, 0, 2 * GN * sizeof(unsigned long long), stream));
     HIPCHK(hipMemsetAsync(S.bqn, 0, 4 * sizeof(uint32_t), stream));
     HIPCHK(hipMemsetAsync(S.rln, 0, sizeof(uint32_t), stream));
+    HIPCHK(hipMemsetAsync(S.wdn, 0, GN * sizeof(unsigned long long), stream));
   }
   HIPCHK(hipStreamSynchronize(stream));
   return BCD_OK;

@@ -88,6 +88,7 @@ struct BatchState {
   uint32_t *bqn;             // [3] relaxation queue lengths (rotating)
   uint32_t *rl;              // [G*n] items reached by any lane
   uint32_t *rln;             // [1]
+  unsigned long long *wdn;   // [G][n] lanes on whose DAG the vertex is a target or lies below one
 };
 
 // Plain engine state (one source).

@@ -465,7 +465,7 @@ namespace bcd {
 uint64_t batch_workspace_bytes(const Graph *g, int groups) {
   const uint64_t GN = (uint64_t)groups * (uint64_t)g->n;
   uint64_t b = GN * kLanes * 16 + GN * 2 * sizeof(LevMask) + GN * 16 * 12 + (uint64_t)g->n * 24;
-  if (g->weighted) b += GN * kLanes * 8 + GN * 28 + GN * 4 * 8;
+  if (g->weighted) b += GN * kLanes * 8 + GN * 28 + GN * 5 * 8;
   else b += GN * sizeof(MaskRec);
   return b;
 }

@@ -264,10 +264,13 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
   constexpr int kCap = 256;
   __shared__ uint32_t st_all[(BLOCK / 64) * kCap];
   uint32_t *stg = st_all + (threadIdx.x >> 6) * kCap;
-  // per slot: the lanes made ready at the slot's head in this step
-  __shared__ ull cm_all[BLOCK];
+  // per slot: the lanes made ready at the slot's head in this step, and the
+  // lanes that reach it from a vertex that is a target or lies below one
+  __shared__ ull cm_all[BLOCK], cd_all[BLOCK];
   ull *cm = cm_all + (threadIdx.x & ~63u);
+  ull *cd = cd_all + (threadIdx.x & ~63u);
   cm[lane] = 0ull;
+  cd[lane] = 0ull;
   wave_lds_sync();
   int nst = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
@@ -278,17 +281,25 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
     const ull mask = cur[it];
     if (lane == 0) S.imask[base + i] = mask;
     const bool act = (mask >> lane) & 1ull;
-    if (S.tgt_of[v] >= 0) {
-      if (act) atomicMin(&S.tlev[g * kLanes + lane], (uint32_t)level);
-      if (lane == 0) atomicMin(S.tmin, (uint32_t)level);
-    }
+    const bool is_tgt = S.tgt_of[v] >= 0;
+    if (is_tgt && lane == 0) atomicMin(S.tmin, (uint32_t)level);
     if (mask == 0ull) continue;
+    // lanes on which v is a target or lies below one: final now (every DAG
+    // in-arc of a ready lane has pushed); the backward reads only these
+    // (an atomic: waves pushing to v's other, not yet ready lanes may add
+    // their bits in this round)
+    ull dnv = S.wdn[it];
+    if (is_tgt) {
+      dnv |= mask;
+      if (lane == 0) atomicOr(&S.wdn[it], mask);
+    }
     const Compact cp = compact_lanes(mask, act);
     const bool on = cp.slot < cp.slots;
     const uint64_t vrow = (uint64_t)it * kLanes + (uint32_t)cp.src;
     const ull sv = on ? S.sig[vrow] : 0ull;
     const uint32_t dv = on ? S.wd[vrow] : kInf;
     const ull bit = 1ull << cp.src;
+    const bool below = on && ((dnv >> cp.src) & 1ull);
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
     const int64_t stepw = (int64_t)cp.slots * kWU;
     for (int64_t e = e0; e < e1; e += stepw) {
@@ -330,13 +341,17 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
         // the slot's ready lanes take one atomic, and the first mark of the
         // head appends it to the next round
         if (dag && co[u] == 1u) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (dag && below) __hip_atomic_fetch_or(&cd[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         wave_lds_sync();
-        ull m = 0ull;
+        ull m = 0ull, md = 0ull;
         if (cp.j == 0 && on) {
           m = cm[cp.slot];
+          md = cd[cp.slot];
           cm[cp.slot] = 0ull;
+          cd[cp.slot] = 0ull;
         }
         wave_lds_sync();
+        if (md != 0ull) atomicOr(&S.wdn[gbase + wq[u]], md);
         bool first = false;
         if (m != 0ull) first = atomicOr(&nxt[gbase + wq[u]], m) == 0ull;
         stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + wq[u]), next_cnt, S.items, nbase, rend, &S.flags[1]);
@@ -372,8 +387,10 @@ __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int l
     const uint64_t gbase = (uint64_t)g * n;
     const ull mask = S.imask[base + i];
     const int32_t tg = S.tgt_of[v];
-    const uint32_t tl = S.tlev[g * kLanes + lane];
-    const bool need = ((mask >> lane) & 1ull) && (full || (uint32_t)level > tl || tg >= 0);
+    // a target's dependency reads psi only on lanes where v is a target or
+    // lies below one
+    const ull dnv = S.wdn[it];
+    const bool need = ((mask >> lane) & 1ull) && (full || ((dnv >> lane) & 1ull) || tg >= 0);
     const ull em = __ballot(need);
     if (em == 0ull) continue;
     const Compact cp = compact_lanes(em, need);
@@ -442,6 +459,7 @@ __global__ void k_w_cleanup(BatchState S) {
     S.wc[row] = 0u;
     S.sig[row] = 0ull;
     if (lane == 0) S.vis[it] = 0ull;
+    if (lane == 5) S.wdn[it] = 0ull;
     if (lane < 3) S.fr[(uint64_t)lane * GN + it] = 0ull;
     if (lane >= 3 && lane < 5) S.chg[(uint64_t)(lane - 3) * GN + it] = 0ull;
   }
@@ -550,7 +568,9 @@ bcd_status Workspace::ensure_weighted() {
   STCHK(walloc(&S.bqn, 4));
   STCHK(walloc(&S.rl, GN));
   STCHK(walloc(&S.rln, 1));
+  STCHK(walloc(&S.wdn, GN));
   HIPCHK(hipMemsetAsync(S.wd, 0xFF, GN * kLanes * sizeof(uint32_t), stream));
+  HIPCHK(hipMemsetAsync(S.wdn, 0, GN * sizeof(unsigned long long), stream));
   HIPCHK(hipMemsetAsync(S.wc, 0, GN * kLanes * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.chg, 0, 2 * GN * sizeof(unsigned long long), stream));
   HIPCHK(hipMemsetAsync(S.bqn, 0, 4 * sizeof(uint32_t), stream));
@@ -573,6 +593,7 @@ void Workspace::release_weighted() {
   f(S.bqn);
   f(S.rl);
   f(S.rln);
+  f(S.wdn);
   weighted_ready = false;
 }
 
