@@ -28,8 +28,9 @@ def drain(S, n, timeout=120.0):
     return got
 
 
-def test_server_mixed_equals_alone(B, oracle):
-    g = gg.rmat(12, 8, seed=8)
+@pytest.mark.parametrize("weighted", [False, True])
+def test_server_mixed_equals_alone(B, oracle, weighted):
+    g = gg.rmat(12, 8, seed=8, weighted=weighted, max_weight=50)
     G = B.Graph.from_digraph(g)
     G.set_config(groups=2)
     qs = gg.queries_top_and_random(g, seed=4, top=4, rnd=6)
