@@ -1081,25 +1081,34 @@ __global__ void k_plain_gather(PlainState P, const int32_t *verts, int k, int32_
   }
 }
 
-__global__ void k_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc) {
-  __shared__ uint64_t part[1024];
-  const int k = blockIdx.x;  // one counter per workgroup
-  uint64_t s = 0;
-  for (int i = threadIdx.x; i < slots; i += blockDim.x) {
-    s += ctr[(size_t)i * C_COUNT + k];
-    ctr[(size_t)i * C_COUNT + k] = 0;
+// Adds the per-workgroup counter slots into acc and clears them: a thread
+// per slot row (rows are contiguous, so the reads coalesce), a wavefront
+// sum per counter, one atomic per counter and wavefront.  Integer sums:
+// the order does not matter.
+constexpr int kFoldBlock = 256;
+__global__ __launch_bounds__(kFoldBlock) void k_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc) {
+  uint64_t s[C_COUNT];
+#pragma unroll
+  for (int k = 0; k < C_COUNT; ++k) s[k] = 0;
+  for (int i = blockIdx.x * kFoldBlock + threadIdx.x; i < slots; i += gridDim.x * kFoldBlock) {
+    uint64_t *row = ctr + (size_t)i * C_COUNT;
+#pragma unroll
+    for (int k = 0; k < C_COUNT; ++k) {
+      s[k] += row[k];
+      row[k] = 0;
+    }
   }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
+#pragma unroll
+  for (int k = 0; k < C_COUNT; ++k) {
+    uint64_t v = s[k];
+    for (int off = 32; off > 0; off >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, off);
+    if (lane_id() == 0 && v != 0) atomicAdd((unsigned long long *)&acc[k], (unsigned long long)v);
   }
-  if (threadIdx.x == 0) acc[k] += part[0];
 }
 
 hipError_t launch_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctr_fold, dim3(C_COUNT), dim3(1024), 0, st, ctr, slots, acc);
+  const int grid = std::max(1, std::min(32, (slots + kFoldBlock - 1) / kFoldBlock));
+  hipLaunchKernelGGL(k_ctr_fold, dim3(grid), dim3(kFoldBlock), 0, st, ctr, slots, acc);
   return hipGetLastError();
 }
 
