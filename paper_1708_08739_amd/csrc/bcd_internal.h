@@ -80,6 +80,7 @@ struct BatchState {
   int gused;                     // column groups holding sources: 0 .. gused-1
   unsigned long long last_lanes; // lanes of group gused-1 that hold a source
   int bu_den;                    // bottom-up levels: see level_bottom_up (0 = never)
+  int keep_all;                  // 1: the backward runs on every lane (exports), else only below a target
   // weighted graphs only
   uint32_t *wd;              // [G][n][64] distances, 0xFFFFFFFF unreached
   uint32_t *wc;              // [G][n][64] shortest-path-DAG in-arcs not yet pushed

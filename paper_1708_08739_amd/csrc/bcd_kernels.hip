@@ -237,7 +237,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
     }
     const int64_t d1 = disc ? e1 : e0;  // end of the out-arcs to scan
     if (has && sl == 0) {
-      S.imask[base + ii] = mask;
       if (pull) {
         rec[it].vis = rec[it].vis | mask;
         const uint64_t pc = (uint64_t)__popcll(mask);
@@ -291,7 +290,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
     for (int t = 0; t < K; ++t) {
       const int ld = t * SUB;
       const ull mt = read_lane64(mask, ld);
-      if (mt == 0ull) continue;  // slot past the end of the list
+      if (mt == 0ull) {  // slot past the end of the list (or an empty item)
+        if (lane == 0 && i0 + (uint64_t)t < count) S.imask[base + i0 + t] = 0ull;
+        continue;
+      }
       const uint32_t itt = read_lane(it, ld);
       const uint32_t gt = read_lane(g, ld);
       const uint64_t gbt = read_lane64(gbase, ld);
@@ -328,14 +330,21 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
         }
         append_chunk(S, stage, nst, next_cnt, nbase, rend, gbt, ww, eq);
       }
-      if (!pull) continue;
+      // the item's lanes for the backward: all of them for exports, else
+      // those where v is a target or lies below one (a target's dependency
+      // reads psi nowhere else)
+      if (!pull) {  // found bottom-up: its marks are in the record already
+        if (lane == 0) S.imask[base + i0 + t] = S.keep_all ? mt : (mt & rec[itt].dn);
+        continue;
+      }
       const bool act = (mt >> lane) & 1ull;
       const bool is_tgt = (int32_t)read_lane((uint32_t)tg, ld) >= 0;
       if (is_tgt && lane == 0) atomicMin(S.tmin, (uint32_t)level);
-      // the backward needs psi only on these lanes (a target's dependency
-      // depends only on what lies below it)
       const ull dnt = dnacc[t] | (is_tgt ? mt : 0ull);
-      if (dnt != 0ull && lane == 0) rec[itt].dn = rec[itt].dn | dnt;
+      if (lane == 0) {
+        if (dnt != 0ull) rec[itt].dn = rec[itt].dn | dnt;
+        S.imask[base + i0 + t] = S.keep_all ? mt : dnt;
+      }
       if (level > 0) {
         if (act) S.sig[(uint64_t)itt * kLanes + lane] = acc[t];
         if (lov[t]) {
@@ -609,10 +618,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
       emv[t] = 0ull;
       sg[t] = 1ull;
       if (mt == 0ull) continue;
-      // lanes where v is a target or lies below one on the lane's DAG: a
-      // target's dependency reads psi only there
-      const ull dnt = S.rec[read_lane(it, ld)].dn;
-      const bool need = ((mt >> lane) & 1ull) && (full || ((dnt >> lane) & 1ull) || (int32_t)read_lane((uint32_t)tg, ld) >= 0);
+      // the forward kept only the lanes that need psi here (all of them for
+      // exports): those where v is a target or lies below one
+      const bool need = (mt >> lane) & 1ull;
       emv[t] = __ballot(need);
       if (need) sg[t] = S.sig[(uint64_t)read_lane(it, ld) * kLanes + lane];
     }

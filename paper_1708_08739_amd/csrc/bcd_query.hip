@@ -237,6 +237,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     S.gused = (k + kLanes - 1) / kLanes;
     S.last_lanes = (k % kLanes) == 0 ? ~0ull : ((1ull << (k % kLanes)) - 1ull);
     S.bu_den = g->config().bottom_up;
+    S.keep_all = full ? 1 : 0;
     const int P = S.P;
     const Launch L = g->launch_parts(P);
     // level-0 placement depends on the partition sizes (they change when the list grows)
