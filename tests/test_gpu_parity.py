@@ -479,20 +479,20 @@ def test_weighted_many_batches_two_streams(B, oracle):
         assert p["launches"] > 0 and 0 < p["union_ms"] <= p["total_ms"] * (1 + 1e-9) + 1e-6
 
 
-@pytest.mark.parametrize("weighted", [False, True])
-def test_every_source_of_a_many_batch_query(B, oracle, weighted):
+@pytest.mark.parametrize("weighted,bottom_up", [(False, 0), (False, 4), (True, 0)])
+def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up):
     """Every source of RV(r) on R-MAT 14 (edge factor 16), elementwise against
     the oracle, in batches of 4 groups (dozens of batches, two at a time on
-    two streams): catches a wrong value on any lane of any batch, not only in
-    the sum."""
+    two streams), top-down and with bottom-up levels: catches a wrong value on
+    any lane of any batch, not only in the sum."""
     g = gg.rmat(14, 16, seed=41, weighted=weighted, max_weight=100)
     r = gg.top_out_degree(g, 1)[0]
     rv = oracle.rv(g, r)
-    print("every source weighted", weighted, "sources", rv.size, flush=True)
-    dep = dev(B, g, groups=4).dependencies(r, rv)
+    print("every source weighted", weighted, "bottom_up", bottom_up, "sources", rv.size, flush=True)
+    dep = dev(B, g, groups=4, bottom_up=bottom_up).dependencies(r, rv)
     odep, _ = oracle.dependencies(g, r, rv)
     assert close(dep, odep)
-    again = dev(B, g, groups=4).dependencies(r, rv)
+    again = dev(B, g, groups=4, bottom_up=bottom_up).dependencies(r, rv)
     assert np.array_equal(dep, again)
 
 
