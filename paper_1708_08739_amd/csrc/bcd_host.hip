@@ -118,7 +118,6 @@ void Workspace::release() {
   dfree(S.imask);
   dfree(S.cnt);
   dfree(S.off);
-  dfree(S.tlev);
   dfree(S.tmin);
   dfree(S.tgt_of);
   dfree(S.res);
@@ -188,7 +187,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   if (batch_ready) {
     release_weighted();
     dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.rec); dfree(S.bt);
-    dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tlev); dfree(S.tmin);
+    dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tmin);
     dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
     dfree(d_items0); dfree(d_masks0); dfree(d_dest0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0);
     hfree(h_dest0); hfree(h_res);
@@ -218,7 +217,6 @@ bcd_status Workspace::ensure_batch(int G_) {
   const size_t levels = ((size_t)n + kLevelChunkMax + 4) * kMaxParts;
   STCHK(dalloc(&S.cnt, levels));
   STCHK(dalloc(&S.off, levels));
-  STCHK(dalloc(&S.tlev, (size_t)G * kLanes));
   STCHK(dalloc(&S.tmin, 4));
   STCHK(dalloc(&S.tgt_of, (size_t)n));
   STCHK(dalloc(&S.flags, 4));

@@ -66,7 +66,6 @@ struct BatchState {
   int P;
   uint32_t *cnt;             // [(n + 2) * 8] items per (level, partition): index level * P + p
   uint64_t *off;             // [(n + 2) * 8] first item of each (level, partition)
-  uint32_t *tlev;            // [G][64] smallest level at which the lane met a target
   uint32_t *tmin;            // [1] smallest over all lanes
   int32_t *tgt_of;           // [n] target index of a vertex, -1 if none
   double *res;               // [ntgt][G][64] delta of lane on target

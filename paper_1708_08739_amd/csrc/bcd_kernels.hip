@@ -561,9 +561,10 @@ static __device__ __forceinline__ void push_sum_slots(const BatchState &S, uint6
 //   delta(v) = sigma(v) * sum_{w: v in P(w)} psi(w),  psi(w) = (1 + delta(w)) / sigma(w),
 // so psi(v) = 1/sigma(v) + sum psi(w).  Successor w of v is on the DAG for
 // lane b iff w sits on level+1 for b, read from the level-tagged table the
-// previous (deeper) launch wrote.  Lanes whose nearest target lies at or
-// below this level are skipped (their psi here cannot reach a target), and
-// target vertices report delta on their lanes.  No atomics: every sum runs
+// previous (deeper) launch wrote.  Only the lanes the forward kept in the
+// item's mask are computed -- those where v is a target or lies below one
+// (no target's dependency reads psi anywhere else) -- and target vertices
+// report delta on their lanes.  No atomics: every sum runs
 // in arc order, so results are bit-reproducible.  A wavefront takes K items
 // per step, their first 64 / K out-arcs in one chunk of lanes (as in the
 // forward kernel), then longer out-arc lists 64 at a time.

@@ -216,7 +216,7 @@ struct BatchExport {
 
 // One batch: `k` sources already staged in ws->h_items0 / h_masks0 (lane i
 // of the batch is group i/64, lane i%64).  Runs the forward levels until the
-// next level is empty, the backward levels down to the nearest target (or
+// next level is empty, the backward levels down to the shallowest target level (or
 // level 0 when `full`), copies the per-lane target dependencies into
 // ws->h_res, and leaves the state clean for the next batch.
 static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool full, BatchExport *ex,
@@ -248,7 +248,6 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     for (int p = 0; p < P; ++p) hc0[p] = ws->h_cnt0[p];
     HIPCHK(hipMemcpyAsync(&S.cnt[0], hc0, (size_t)P * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (ntgt > 0) HIPCHK(hipMemsetAsync(S.res, 0, (size_t)ntgt * G64 * sizeof(double), st));
-    HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));

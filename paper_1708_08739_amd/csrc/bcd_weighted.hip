@@ -12,7 +12,8 @@
 //   4. backward: Eq.(4) over the rounds of step 3 in reverse -- every DAG
 //      successor of v became ready in a later round, so its psi is final.
 // Step 3's round of a vertex plays the role of the BFS level of the
-// unweighted engine, including the pruning below the nearest target.
+// unweighted engine; the backward computes psi only on lanes where the
+// vertex is a target or lies below one (marks OR'd along the sigma pushes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -630,7 +631,6 @@ static bcd_status run_one_wbatch(Graph *g, Workspace *ws, int k, int ntgt, bool 
     for (int p = 0; p < P; ++p) hc0[p] = ws->h_cnt0[p];
     HIPCHK(hipMemcpyAsync(&S.cnt[0], hc0, (size_t)P * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     if (ntgt > 0) HIPCHK(hipMemsetAsync(S.res, 0, (size_t)ntgt * G64 * sizeof(double), st));
-    HIPCHK(hipMemsetAsync(S.tlev, 0xFF, G64 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
