@@ -335,6 +335,8 @@ def main():
     ap.add_argument("--bottom-up", type=int, default=-1,
                     help="bottom-up threshold denominator for the unweighted forward (0 = off, -1 = library default)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(cores, 16))")
+    ap.add_argument("--compress", action="store_true",
+                    help="exact and set calls fold sources with no in-arcs and one out-arc into their successor")
     ap.add_argument("--engine", choices=["auto", "batched", "lds", "plain"], default="auto",
                     help="per-source engine (auto: the LDS engine for the ER 2k workload, else batched)")
     ap.add_argument("--plain-sources", type=int, default=256)
@@ -371,6 +373,8 @@ def main():
         kw["items"] = args.items
     if args.bottom_up >= 0:
         kw["bottom_up"] = args.bottom_up
+    if args.compress:
+        kw["compress"] = 1
     engines = {"batched": bcd.BCD_ENGINE_BATCHED, "lds": bcd.BCD_ENGINE_LDS, "plain": bcd.BCD_ENGINE_PLAIN}
     ename = args.engine if args.engine != "auto" else ("lds" if args.workload == "er2000" else "batched")
     cfg = G.set_config(engine=engines[ename], **kw)
@@ -447,7 +451,7 @@ def main():
                           "config": {"workload": wname, "n": g.n, "m": g.m,
                                      "groups": extra.get("serving", {}).get("groups", cfg.groups),
                                      "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items,
-                                     "bottom_up": cfg.bottom_up},
+                                     "bottom_up": cfg.bottom_up, "compress": cfg.compress},
                           **extra}), flush=True)
         return
 
@@ -527,7 +531,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "graph": g.name, "n": g.n, "m": g.m, "queries": [int(q) for q in queries],
                    "engine": ename, "batch_width": 64 * cfg.groups if ename == "batched" else 1, "block": cfg.block,
-                   "grid_mult": cfg.grid_mult, "items": cfg.items, "bottom_up": cfg.bottom_up},
+                   "grid_mult": cfg.grid_mult, "items": cfg.items, "bottom_up": cfg.bottom_up, "compress": cfg.compress},
         "p50_query_ms": round(float(np.percentile(lat_ms, 50)), 3),
         "p99_query_ms": round(float(np.percentile(lat_ms, 99)), 3),
         "traversed_edges_per_step": te_total // args.steps,

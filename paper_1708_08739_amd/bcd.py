@@ -52,7 +52,8 @@ class Stats(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("engine", C.c_int32), ("groups", C.c_int32), ("block", C.c_int32),
-                ("grid_mult", C.c_int32), ("items", C.c_int32), ("bottom_up", C.c_int32)]
+                ("grid_mult", C.c_int32), ("items", C.c_int32), ("bottom_up", C.c_int32),
+                ("compress", C.c_int32)]
 
 
 class SampleParams(C.Structure):
@@ -240,8 +241,10 @@ class Graph:
         return c
 
     def set_config(self, engine=None, groups=None, block=None, grid_mult=None, items=None,
-                   bottom_up=None) -> Config:
+                   bottom_up=None, compress=None) -> Config:
         c = self.config()
+        if compress is not None:
+            c.compress = int(compress)
         if items is not None:
             c.items = items
         if bottom_up is not None:

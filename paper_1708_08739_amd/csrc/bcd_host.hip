@@ -553,6 +553,10 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   std::vector<int64_t> irp((size_t)n + 1, 0);
   for (int64_t e = 0; e < m; ++e) irp[(size_t)col[e] + 1]++;
   for (int64_t v = 0; v < n; ++v) irp[(size_t)v + 1] += irp[(size_t)v];
+  // sources that can be folded into their only successor (no in-arcs, one out-arc)
+  g->leaf_next.assign((size_t)n, -1);
+  for (int64_t v = 0; v < n; ++v)
+    if (irp[(size_t)v + 1] == irp[(size_t)v] && row_ptr[v + 1] - row_ptr[v] == 1) g->leaf_next[(size_t)v] = col[row_ptr[v]];
   std::vector<int32_t> icol((size_t)std::max<int64_t>(m, 1));
   std::vector<uint32_t> iw(weight ? (size_t)std::max<int64_t>(m, 1) : 0);
   {
@@ -629,6 +633,7 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
     return fail(BCD_ERR_INVALID_ARG, "items must be 1, 2 or 4 (0 = default)");
   if (cfg->bottom_up < -1 || cfg->bottom_up > 4096)
     return fail(BCD_ERR_INVALID_ARG, "bottom_up must be in [-1, 4096]");
+  if (cfg->compress != 0 && cfg->compress != 1) return fail(BCD_ERR_INVALID_ARG, "compress must be 0 or 1");
   std::lock_guard<std::mutex> lk(g->cfg_mu);
   g->cfg = *cfg;
   if (g->cfg.items == 0) g->cfg.items = kDefaultItems;

@@ -142,6 +142,7 @@ struct Graph {
   int cus = 1;
   size_t lds_block_bytes = 0;  // LDS one workgroup may allocate
   std::vector<int64_t> h_rp;
+  std::vector<int32_t> leaf_next;  // head of the only out-arc of a vertex with no in-arcs, else -1
   int64_t *d_rp = nullptr;
   int32_t *d_col = nullptr;
   uint32_t *d_w = nullptr;

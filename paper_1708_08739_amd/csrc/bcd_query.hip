@@ -736,6 +736,61 @@ bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
   return run_batched(g, ws, src, tgt, want_counters, out);
 }
 
+// Exact and set calls with compression on: a source s with no in-arcs and
+// a single out-arc (s, v) runs no pass.  Every path from s leaves through
+// v, and s is reached from nowhere, so for a target t != v the dependency
+// delta_s(t) equals delta_v(t) bit for bit (the same path counts and arc
+// order below v); when v is not among the sources that run, v reaches no
+// target but itself and delta_s(t) = 0; and delta_s(v) is the number of
+// vertices v reaches (every one of them is reached through v).  `src` and
+// the sources that run are ascending; dep is filled for all of `src`.
+static bcd_status run_sources_folded(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
+                                     const std::vector<int32_t> &tgt, SourceRun &out, int64_t *ran) {
+  if (g->config().compress == 0) {
+    *ran = (int64_t)src.size();
+    return run_sources(g, ws, src, tgt, false, out);
+  }
+  const size_t ns = src.size(), nt = tgt.size();
+  std::vector<int32_t> runs;
+  runs.reserve(ns);
+  for (int32_t s : src)
+    if (g->leaf_next[(size_t)s] < 0) runs.push_back(s);
+  SourceRun run;
+  if (!runs.empty()) STCHK(run_sources(g, ws, runs, tgt, false, run));
+  std::vector<int64_t> reach(nt, -1);  // vertices a target reaches, when needed
+  out.dep.assign(ns * nt, 0.0);
+  size_t j = 0;
+  for (size_t i = 0; i < ns; ++i) {
+    const int32_t s = src[i];
+    const int32_t v = g->leaf_next[(size_t)s];
+    if (v < 0) {
+      for (size_t t = 0; t < nt; ++t) out.dep[i * nt + t] = run.dep[j * nt + t];
+      ++j;
+      continue;
+    }
+    const auto it = std::lower_bound(runs.begin(), runs.end(), v);
+    const bool has_v = it != runs.end() && *it == v;
+    const size_t jv = (size_t)(it - runs.begin());
+    for (size_t t = 0; t < nt; ++t) {
+      if (tgt[t] == v) {
+        if (reach[t] < 0) {
+          std::vector<uint32_t> bits;
+          STCHK(reach_set(g, ws, v, false, bits, &reach[t], nullptr));
+        }
+        out.dep[i * nt + t] = (double)reach[t];
+      } else {
+        out.dep[i * nt + t] = has_v ? run.dep[jv * nt + t] : 0.0;
+      }
+    }
+  }
+  out.te = run.te;
+  out.reached = run.reached;
+  out.dag = run.dag;
+  out.width = run.width;
+  *ran = (int64_t)runs.size();
+  return BCD_OK;
+}
+
 }  // namespace bcd
 
 using namespace bcd;
@@ -797,11 +852,12 @@ bcd_status bcd_bc_exact(const bcd_graph *gh, bcd_vid r, double *bc, bcd_stats *s
   bits_to_list(bits, g->n, r, rv);
   const double t1 = now_s();
   SourceRun run;
-  STCHK(run_sources(g, ls.w.get(), rv, std::vector<int32_t>{r}, false, run));
+  int64_t ran = 0;
+  STCHK(run_sources_folded(g, ls.w.get(), rv, std::vector<int32_t>{r}, run, &ran));
   const double v = compensated_sum(run.dep.data(), rv.size(), 1);
   const double t2 = now_s();
   s.rv_size = k;
-  s.distinct_sources = (int64_t)rv.size();
+  s.distinct_sources = ran;
   s.traversed_edges = run.te;
   s.reached = run.reached;
   s.dag_arcs = run.dag;
@@ -839,7 +895,8 @@ bcd_status bcd_bc_set(const bcd_graph *gh, const bcd_vid *rs, int64_t l, double 
   bits_to_list(uni, g->n, -1, D);
   const double t1 = now_s();
   SourceRun run;
-  STCHK(run_sources(g, ls.w.get(), D, tg, false, run));
+  int64_t ran = 0;
+  STCHK(run_sources_folded(g, ls.w.get(), D, tg, run, &ran));
   std::vector<double> per(tg.size());
   for (size_t t = 0; t < tg.size(); ++t)
     per[t] = g->outdeg(tg[t]) == 0 ? 0.0 : compensated_sum(run.dep.data() + t, D.size(), tg.size());
@@ -851,7 +908,7 @@ bcd_status bcd_bc_set(const bcd_graph *gh, const bcd_vid *rs, int64_t l, double 
     bcd_stats s{};
     s.rv_size = (int64_t)D.size();
     s.fr_size = -1;
-    s.distinct_sources = (int64_t)D.size();
+    s.distinct_sources = ran;
     s.traversed_edges = run.te;
     s.reached = run.reached;
     s.dag_arcs = run.dag;

@@ -496,6 +496,35 @@ def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up):
     assert np.array_equal(dep, again)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_compression_folds_leaf_sources(B, oracle, weighted):
+    """Compression on (sources with no in-arcs and one out-arc take their
+    successor's dependency, or its reach count when the successor is the
+    target): exact and set values match the oracle and the uncompressed run,
+    with fewer sources run; queries include successors of such sources."""
+    g = gg.rmat(12, 8, seed=8, weighted=weighted, max_weight=50)
+    ind, outd = g.in_degree(), g.out_degree()
+    leaves = np.flatnonzero((ind == 0) & (outd == 1))
+    succ = sorted(set(int(g.col[g.row_ptr[s]]) for s in leaves))
+    qs = gg.queries_top_and_random(g, seed=4, top=4, rnd=4) + [v for v in succ if outd[v] > 0][:4]
+    G0, G1 = dev(B, g), dev(B, g, compress=1)
+    fewer = 0
+    for r in qs:
+        a, sa = G0.bc_exact(r)
+        b, sb = G1.bc_exact(r)
+        want, _ = oracle.bc_exact(g, r)
+        print("compress r", r, sa["distinct_sources"], sb["distinct_sources"], a, b, flush=True)
+        assert close(b, want) and close(b, a), (r, a, b, want)
+        assert sb["distinct_sources"] <= sa["distinct_sources"]
+        fewer += sb["distinct_sources"] < sa["distinct_sources"]
+    assert fewer > 0
+    assert close(G1.bc_set(qs)[0], oracle.bc_set(g, qs)[0])
+    # in-out star: every in-leaf is folded, BC(c) = a * b exactly
+    gs, c = gg.in_out_star(5, 7)
+    got, st = dev(B, gs, compress=1).bc_exact(c)
+    assert got == 35.0 and st["distinct_sources"] == 0
+
+
 def test_bcd_procedure_and_unpruned_sampling(B, oracle):
     g = gg.rmat(12, 8, seed=7)
     G = dev(B, g)
