@@ -352,7 +352,7 @@ def main():
                     help="also run the library's streaming-copy probe (1 GiB copied, known traffic)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the whole path on a single MI355X "
+        print("bench.py measures one GPU only: the library runs the whole path on a single MI355X "
               "(multi-GPU source sharding is designed but not built); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
