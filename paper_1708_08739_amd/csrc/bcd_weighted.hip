@@ -162,6 +162,7 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
       }
 #pragma unroll
       for (int u = 0; u < kWU; ++u) {
+        if (__ballot(imp[u]) == 0ull) continue;  // nothing improved in this step (wave-uniform)
         if (imp[u]) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         wave_lds_sync();
         ull m = 0ull;
@@ -341,6 +342,7 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
         // a lane whose push completed the head's in-arcs is ready next round;
         // the slot's ready lanes take one atomic, and the first mark of the
         // head appends it to the next round
+        if (__ballot(dag && (co[u] == 1u || below)) == 0ull) continue;  // no flag to set in this step
         if (dag && co[u] == 1u) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         if (dag && below) __hip_atomic_fetch_or(&cd[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         wave_lds_sync();
