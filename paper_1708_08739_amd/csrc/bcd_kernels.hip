@@ -164,10 +164,11 @@ static __device__ __forceinline__ void append_chunk(const BatchState &S, uint32_
 // With bottom-up levels enabled, step 1 is skipped when the level was found
 // by k_bu_level (which pulled the counts), and step 2 when level+1 will be;
 // the item masks are recorded for the backward either way.
-// At most 72 VGPRs (7 waves per SIMD instead of 6; a few bytes spill to
-// scratch): measured about 2 % faster at R-MAT 16.
+// At least 6 waves per SIMD: with the below-target marks, asking for 7
+// (72 VGPRs) made the compiler spill 44 bytes per lane and measured 3.5 %
+// slower at R-MAT 16 (5 waves: 2 % slower).
 template <int BLOCK, int K>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_fwd_level(DevGraph G,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_level(DevGraph G,
                                                                                                  BatchState S,
                                                                                                  int level) {
   constexpr int SUB = kLanes / K;
