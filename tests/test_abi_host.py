@@ -170,3 +170,36 @@ def test_bench_roofline_uses_busy_time():
     b = bench.roofline_from_profile(Stub(False), bwd, fwd, "batched", "no-such-workload")
     assert b["kernel"] == "k_bwd_level"
     assert bench.roofline_from_profile(Stub(False), dict(fwd, launches=0), bwd, "batched", "x") is None
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and, field by
+    field, the header's offsets (a C program built from include/bcd.h with
+    gcc prints them)."""
+    import shutil
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    pairs = {"bcd_stats": bcd.Stats, "bcd_config": bcd.Config, "bcd_sample_params": bcd.SampleParams,
+             "bcd_kernel_profile": bcd.KernelProfile, "bcd_server_config": bcd.ServerConfig,
+             "bcd_query": bcd.Query, "bcd_result": bcd.Result, "bcd_server_stats": bcd.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bcd.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True, timeout=120)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=60).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            a, b, c = ln.split()
+            got[(a, b)] = int(c)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
