@@ -372,3 +372,31 @@ def test_bcd_procedure_oracle(oracle):
     assert ex and v == oracle.bc_exact(g, r)[0]
     v, ex = oracle.bc_bcd(g, r, tau=k - 1, seed=1)
     assert not ex and v == oracle.bc_sampled(g, r, k - 1, 1)[0]
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_leaf_source_identity(oracle, weighted):
+    """The identity compression relies on, by brute-force path enumeration:
+    a source s with no in-arcs and one out-arc (s, v) has delta_s(r) =
+    delta_v(r) for r != v, and delta_s(v) = the number of vertices v reaches."""
+    checked = 0
+    for seed in range(1, 13):
+        checked += _leaf_identity(gg.random_small(9, 0.18, seed=seed, max_weight=3 if weighted else 0))
+    assert checked > 20
+
+
+def _leaf_identity(g):
+    ind, outd = g.in_degree(), g.out_degree()
+    paths = BF.all_pairs_paths(g)
+    checked = 0
+    for s in np.flatnonzero((ind == 0) & (outd == 1)).tolist():
+        v = int(g.col[g.row_ptr[s]])
+        reach_v = sum(1 for t in range(g.n) if t != v and (v, t) in paths)
+        for r in range(g.n):
+            if r == s:
+                continue
+            got = BF.dependency(g, s, r, paths)
+            want = Fraction(reach_v) if r == v else BF.dependency(g, v, r, paths)
+            assert got == want, (g.name, s, v, r, got, want)
+            checked += 1
+    return checked
