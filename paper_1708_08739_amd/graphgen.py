@@ -333,6 +333,26 @@ def diamond_chain(k: int) -> tuple[Digraph, dict]:
     return from_arcs(3 * k + 1, src, dst, name=f"diamond{k}"), ids
 
 
+def diamond_chain_weighted(k: int, mixed: bool) -> tuple[Digraph, dict, int]:
+    """``diamond_chain(k)`` with arc weights that keep both branches of every
+    diamond equally long: all 3 (``mixed`` False), or x -> a 1, x -> b 2,
+    a -> x' 2, b -> x' 1 (``mixed`` True: the two middle vertices of a
+    diamond at different distances).  Returns (graph, ids, length of one
+    diamond)."""
+    g, ids = diamond_chain(k)
+    w = np.empty(g.m, dtype=np.uint32)
+    for u in range(g.n):
+        a, b = int(g.row_ptr[u]), int(g.row_ptr[u + 1])
+        if not mixed:
+            w[a:b] = 3
+        elif u % 3 == 0:  # a joint x_{i-1}: its arcs to a_i then b_i
+            w[a:b] = [1, 2][: b - a]
+        else:  # a_i (id 3i-2) or b_i (id 3i-1): its one arc to x_i
+            w[a:b] = 2 if u % 3 == 1 else 1
+    name = g.name + ("_mixed" if mixed else "_w3")
+    return Digraph(g.n, g.row_ptr, g.col, w, name), ids, (3 if mixed else 6)
+
+
 def grid_right_down(rows: int, cols: int) -> Digraph:
     """Directed grid: (i, j) -> (i, j+1) and (i, j) -> (i+1, j); id = i*cols + j."""
     src, dst = [], []

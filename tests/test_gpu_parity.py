@@ -496,24 +496,23 @@ def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up):
     assert np.array_equal(dep, again)
 
 
-def test_weighted_sigma_overflow(B, oracle):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_weighted_sigma_overflow(B, oracle, mixed):
     """Exact uint64 path counts and the overflow error of the weighted
-    engine.  Every arc weight 3 keeps the unweighted diamond chain's shortest
-    paths: 2^i of them from x_0 to x_i, so 63 diamonds reach 2^63 exactly and
-    64 overflow."""
-    def w3(g):
-        return gg.Digraph(g.n, g.row_ptr, g.col, np.full(g.m, 3, dtype=np.uint32), g.name + "_w3")
-
-    g63, ids63 = gg.diamond_chain(63)
-    G = dev(B, w3(g63))
+    engine.  The weighted diamond chains keep both branches of every diamond
+    equally long (all arcs 3, or 1+2 against 2+1 with the two middle
+    vertices at different distances): 2^i shortest paths from x_0 to x_i, so
+    63 diamonds reach 2^63 exactly and 64 overflow."""
+    g63, ids63, span = gg.diamond_chain_weighted(63, mixed)
+    G = dev(B, g63)
     d, sg, _ = G.source_pass(0)
-    assert int(sg[ids63["x"][63]]) == 1 << 63 and int(d[ids63["x"][63]]) == 3 * 2 * 63
+    assert int(sg[ids63["x"][63]]) == 1 << 63 and int(d[ids63["x"][63]]) == span * 63
     assert G.bc_exact(ids63["x"][31])[0] == 9 * 31 * 32
     # the plain engine runs a weighted query one source per batch
-    assert dev(B, w3(g63), engine=B.BCD_ENGINE_PLAIN).bc_exact(ids63["x"][31])[0] == 9 * 31 * 32
-    g64, ids64 = gg.diamond_chain(64)
+    assert dev(B, g63, engine=B.BCD_ENGINE_PLAIN).bc_exact(ids63["x"][31])[0] == 9 * 31 * 32
+    g64, ids64, _ = gg.diamond_chain_weighted(64, mixed)
     for cfg in (dict(), dict(engine=B.BCD_ENGINE_PLAIN)):
-        G = dev(B, w3(g64), **cfg)
+        G = dev(B, g64, **cfg)
         with pytest.raises(B.BcdError) as e:
             G.bc_exact(ids64["x"][40])
         assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW, cfg
@@ -521,8 +520,7 @@ def test_weighted_sigma_overflow(B, oracle):
         G.source_pass(0)
     assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW
     # counts on both sides of 2^32 in one batch, sources at different depths
-    g40, ids40 = gg.diamond_chain(40)
-    g40 = w3(g40)
+    g40, ids40, _ = gg.diamond_chain_weighted(40, mixed)
     src = [ids40["x"][i] for i in (0, 3, 9, 20, 30)] + [ids40["a"][2], ids40["b"][7]]
     want = [oracle.source_pass(g40, s) for s in src]
     for cfg in (dict(groups=1), dict(engine=B.BCD_ENGINE_PLAIN)):

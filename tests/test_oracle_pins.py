@@ -168,15 +168,22 @@ def test_diamond_chain_formulas(oracle):
         assert oracle.bc_exact(g, ids["b"][i])[0] == want
 
 
-def test_sigma_exact_at_limit_and_overflow(oracle):
-    """Diamond chain: sigma(x_k) = 2^k from x_0.  k = 63 fits uint64 and
-    every dependency ratio is a power of two, so BC is exact; k = 64 wraps
-    and must be reported."""
-    g, ids = gg.diamond_chain(63)
+@pytest.mark.parametrize("kind", [None, "w3", "mixed"])
+def test_sigma_exact_at_limit_and_overflow(oracle, kind):
+    """Diamond chain: sigma(x_k) = 2^k from x_0 (with weights: both branches
+    of every diamond equally long).  k = 63 fits uint64 and every dependency
+    ratio is a power of two, so BC is exact; k = 64 wraps and must be
+    reported."""
+    if kind is None:
+        (g, ids), span = gg.diamond_chain(63), 2
+    else:
+        g, ids, span = gg.diamond_chain_weighted(63, kind == "mixed")
     dist, sig, _, ovf, _ = oracle.source_pass(g, 0)
     assert not ovf and int(sig[ids["x"][63]]) == 1 << 63
+    assert all(int(dist[ids["x"][i]]) == span * i for i in range(64))
+    assert all(int(sig[ids["x"][i]]) == 1 << i for i in range(64))
     assert oracle.bc_exact(g, ids["x"][31])[0] == 9 * 31 * 32
-    g64, ids64 = gg.diamond_chain(64)
+    g64, ids64 = gg.diamond_chain(64) if kind is None else gg.diamond_chain_weighted(64, kind == "mixed")[:2]
     _, sig, _, ovf, _ = oracle.source_pass(g64, 0)
     assert ovf
     with pytest.raises(oracle.OracleError) as e:
