@@ -496,6 +496,38 @@ def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up):
     assert np.array_equal(dep, again)
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_concurrent_queries_on_one_graph(B, weighted):
+    """Several host threads query one graph at once (every call leases its
+    own workspace and stream; ctypes drops the GIL during the call): each
+    value equals the one-at-a-time value bit for bit."""
+    import threading
+    g = gg.rmat(12, 8, seed=21, weighted=weighted, max_weight=20)
+    G = dev(B, g, groups=2)  # 128 sources per batch: every query takes several
+    rs = gg.top_out_degree(g, 8)
+    want = {("e", r): G.bc_exact(r)[0] for r in rs}
+    want.update({("s", r): G.bc_sampled(r, T=300, seed=r)[0] for r in rs})
+    assert sum(G.bc_exact(r)[1]["rv_size"] > 128 for r in rs) >= 4
+    got, errs = {}, []
+
+    def work(part):
+        try:
+            for r in part:
+                got[("e", r)] = G.bc_exact(r)[0]
+                got[("s", r)] = G.bc_sampled(r, T=300, seed=r)[0]
+        except Exception as e:  # reported by the assertion below
+            errs.append(e)
+
+    ts = [threading.Thread(target=work, args=(rs[i::4],)) for i in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=100)
+    assert not errs, errs
+    assert not any(t.is_alive() for t in ts)
+    assert got == want
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_weighted_sigma_overflow(B, oracle, mixed):
     """Exact uint64 path counts and the overflow error of the weighted
