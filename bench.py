@@ -189,11 +189,14 @@ def serve(G, g, args):
     qs = pool[: args.queries]
 
     # largest group count whose workspaces fit in 85 % of the budget (the rest
-    # holds the queries' result buffers)
+    # holds the queries' result buffers) and that splits evenly over the 8
+    # XCD partitions (at most 8 groups, or a multiple of 8): group g goes to
+    # partition g % 8, so 9 groups would leave one partition twice the work
     budget = args.hbm_budget << 30
     groups = G.config().groups
-    while groups > 1 and bcd.Server.workspace_bytes(G, groups, args.workers) > budget * 85 // 100:
-        groups //= 2
+    while groups > 1 and (bcd.Server.workspace_bytes(G, groups, args.workers) > budget * 85 // 100
+                          or (groups > 8 and groups % 8 != 0)):
+        groups -= 1
     log(f"[bench] serving: {args.workers} workers x {groups} groups, budget {args.hbm_budget} GiB")
 
     def run(rate):
@@ -345,7 +348,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--queries", type=int, default=64, help="serving: number of sampled queries")
-    ap.add_argument("--workers", type=int, default=2, help="serving: concurrent batches")
+    ap.add_argument("--workers", type=int, default=6, help="serving: concurrent batches")
     ap.add_argument("--hbm-budget", type=int, default=240, help="serving: HBM budget in GiB (288 GB on the GPU)")
     ap.add_argument("--set-size", type=int, default=64)
     ap.add_argument("--probe-bw", action="store_true",
