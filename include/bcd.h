@@ -84,7 +84,10 @@ typedef struct bcd_stats {
 
 typedef struct bcd_config {
   int32_t engine;     /* BCD_ENGINE_* */
-  int32_t groups;     /* batched engine: 64-source column groups per batch, >= 1 */
+  int32_t groups;     /* batched engine: 64-source column groups per batch, >= 1
+                         (default: the path-count rows near 64 GiB, at most 96,
+                         128 on weighted graphs, a multiple of 8 above 8 since
+                         group j runs in partition j % 8 of the 8 XCDs) */
   int32_t block;      /* threads per workgroup for traversal kernels: 64, 128, 256, 512
                          (default 256, 64 on weighted graphs) */
   int32_t grid_mult;  /* workgroups per compute unit for traversal kernels, >= 1 */
