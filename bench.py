@@ -188,15 +188,8 @@ def serve(G, g, args):
     pool = [v for v in gg.uniform_vertices(g.n, 20 * args.queries, seed=105) if ind[v] > 0 and outd[v] > 0]
     qs = pool[: args.queries]
 
-    # largest group count whose workspaces fit in 85 % of the budget (the rest
-    # holds the queries' result buffers) and that splits evenly over the 8
-    # XCD partitions (at most 8 groups, or a multiple of 8): group g goes to
-    # partition g % 8, so 9 groups would leave one partition twice the work
     budget = args.hbm_budget << 30
-    groups = G.config().groups
-    while groups > 1 and (bcd.Server.workspace_bytes(G, groups, args.workers) > budget * 85 // 100
-                          or (groups > 8 and groups % 8 != 0)):
-        groups -= 1
+    groups = serving_width(lambda gr: bcd.Server.workspace_bytes(G, gr, args.workers), G.config().groups, budget)
     log(f"[bench] serving: {args.workers} workers x {groups} groups, budget {args.hbm_budget} GiB")
 
     def run(rate):
@@ -323,6 +316,18 @@ def cpu_baseline(g, r, budget_s: float, threads: int):
     return {"value": te / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
             "sample": f"{done} seeded sources of RV({r}) (|RV| = {rv.size}), per-source passes, "
                       f"{te} traversed arcs in {dt:.1f} s"}
+
+
+def serving_width(workspace_bytes, start: int, budget: int) -> int:
+    """Largest group count <= start whose workspaces (workspace_bytes(groups),
+    all workers) fit in 85 % of the budget (the rest holds the queries'
+    result buffers) and that splits evenly over the 8 XCD partitions (at most
+    8 groups, or a multiple of 8): group g goes to partition g % 8, so 9
+    groups would leave one partition twice the work.  At least 1."""
+    groups = max(1, start)
+    while groups > 1 and (workspace_bytes(groups) > budget * 85 // 100 or (groups > 8 and groups % 8 != 0)):
+        groups -= 1
+    return groups
 
 
 def main():

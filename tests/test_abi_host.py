@@ -212,3 +212,22 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_serving_width_fits_budget_and_splits_evenly():
+    """The serving benchmark's batch width: the widest that fits 85 % of the
+    budget and is at most 8 or a multiple of 8 (R-MAT 22: 5.5 GB per group)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    per_group = 1312 * (1 << 22)  # bytes per (group, vertex) x n at R-MAT 22
+
+    def width(workers, budget_gib, start=16):
+        return bench.serving_width(lambda g: g * per_group * workers, start, budget_gib << 30)
+
+    assert [width(w, 240) for w in (1, 2, 3, 4, 6, 8)] == [16, 16, 8, 8, 6, 4]
+    assert width(6, 64) == 1 and width(2, 64) == 5  # 2 x 5 x 5.5 GB <= 0.85 x 64 GiB
+    for w in range(1, 17):
+        for budget in (16, 64, 128, 240, 288):
+            g = width(w, budget, start=96)
+            assert g >= 1 and (g <= 8 or g % 8 == 0)
+            assert g == 1 or g * per_group * w <= (budget << 30) * 85 // 100
