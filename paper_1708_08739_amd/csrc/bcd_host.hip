@@ -171,28 +171,31 @@ bcd_status Workspace::init_common(Graph *g) {
 
 bcd_status Workspace::ensure_reach() {
   if (reach_ready) return BCD_OK;
+  // what an earlier call that failed part way left allocated
+  dfree(bitmap); dfree(rq[0]); dfree(rq[1]); dfree(rqn); hfree(h_bitmap);
   const size_t words = (size_t)(n + 31) / 32;
   STCHK(dalloc(&bitmap, words));
   STCHK(dalloc(&rq[0], (size_t)n));
   STCHK(dalloc(&rq[1], (size_t)n));
   STCHK(dalloc(&rqn, 2));
   STCHK(halloc(&h_bitmap, words));
-  STCHK(halloc(&h_misc, 64));
+  if (!h_misc) STCHK(halloc(&h_misc, 64));  // shared with the plain engine
   reach_ready = true;
   return BCD_OK;
 }
 
 bcd_status Workspace::ensure_batch(int G_) {
   if (batch_ready && G == G_) return BCD_OK;
-  if (batch_ready) {
-    release_weighted();
-    dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.rec); dfree(S.bt);
-    dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tmin);
-    dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
-    dfree(d_items0); dfree(d_masks0); dfree(d_dest0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0);
-    hfree(h_dest0); hfree(h_res);
-    batch_ready = false;
-  }
+  // the previous width's arrays, or what an earlier call that failed part
+  // way left allocated (every free is a no-op on a null pointer)
+  release_weighted();
+  dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.rec); dfree(S.bt);
+  dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tmin);
+  dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
+  dfree(d_items0); dfree(d_masks0); dfree(d_dest0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0);
+  hfree(h_dest0); hfree(h_res);
+  res_cap = 0;
+  batch_ready = false;
   if ((uint64_t)G_ * (uint64_t)n >= (1ull << 32))
     return fail(BCD_ERR_UNSUPPORTED, "groups * n must stay below 2^32");
   G = G_;
@@ -279,9 +282,10 @@ bcd_status Workspace::ensure_res(size_t need) {
   if (need <= res_cap) return BCD_OK;
   dfree(S.res);
   hfree(h_res);
+  res_cap = 0;  // recorded only once both buffers exist
+  STCHK(dalloc(&S.res, need));
+  STCHK(halloc(&h_res, need));
   res_cap = need;
-  STCHK(dalloc(&S.res, res_cap));
-  STCHK(halloc(&h_res, res_cap));
   return BCD_OK;
 }
 
@@ -297,8 +301,12 @@ bcd_status Workspace::grow_items() {
   dfree(S.imask);
   S.capP = ncapP;
   S.cap = S.capP * (uint64_t)S.P;
+  // if an allocation fails the workspace must not be reused as it stands:
+  // the next ensure_batch rebuilds every array
+  batch_ready = false;
   STCHK(dalloc(&S.items, S.cap));
   STCHK(dalloc(&S.imask, S.cap));
+  batch_ready = true;
   return BCD_OK;
 }
 
@@ -328,6 +336,9 @@ bcd_status Workspace::reset_batch_dense() {
 
 bcd_status Workspace::ensure_plain() {
   if (plain_ready) return BCD_OK;
+  // what an earlier call that failed part way left allocated
+  dfree(P.d); dfree(P.sig); dfree(P.psi); dfree(P.dout); dfree(P.queue);
+  dfree(P.cnt); dfree(P.off); dfree(P.flags); dfree(P.ctr); dfree(P.acc);
   std::memset(&P, 0, sizeof(P));
   P.n = n;
   STCHK(dalloc(&P.d, (size_t)n));

@@ -337,6 +337,10 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
     int ntgt = 0;
     bool threw = false;
     try {
+      // an earlier batch whose item-list growth failed left this workspace to
+      // be rebuilt (both calls return at once when it is ready)
+      if (rc == BCD_OK) rc = ws->ensure_batch(S->cfg.groups);
+      if (rc == BCD_OK && g->weighted) rc = ws->ensure_weighted();
       if (rc == BCD_OK) {
         std::sort(tg.begin(), tg.end());
         tg.erase(std::unique(tg.begin(), tg.end()), tg.end());

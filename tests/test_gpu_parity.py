@@ -528,6 +528,40 @@ def test_concurrent_queries_on_one_graph(B, weighted):
     assert got == want
 
 
+def test_recovers_from_device_allocation_failure(B):
+    """A batch width whose path counts fit in HBM but whose psi rows do not
+    fails with BCD_ERR_OUT_OF_MEMORY, and what it had allocated is released:
+    a width needing most of HBM then succeeds on the same graph and gives the
+    right value."""
+    import ctypes as C
+    # free HBM from the HIP runtime the library itself loaded
+    hip_path = next(ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln)
+    hip = C.CDLL(hip_path)
+    free_b, total_b = C.c_size_t(), C.c_size_t()
+    assert hip.hipMemGetInfo(C.byref(free_b), C.byref(total_b)) == 0
+    free = free_b.value
+    n = 1 << 22
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = 2
+    rp[1] = 1  # arcs 0 -> 1 -> 2: BC(1) = 1, RV(1) = {0}
+    g = gg.Digraph(n, rp, np.array([1, 2], dtype=np.int32))
+    G = dev(B, g, groups=1)
+    assert G.bc_exact(1)[0] == 1.0
+    row = n * 64 * 8  # one group's path counts (and as much again for psi)
+    g_fail = int(0.55 * free) // row  # sigma fits, sigma + psi does not
+    g_ok = int(0.60 * free) // (n * 1312)  # every array of the width: fits only if nothing leaked
+    assert g_fail * row * 2 > free and g_ok > 8
+    G.set_config(groups=g_fail)
+    with pytest.raises(B.BcdError) as e:
+        G.bc_exact(1)
+    assert e.value.code == B.BCD_ERR_OUT_OF_MEMORY
+    G.set_config(groups=g_ok)
+    assert G.bc_exact(1)[0] == 1.0
+    G.set_config(groups=1)
+    assert G.bc_exact(1)[0] == 1.0
+    G.close()
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_weighted_sigma_overflow(B, oracle, mixed):
     """Exact uint64 path counts and the overflow error of the weighted
