@@ -269,7 +269,8 @@ bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps);
 typedef struct bcd_server_config {
   uint64_t hbm_budget_bytes; /* device bytes for workspaces + per-query buffers; 0 = 64 GiB */
   int32_t workers;           /* concurrent batches (one stream each), >= 1; 0 = 2 */
-  int32_t groups;            /* 64-source column groups per batch; 0 = graph's configured value */
+  int32_t groups;            /* 64-source column groups per batch; 0 = graph's configured value.
+                                Above 8, a multiple of 8 keeps the 8 XCD partitions even */
   int32_t queue_capacity;    /* max queries submitted and not yet polled; 0 = 4096 */
   int32_t reserved;
 } bcd_server_config;
