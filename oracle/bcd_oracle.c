@@ -250,8 +250,20 @@ static int64_t forward(const og *G, int32_t s, oscratch *S, int *ovf, oc *cnt) {
     }
     settled = tail;
   } else {
-    /* Dijkstra; a vertex is settled when popped with its final distance */
+    /* Dijkstra; a vertex is settled when popped with its final distance.
+       sigma[w] is reset on a strict improvement of d[w] and grows on a tie,
+       so a tie at a tentative distance that is later beaten leaves no trace
+       in the final sigma[w].  Its wrap-around must not either: wrap[w]
+       records a wrapped add into sigma[w] at the current d[w] and is
+       cleared with sigma[w].  Overflow is a FINAL count above 2^64 - 1, so
+       the flag is raised from the wrap bits of the settled vertices once
+       every distance is final.  (If some final sigma_s(v) exceeds 2^64 - 1,
+       then at some vertex on the way the exact sum of its final
+       predecessors' counts does, and that add wraps; the converse holds
+       because a count that wrapped only feeds vertices whose own exact
+       count is at least as large.) */
     char *done = calloc((size_t)n, 1);
+    char *wrap = calloc((size_t)n, 1);
     int64_t hs = 0;
     heap_push(S, &hs, 0, s);
     while (hs > 0) {
@@ -268,13 +280,19 @@ static int64_t forward(const og *G, int32_t s, oscratch *S, int *ovf, oc *cnt) {
         if (nd < S->d[w]) {
           S->d[w] = nd;
           S->sigma[w] = S->sigma[v];
+          wrap[w] = 0;
           heap_push(S, &hs, nd, w);
         } else if (nd == S->d[w]) {
-          sigma_add(&S->sigma[w], S->sigma[v], ovf);
+          int c = 0;
+          sigma_add(&S->sigma[w], S->sigma[v], &c);
+          if (c) wrap[w] = 1;
         }
       }
     }
+    for (int64_t i = 0; i < settled; ++i)
+      if (wrap[S->order[i]]) *ovf = 1;
     free(done);
+    free(wrap);
     /* SPD arcs, counted on the final distances */
     for (int64_t i = 0; i < settled; ++i) {
       int32_t v = S->order[i];

@@ -74,19 +74,31 @@ def dependency(g, s, r, paths=None):
     return tot
 
 
-def reachers(g, r):
-    """RV(r) by Def.1: every v != r with a directed v->r path (transitive
-    closure by repeated relaxation, no BFS)."""
+def closure(g):
+    """reach[u][v]: a directed u->v path of at least one arc exists
+    (Warshall's transitive closure of the arc relation, no BFS)."""
     n = g.n
     reach = [[False] * n for _ in range(n)]
     for v in range(n):
         for e in range(int(g.row_ptr[v]), int(g.row_ptr[v + 1])):
             reach[v][int(g.col[e])] = True
-    for k in range(n):  # Warshall
+    for k in range(n):
         for i in range(n):
             if reach[i][k]:
                 ri, rk = reach[i], reach[k]
                 for j in range(n):
                     if rk[j]:
                         ri[j] = True
-    return sorted(v for v in range(n) if v != r and reach[v][r])
+    return reach
+
+
+def reachers(g, r, reach=None):
+    """RV(r) by Def.1: every v != r with a directed v->r path."""
+    reach = reach if reach is not None else closure(g)
+    return sorted(v for v in range(g.n) if v != r and reach[v][r])
+
+
+def reached_from(g, r, reach=None):
+    """Every t != r with a directed r->t path (the vertices r reaches)."""
+    reach = reach if reach is not None else closure(g)
+    return sorted(t for t in range(g.n) if t != r and reach[r][t])

@@ -24,17 +24,71 @@ def close(a, b, rel=1e-12):
 def test_all_digraphs_on_four_vertices(oracle):
     """Every one of the 4,096 digraphs on 4 vertices, every r: the oracle's
     E-BCD equals Eq.(1) evaluated by path enumeration; RV(r) equals the
-    transitive-closure set (Def.1 vs Def.3, Prop.2)."""
+    transitive-closure set (Def.1 vs Def.3, Prop.2); the count of vertices
+    r reaches (the bound K taken for Eq.(8)) equals the closure's count."""
     for code in range(1 << 12):
         g = gg.digraph_from_code(4, code)
         bc = BF.betweenness(g)
+        reach = BF.closure(g)
         for r in range(4):
             got, st = oracle.bc_exact(g, r, threads=1)
             assert close(got, float(bc[r])), (code, r, got, bc[r])
             rv = oracle.rv(g, r).tolist()
-            assert rv == BF.reachers(g, r), (code, r)
+            assert rv == BF.reachers(g, r, reach), (code, r)
+            assert oracle.fr_count(g, r) == len(BF.reached_from(g, r, reach)), (code, r)
             if g.out_degree()[r] == 0:
                 assert st["rv_size"] == -1 and got == 0.0
+
+
+def test_forward_reach_closed_forms_and_random(oracle):
+    """Vertices reached from r, r excluded: n-1-i on the directed path 0->..->n-1
+    (and RV(i) = {0..i-1} has the other i), n-1 on a cycle, b from the centre of
+    an in-out star, b+1 from an in-leaf, 0 from an out-leaf; random graphs of
+    7-10 vertices against the transitive closure.  Counting r itself, or
+    walking the reverse graph, fails the path and the star."""
+    n = 30
+    p = gg.directed_path(n)
+    assert [oracle.fr_count(p, i) for i in range(n)] == [n - 1 - i for i in range(n)]
+    c = gg.directed_cycle(11)
+    assert all(oracle.fr_count(c, i) == 10 for i in range(11))
+    st, centre = gg.in_out_star(4, 6)
+    assert oracle.fr_count(st, centre) == 6
+    assert all(oracle.fr_count(st, v) == 7 for v in range(1, 5))
+    assert all(oracle.fr_count(st, v) == 0 for v in range(5, 11))
+    for seed in range(10):
+        g = gg.random_small(7 + seed % 4, 0.2, seed=300 + seed)
+        reach = BF.closure(g)
+        for r in range(g.n):
+            assert oracle.fr_count(g, r) == len(BF.reached_from(g, r, reach)), (seed, r)
+
+
+def test_check_graph_accepts_and_rejects(oracle):
+    """The oracle's CSR validator (Section 2 graph model) against graphs built
+    to break exactly one rule, and the generated workloads it must accept."""
+    good = gg.Digraph(3, np.array([0, 2, 3, 3]), np.array([1, 2, 0], dtype=np.int32))
+    assert oracle.check_graph(good) == oracle.OK
+    wgood = gg.Digraph(3, good.row_ptr, good.col, np.array([1, 5, 2], dtype=np.uint32))
+    assert oracle.check_graph(wgood) == oracle.OK
+    bad = {
+        "row_ptr[0] != 0": (3, [1, 2, 3, 3], [1, 2, 0], None),
+        "row_ptr[n] != m": (3, [0, 2, 3, 2], [1, 2, 0], None),
+        "decreasing": (3, [0, 2, 1, 3], [1, 2, 0], None),
+        "head out of range": (3, [0, 2, 3, 3], [1, 3, 0], None),
+        "negative head": (3, [0, 2, 3, 3], [1, -1, 0], None),
+        "self-loop": (3, [0, 2, 3, 3], [0, 2, 0], None),
+        "repeated arc": (3, [0, 2, 3, 3], [2, 2, 0], None),
+        "unsorted row": (3, [0, 2, 3, 3], [2, 1, 0], None),
+        "zero weight": (3, [0, 2, 3, 3], [1, 2, 0], [1, 0, 1]),
+    }
+    for what, (n, rp, col, w) in bad.items():
+        g = gg.Digraph(n, np.array(rp, dtype=np.int64), np.array(col, dtype=np.int32),
+                       None if w is None else np.array(w, dtype=np.uint32))
+        assert oracle.check_graph(g) == oracle.BAD_GRAPH, what
+    empty = gg.Digraph(0, np.array([0]), np.array([], dtype=np.int32))
+    assert oracle.check_graph(empty) == oracle.INVALID
+    for g in (gg.er_2000()[0], gg.rmat(10, 8, seed=21), gg.with_weights(gg.rmat(9, 6, seed=5), seed=11, max_weight=7),
+              gg.superseded_tie_chain(63, 2)[0]):
+        assert oracle.check_graph(g) == oracle.OK, g.name
 
 
 @pytest.mark.parametrize("seed", range(12))
@@ -189,6 +243,35 @@ def test_sigma_exact_at_limit_and_overflow(oracle, kind):
     with pytest.raises(oracle.OracleError) as e:
         oracle.bc_exact(g64, ids64["x"][40])
     assert e.value.code == oracle.OVERFLOW
+
+
+def test_superseded_tie_is_not_overflow(oracle):
+    """Overflow means a FINAL path count above 2^64 - 1 (Section 2 counts over
+    shortest paths only).  On the weighted trap graph, t first gets the
+    tentative distance d(x_63) + 11 from p and q, whose counts (2^63 each)
+    add up to 2^64 and wrap; z then gives t the shorter distance d(x_63) + 3
+    with 2^63 paths.  No final count overflows, so the pass is exact and
+    BC(z) = 190 (the 190 chain vertices reach t only through z, one shortest
+    path each way as a fraction).  With a second such z, t really has 2^64
+    shortest paths, which must be reported."""
+    g, ids = gg.superseded_tie_chain(63, 1)
+    dist, sig, _, ovf, _ = oracle.source_pass(g, 0)
+    assert not ovf
+    assert all(int(sig[ids["x"][i]]) == 1 << i for i in range(64))
+    assert int(sig[ids["p"]]) == int(sig[ids["q"]]) == int(sig[ids["z"][0]]) == 1 << 63
+    assert int(sig[ids["t"]]) == 1 << 63
+    assert int(dist[ids["t"]]) == 2 * 63 + 3 and int(dist[ids["p"]]) == 2 * 63 + 1
+    assert oracle.bc_exact(g, ids["z"][0])[0] == 190.0
+    assert oracle.bc_exact(g, ids["p"])[0] == 0.0  # p lies on no shortest path to t
+    g2, ids2 = gg.superseded_tie_chain(63, 2)
+    _, sig2, _, ovf2, _ = oracle.source_pass(g2, 0)
+    assert ovf2 and int(sig2[ids2["z"][1]]) == 1 << 63
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.bc_exact(g2, ids2["z"][0])
+    assert e.value.code == oracle.OVERFLOW
+    # from a_1 (one diamond in) every count halves: nothing wraps, even with two z
+    _, _, _, ovf3, _ = oracle.source_pass(g2, ids2["a"][1])
+    assert not ovf3
 
 
 def test_grid_binomials_and_overflow(oracle):
