@@ -28,7 +28,24 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+GEN_SRC = os.path.join(HERE, "gen", "rmat_draws.c")
+GEN_LIB = os.path.join(HERE, "gen", "librmat_draws.so")
+
+
+def build_gen(verbose: bool = False) -> str:
+    """The C form of the input generator's R-MAT draws (host code, gcc)."""
+    tmp = GEN_LIB + ".tmp"
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-Wall", "-Wextra",
+           "-ffp-contract=off", "-o", tmp, GEN_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, GEN_LIB)
+    return GEN_LIB
+
+
 def build(verbose: bool = False) -> str:
+    build_gen(verbose)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *HIP_FLAGS, "-o", tmp, *sources(), "-lpthread"]
     if verbose:

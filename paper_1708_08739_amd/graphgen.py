@@ -17,7 +17,9 @@ positive integers (the paper assumes positive weights).
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
+import os
 
 import numpy as np
 
@@ -146,6 +148,57 @@ def erdos_renyi(n: int, m: int, seed: int) -> Digraph:
 
 RMAT_ABCD = (0.57, 0.19, 0.19, 0.05)
 
+_NATIVE_DRAWS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen", "librmat_draws.so")
+_native = None
+
+
+def _native_draws():
+    """The C form of the quadrant draws (gen/rmat_draws.c, built next to the
+    library), or None when it has not been built."""
+    global _native
+    if _native is None:
+        _native = False
+        if os.path.exists(_NATIVE_DRAWS):
+            lib = ctypes.CDLL(_NATIVE_DRAWS)
+            lib.rmat_draws.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int64, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+            lib.rmat_draws.restype = None
+            _native = lib
+    return _native or None
+
+
+def rmat_draws(scale: int, ne: int, seed: int, abcd=RMAT_ABCD, chunk: int = 1 << 21,
+               native: bool | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """The ``ne`` R-MAT draws before relabelling: at each of ``scale`` bit
+    levels (most significant first) value ``e * scale + level`` of stream
+    ``seed``, as a uniform double, picks quadrant a:(0,0) b:(0,1) c:(1,0)
+    d:(1,1) as (source bit, destination bit).  ``native`` None uses the C
+    form when built (same values), False forces NumPy."""
+    a, b, c, _ = abcd
+    t1, t2, t3 = a, a + b, a + b + c
+    lib = _native_draws() if native is not False else None
+    if lib is not None:
+        src = np.empty(ne, dtype=np.int64)
+        dst = np.empty(ne, dtype=np.int64)
+        lib.rmat_draws(seed & 0xFFFFFFFFFFFFFFFF, scale, ne, t1, t2, t3, src.ctypes.data, dst.ctypes.data)
+        return src, dst
+    if native:
+        raise RuntimeError("gen/librmat_draws.so is not built")
+    srcs = []
+    dsts = []
+    for e0 in range(0, ne, chunk):
+        ce = min(chunk, ne - e0)
+        u = unit(stream(seed, e0 * scale, ce * scale)).reshape(ce, scale)
+        sbit = (u >= t2).astype(np.int64)
+        dbit = (((u >= t1) & (u < t2)) | (u >= t3)).astype(np.int64)
+        wts = (np.int64(1) << np.arange(scale - 1, -1, -1, dtype=np.int64))
+        srcs.append(sbit @ wts)
+        dsts.append(dbit @ wts)
+        del u, sbit, dbit
+    if not srcs:
+        return np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64)
+    return np.concatenate(srcs), np.concatenate(dsts)
+
 
 def rmat(scale: int, edge_factor: int, seed: int, abcd=RMAT_ABCD,
          weighted: bool = False, max_weight: int = 100, chunk: int = 1 << 21,
@@ -163,21 +216,7 @@ def rmat(scale: int, edge_factor: int, seed: int, abcd=RMAT_ABCD,
     repeats are dropped after turning."""
     n = 1 << scale
     ne = edge_factor * n
-    a, b, c, _ = abcd
-    t1, t2, t3 = a, a + b, a + b + c
-    srcs = []
-    dsts = []
-    for e0 in range(0, ne, chunk):
-        ce = min(chunk, ne - e0)
-        u = unit(stream(seed, e0 * scale, ce * scale)).reshape(ce, scale)
-        sbit = (u >= t2).astype(np.int64)
-        dbit = (((u >= t1) & (u < t2)) | (u >= t3)).astype(np.int64)
-        wts = (np.int64(1) << np.arange(scale - 1, -1, -1, dtype=np.int64))
-        srcs.append(sbit @ wts)
-        dsts.append(dbit @ wts)
-        del u, sbit, dbit
-    src = np.concatenate(srcs)
-    dst = np.concatenate(dsts)
+    src, dst = rmat_draws(scale, ne, seed, abcd, chunk=chunk)
     perm = np.argsort(stream(seed + 1, 0, n), kind="stable").astype(np.int64)
     src = perm[src]
     dst = perm[dst]
@@ -394,3 +433,27 @@ def digraph_from_code(n: int, code: int) -> Digraph:
                 dst.append(v)
             k += 1
     return from_arcs(n, src, dst, name=f"code{n}_{code}")
+
+
+def superseded_tie_chain(k: int, final_paths: int) -> tuple[Digraph, dict]:
+    """A weighted trap for path counting: the diamond chain of ``k`` (every
+    arc length 1, so x_k has 2^k shortest paths from x_0), then x_k -> p and
+    x_k -> q (length 1), p -> t and q -> t (length 10), and ``final_paths``
+    vertices z_j with x_k -> z_j (length 2) and z_j -> t (length 1).  Before
+    any z_j is settled, t holds the tentative distance d(x_k) + 11 with the
+    counts of p and q added together; every z_j then gives t the shorter
+    distance d(x_k) + 3, reached only through the z_j.  Ids: the chain's
+    (``x``, ``a``, ``b``), then p, q, t and the z_j."""
+    g, ids = diamond_chain(k)
+    x = ids["x"][k]
+    p, q, t = g.n, g.n + 1, g.n + 2
+    zs = [g.n + 3 + j for j in range(final_paths)]
+    src, dst = [list(a) for a in g.arcs()]
+    w = [1] * g.m
+    for a, b, ln in [(x, p, 1), (x, q, 1), (p, t, 10), (q, t, 10)]:
+        src.append(a), dst.append(b), w.append(ln)
+    for z in zs:
+        for a, b, ln in [(x, z, 2), (z, t, 1)]:
+            src.append(a), dst.append(b), w.append(ln)
+    out = from_arcs(g.n + 3 + final_paths, src, dst, w, name=f"supersede{k}_{final_paths}")
+    return out, dict(ids, p=p, q=q, t=t, z=zs)

@@ -35,3 +35,15 @@ def test_dag_set_list(oracle):
     g = gg.rmat20_dag()
     for i in (0, 31, 63):
         assert oracle.rv(g, qs[i]).size == sizes[i]
+
+
+def test_native_rmat_draws_equal_numpy():
+    """The C form of the R-MAT quadrant draws gives the NumPy form's values
+    bit for bit (scales and seeds of several workloads, other thresholds)."""
+    from paper_1708_08739_amd import build
+    if not os.path.exists(build.GEN_LIB):
+        build.build_gen()
+    for scale, ef, seed, abcd in ((10, 8, 3, gg.RMAT_ABCD), (13, 16, 4, gg.RMAT_ABCD), (12, 8, 2, (0.45, 0.15, 0.15, 0.25))):
+        a = gg.rmat_draws(scale, ef << scale, seed, abcd, native=True)
+        b = gg.rmat_draws(scale, ef << scale, seed, abcd, native=False)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (scale, seed)
