@@ -1,24 +1,32 @@
 #!/usr/bin/env python3
-"""Benchmark: RV(r)-pruned exact betweenness of single vertices on one MI355X.
+"""Benchmark: RV(r)-pruned betweenness of single vertices on one MI355X.
 
-Default workload (one step): directed R-MAT scale 16, edge factor 8
-(a,b,c,d = .57,.19,.19,.05, seeded vertex relabelling, repeats and
-self-loops dropped), unweighted; the 8 query vertices are the 4 of largest
-out-degree plus 4 seeded uniform ones; each query is an exact BC(r) call
-(Alg.1) through the C ABI with the batched engine.  The graph is resident
-in HBM before timing starts.  Other workloads (--workload): er2000 (ER
-n=2,000, m=10,000, one exact query; LDS engine), rmat18w (weighted R-MAT
-18), rmat20set (set of 64 vertices on R-MAT 20), rmat20dagset (set of 64
-vertices with |RV(r)| spread from 15 to 1e5 on an acyclic R-MAT 20), rmat22serve (sampled
-queries through the server on R-MAT 22), rmat16bcd (the paper's BCD
+Default workload: serving sampled BC(r) queries (Alg.2, T from Eq.(8) with
+eps = 0.01 normalised, delta = 0.1, K = the vertices r reaches, seeded
+draws) on a directed R-MAT scale 22 graph (4,194,304 vertices, edge factor
+16, a,b,c,d = .57,.19,.19,.05, seeded relabelling, repeats and self-loops
+dropped, unweighted), CSR and transpose resident in HBM, through the
+library's server with a 64 GB HBM budget.  Query vertices are seeded
+uniform vertices with in- and out-arcs.  One step = 25 queries: the K
+steps' queries (500 at K = 20) are all submitted at once to a warm server
+and the timed region ends when the last one is reduced on the host, so
+the region is the saturation run; step i ends when 25 * i queries are
+done.  Then the same queries arrive as a Poisson process at 0.5x and 0.9x
+the measured saturation rate (p50/p99 latency from arrival to result).
+
+value = whole-job GTEPS = traversed arcs (sum of m_s over every source pass
+the server ran) / wall time of the timed region.
+
+Other workloads (--workload): rmat16 (R-MAT 16, edge factor 8, 8 exact
+queries, one step = the 8 queries), er2000 (ER n=2,000, m=10,000, one
+exact query; LDS engine), rmat18w (weighted R-MAT 18), rmat20set (set of
+64 vertices on R-MAT 20), rmat20dagset (set of 64 vertices with |RV(r)|
+spread from 15 to 1e5 on an acyclic R-MAT 20), rmat16bcd (the paper's BCD
 procedure and the unpruned sampling baseline on R-MAT 16, per query).
 
-value = whole-job GTEPS = sum over queries of traversed arcs (sum of m_s
-over the sources in RV(r)) / wall time of the K timed steps.
-
-Also printed on the same JSON line: p50/p99 per-query latency, the plain
-one-source-per-launch engine on a sample of sources, the forward kernel's
-HBM roofline figures, and the CPU oracle timed on a bounded sample.
+The JSON line also carries the forward kernels' HBM roofline figures, the
+plain one-source-per-launch engine on a sample of sources, and the CPU
+oracle timed on a bounded sample of the same work.
 """
 from __future__ import annotations
 
@@ -38,8 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, each scaled by what it reads for a copy kernel of known size),
 # valid only while the unweighted kernels' sources hash to the recorded value.
-TRAFFIC_FILES = {"k_fwd_level": "profiles/k_fwd_level_rmat16_ef8.md",
-                 "k_bwd_level": "profiles/k_fwd_level_rmat16_ef8.md"}
+TRAFFIC_FILES = {"k_fwd_level": ["profiles/k_fwd_level_rmat16_ef8.md"],
+                 "k_bwd_level": ["profiles/k_fwd_level_rmat16_ef8.md"],
+                 "k_fwd_level+k_bu_level": ["profiles/k_fwd_level_rmat22_serving.md"]}
 KERNEL_SOURCES = ["paper_1708_08739_amd/csrc/bcd_kernels.hip", "paper_1708_08739_amd/csrc/bcd_device.h",
                   "paper_1708_08739_amd/csrc/bcd_internal.h"]
 
@@ -57,52 +66,81 @@ def measured_traffic(kernel: str, workload_name: str, batch_width: int):
     """Counter-measured HBM bytes per launch of `kernel` on `workload_name` at
     `batch_width` sources per batch, or None when none were taken at that
     width or the kernel sources changed since."""
-    path = TRAFFIC_FILES.get(kernel)
-    if path is None or not os.path.exists(os.path.join(ROOT, path)):
-        return None
     rec = {}
-    with open(os.path.join(ROOT, path)) as fh:
-        for line in fh:
-            if line.startswith("traffic:"):
-                parts = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
-                if (parts.get("kernel") == kernel and parts.get("workload") == workload_name
-                        and parts.get("batch_width") == str(batch_width)):
-                    rec = parts
+    for path in TRAFFIC_FILES.get(kernel, []):
+        if not os.path.exists(os.path.join(ROOT, path)):
+            continue
+        with open(os.path.join(ROOT, path)) as fh:
+            for line in fh:
+                if line.startswith("traffic:"):
+                    parts = dict(kv.split("=", 1) for kv in line[len("traffic:"):].split())
+                    if (parts.get("kernel") == kernel and parts.get("workload") == workload_name
+                            and parts.get("batch_width") == str(batch_width)):
+                        rec = parts
     if not rec or rec.get("sources_sha256") != kernel_sources_sha256():
         return None
     return float(rec["bytes_per_launch"])
 
 
-def roofline_from_profile(G, fwd: dict, bwd: dict, ename: str, wname: str):
-    """HBM roofline of the dominant pass from the library's kernel profile:
-    algorithmic bytes over the busy time of its launches."""
+def roofline_from_profile(G, fwd: dict, bwd: dict, ename: str, wname: str, batch_width: int | None = None,
+                          probe_gbs: float | None = None, bottom_up: bool = False):
+    """HBM roofline of the dominant pass from the library's kernel profile.
+
+    Bytes: the per-source model (32 per (source, vertex) + 8 per (source,
+    arc) + 8 per (source, DAG arc) in each pass), and the schedule-aware
+    model that counts the graph structure once per work item (64 sources of
+    a column group at one vertex and level).  Time: launches of concurrent
+    batches overlap on their streams, so `achieved` and `frac` divide by the
+    union of the launch intervals (each instant counted once); the
+    per-launch figures divide by the summed durations.  `traffic` is the
+    counter-measured HBM bytes per launch recorded in profiles/ for this
+    workload and width, or None."""
     if fwd["launches"] == 0:
         return None
     dom, kind = (fwd, "forward") if fwd["total_ms"] >= bwd["total_ms"] else (bwd, "backward")
-    # Pipelined batches run launches of this kernel on two streams at once, so their
-    # event durations overlap: the rate is taken over the union of the launch intervals
-    # (each instant counted once); the per-launch average is kept beside it.
     busy_ms = dom["union_ms"] if dom["union_ms"] > 0 else dom["total_ms"]
     achieved = dom["alg_bytes"] / (busy_ms * 1e-3) / 1e9
     per_launch = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9
+    sched = dom.get("sched_bytes", 0.0) or 0.0
     if G.info()[2]:
         # weighted engine: the forward is three kernels (relaxation rounds, DAG
         # in-degrees, topological rounds), profiled together
         kname = "k_w_relax+k_w_count+k_w_sigma" if kind == "forward" else "k_w_bwd"
     elif ename == "lds":
         kname = "k_lds_pass"  # both passes in one kernel, timed as the forward
+    elif kind == "forward" and bottom_up:
+        kname = "k_fwd_level+k_bu_level"  # a level found bottom-up runs both, timed as two launches
     else:
         kname = f"k_{'fwd' if kind == 'forward' else 'bwd'}_level"
-    traffic = measured_traffic(kname, wname, 64 * G.config().groups if ename == "batched" else 1)
-    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if traffic is None else round(traffic, 1),
-            "kernel": kname,
-            "launches": dom["launches"], "avg_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 2),
-            "alg_bytes_per_launch": round(dom["alg_bytes"] / dom["launches"], 1),
-            "launch_union_ms": round(busy_ms, 3), "launch_sum_ms": round(dom["total_ms"], 3),
-            "per_launch_achieved": round(per_launch, 2),
-            "lanes_per_item": round(dom["vertex_pairs"] / dom["items"], 2) if dom["items"] else None}
+    if batch_width is None:
+        batch_width = 64 * G.config().groups if ename == "batched" else 1
+    traffic = measured_traffic(kname, wname, batch_width)
+    per_launch_s = dom["total_ms"] * 1e-3 / dom["launches"]
+    out = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else round(traffic, 1),
+           "kernel": kname,
+           "launches": dom["launches"], "avg_launch_us": round(per_launch_s * 1e6, 2),
+           "alg_bytes_per_launch": round(dom["alg_bytes"] / dom["launches"], 1),
+           "launch_union_ms": round(busy_ms, 3), "launch_sum_ms": round(dom["total_ms"], 3),
+           "per_launch_achieved": round(per_launch, 2),
+           "per_launch_frac": round(per_launch / HBM_PEAK_GBS, 4),
+           "lanes_per_item": round(dom["vertex_pairs"] / dom["items"], 2) if dom["items"] else None}
+    if sched > 0:
+        out["sched_bytes_per_launch"] = round(sched / dom["launches"], 1)
+        out["sched_achieved"] = round(sched / (busy_ms * 1e-3) / 1e9, 2)
+        out["sched_frac"] = round(out["sched_achieved"] / HBM_PEAK_GBS, 4)
+    if traffic is not None:
+        # counter bytes per launch over the per-launch time, and over the busy
+        # time (the launches of one timed region, overlapping)
+        out["traffic_achieved"] = round(traffic * dom["launches"] / (busy_ms * 1e-3) / 1e9, 2)
+        out["traffic_frac"] = round(out["traffic_achieved"] / HBM_PEAK_GBS, 4)
+    if probe_gbs:
+        out["probe_gbs"] = round(probe_gbs, 1)
+        out["probe_frac"] = round(achieved / probe_gbs, 4)
+        if sched > 0:
+            out["sched_probe_frac"] = round(out["sched_achieved"] / probe_gbs, 4)
+    return out
 
 
 def log(*a):
@@ -179,63 +217,199 @@ def select_uneven(G, g, k: int, seed: int, lo=10, hi=100000):
     return chosen, [sizes[v] for v in chosen]
 
 
-def serve(G, g, args):
-    """Serving: sampled BC(r) queries (eps = 0.01 normalised, delta = 0.1,
-    K = reach of r, seeded) on R-MAT; first all at t = 0 to find the
-    saturation throughput, then Poisson arrivals at a fraction of it."""
-    from paper_1708_08739_amd import bcd, graphgen as gg
+def serving_queries(g, count: int, seed: int) -> list[int]:
+    """`count` seeded uniform vertices with in- and out-arcs."""
+    from paper_1708_08739_amd import graphgen as gg
     ind, outd = g.in_degree(), g.out_degree()
-    pool = [v for v in gg.uniform_vertices(g.n, 20 * args.queries, seed=105) if ind[v] > 0 and outd[v] > 0]
-    qs = pool[: args.queries]
+    pool = [v for v in gg.uniform_vertices(g.n, 20 * count + 100, seed=seed) if ind[v] > 0 and outd[v] > 0]
+    if len(pool) < count:
+        raise SystemExit("not enough query vertices")
+    return pool[:count]
 
-    budget = args.hbm_budget << 30
-    groups = serving_width(lambda gr: bcd.Server.workspace_bytes(G, gr, args.workers), G.config().groups, budget)
-    log(f"[bench] serving: {args.workers} workers x {groups} groups, budget {args.hbm_budget} GiB")
 
-    def run(rate):
-        S = bcd.Server(G, workers=args.workers, groups=groups, hbm_budget_bytes=budget)
-        gaps = [0.0] * len(qs)
-        if rate > 0:
-            u = gg.unit(gg.stream(205, 0, len(qs)))
-            gaps = list(-np.log1p(-u) / rate)
+def hbm_free_bytes() -> int:
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    return int(free)
+
+
+def serve_bench(args):
+    """The serving workload: see the module docstring.  Prints the JSON line."""
+    import torch
+    from paper_1708_08739_amd import bcd, graphgen as gg
+    t_start = time.perf_counter()
+    g = gg.rmat22()
+    log(f"[bench] R-MAT 22 generated: n={g.n} m={g.m} ({time.perf_counter() - t_start:.1f} s)")
+    G = bcd.Graph.from_digraph(g)
+    kw = config_overrides(args)
+    if kw:
+        G.set_config(**kw)
+    cfg = G.config()
+    K, W, Q = args.steps, args.warmup, args.queries_per_step
+    qs = serving_queries(g, K * Q, seed=105)
+    warm = serving_queries(g, max(W * Q, 1), seed=106)[: W * Q]
+    if args.hbm_budget_gb > 0:
+        budget = int(args.hbm_budget_gb * 1e9)
+    else:  # all free HBM but 8 GB
+        budget = hbm_free_bytes() - (8 << 30)
+    groups = args.groups or serving_width(lambda gr: bcd.Server.workspace_bytes(G, gr, args.workers), 96, budget)
+    log(f"[bench] serving: {args.workers} workers x {groups} groups, HBM budget {budget / 1e9:.1f} GB, "
+        f"{K} steps x {Q} queries, {W} warm-up steps")
+    S = bcd.Server(G, workers=args.workers, groups=groups, hbm_budget_bytes=budget)
+
+    def submit_all(vertices, seed0, gaps=None):
+        """Submit every query (at the given arrival gaps), return the results."""
         t0 = time.perf_counter()
         arrive = 0.0
         tickets = {}
-        for i, r in enumerate(qs):
-            arrive += gaps[i]
-            while True:
-                rem = arrive - (time.perf_counter() - t0)
-                if rem <= 0:
-                    break
-                time.sleep(min(0.001, rem))
-            tickets[S.submit(bcd.BCD_QUERY_SAMPLED, r=r, eps=0.01, delta=0.1, seed=305 + i)] = r
+        for i, r in enumerate(vertices):
+            if gaps is not None:
+                arrive += gaps[i]
+                while True:
+                    rem = arrive - (time.perf_counter() - t0)
+                    if rem <= 0:
+                        break
+                    time.sleep(min(0.001, rem))
+            tickets[S.submit(bcd.BCD_QUERY_SAMPLED, r=r, eps=0.01, delta=0.1, seed=seed0 + i)] = i
+        return t0, tickets
+
+    def drain(tickets, step_every=0):
         res = []
-        while len(res) < len(qs):
+        done_steps = 0
+        while len(res) < len(tickets):
             res += S.poll(timeout_s=1.0)
-        wall = time.perf_counter() - t0
-        sst = S.stats()
-        S.close()
+            while step_every and len(res) >= (done_steps + 1) * step_every:
+                done_steps += 1
+                log(f"[bench] step {done_steps}/{len(tickets) // step_every} done")
         bad = [x for x in res if x["status"] != bcd.BCD_OK]
         if bad:
             raise SystemExit(f"serving: {len(bad)} queries failed: {bad[0]}")
-        lat = np.array([x["t_done_s"] - x["t_arrive_s"] for x in res])
-        te = sst["traversed_edges"]
-        return {"queries": len(qs), "wall_s": round(wall, 3), "qps": round(len(qs) / wall, 3),
-                "gteps": round(te / wall / 1e9, 3), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-                "samples_mean": float(np.mean([x["stats"]["samples"] for x in res])),
-                "batches": sst["batches"], "lane_occupancy": round(sst["lanes_used"] / max(sst["lane_slots"], 1), 3),
-                "shared_lanes": sst["shared_lanes"],
-                "distinct_sources_mean": float(np.mean([x["stats"]["distinct_sources"] for x in res]))}, te
-    sat, te = run(0.0)
-    log(f"[bench] serving saturation: {sat}")
-    out = {"workers": args.workers, "groups": groups, "hbm_budget_gib": args.hbm_budget,
-           "query_vertices": [int(v) for v in qs], "saturation": sat}
-    for frac in (0.5, 0.9):
-        r, _ = run(frac * sat["qps"])
-        log(f"[bench] serving at {frac} x saturation: {r}")
-        out[f"poisson_{frac}"] = r
-    return out
+        return res
+
+    if W > 0:
+        _, tk = submit_all(warm, 905)
+        drain(tk)
+        log(f"[bench] warm-up: {W} steps ({len(warm)} queries) done")
+    probe = None
+    if not args.no_probe:
+        probe = bcd.bcd_bandwidth_probe(4 << 30, 5)
+        log(f"[bench] copy probe: {probe:.1f} GB/s (4 GiB read + 4 GiB written per launch)")
+    if not args.no_profile:
+        G.profile_reset()
+        G.profile_enable(True)
+    st0 = S.stats()
+    torch.cuda.synchronize()
+    t0, tk = submit_all(qs, 305)
+    res = drain(tk, step_every=Q)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    G.profile_enable(False)
+    st1 = S.stats()
+    te = st1["traversed_edges"] - st0["traversed_edges"]
+    lat = np.array([x["t_done_s"] - x["t_arrive_s"] for x in res]) * 1e3
+    qps = len(qs) / wall
+    sat = {"queries": len(qs), "wall_s": round(wall, 3), "qps": round(qps, 3), "gteps": round(te / wall / 1e9, 3),
+           "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+           "samples_mean": float(np.mean([x["stats"]["samples"] for x in res])),
+           "distinct_sources_mean": float(np.mean([x["stats"]["distinct_sources"] for x in res])),
+           "exact_fallbacks": int(sum(x["stats"]["ran_exact"] for x in res)),
+           "batches": st1["batches"] - st0["batches"],
+           "lane_occupancy": round((st1["lanes_used"] - st0["lanes_used"]) /
+                                   max(st1["lane_slots"] - st0["lane_slots"], 1), 3),
+           "shared_lanes": st1["shared_lanes"] - st0["shared_lanes"]}
+    log(f"[bench] saturation: {sat}")
+    roof = None
+    if not args.no_profile:
+        roof = roofline_from_profile(G, G.profile(0), G.profile(1), "batched", wname_serving(args),
+                                     batch_width=64 * groups, probe_gbs=probe, bottom_up=cfg.bottom_up > 0)
+        log(f"[bench] roofline: {roof}")
+    poisson = {}
+    if not args.no_poisson:
+        for frac in (0.5, 0.9):
+            rate = frac * qps
+            u = gg.unit(gg.stream(205, 0, len(qs)))
+            gaps = list(-np.log1p(-u) / rate)
+            a = S.stats()
+            tp0, tk = submit_all(qs, 305, gaps)
+            r2 = drain(tk)
+            w2 = time.perf_counter() - tp0
+            b = S.stats()
+            l2 = np.array([x["t_done_s"] - x["t_arrive_s"] for x in r2]) * 1e3
+            poisson[f"poisson_{frac}"] = {
+                "rate_qps": round(rate, 3), "wall_s": round(w2, 3), "qps": round(len(qs) / w2, 3),
+                "gteps": round((b["traversed_edges"] - a["traversed_edges"]) / w2 / 1e9, 3),
+                "p50_ms": round(float(np.percentile(l2, 50)), 2), "p99_ms": round(float(np.percentile(l2, 99)), 2)}
+            log(f"[bench] Poisson arrivals at {frac} x saturation: {poisson[f'poisson_{frac}']}")
+    S.close()
+    plain = None
+    if args.plain_sources > 0:
+        plain = plain_form(G, g, qs[0], min(args.plain_sources, 16))
+        log(f"[bench] plain engine: {plain}")
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        rv = O.rv(g, qs[0])
+        idx = [int(gg.below(np.array([x], dtype=np.uint64), rv.size)[0]) for x in gg.stream(305, 0, 1024)]
+        src = rv[np.unique(np.array(idx, dtype=np.int64))] if rv.size else rv
+        cpu = cpu_baseline(g, qs[0], src, args.cpu_budget, args.cpu_threads,
+                           f"distinct drawn sources of the first query (r = {qs[0]}, |RV| = {rv.size}, "
+                           f"seed 305 draws)")
+        log(f"[bench] cpu baseline: {cpu}")
+    out = {
+        "metric": "GTEPS for RV(r)-pruned BC(r) on one MI355X; p50/p99 query latency",
+        "value": round(te / wall / 1e9, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(wall * 1e3 / K, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64+f64",
+        "data": "synthetic",
+        "config": {"workload": wname_serving(args), "graph": g.name, "n": g.n, "m": g.m,
+                   "queries": len(qs), "queries_per_step": Q, "query": "sampled eps=0.01 (normalised) delta=0.1",
+                   "hbm_budget_gb": round(budget / 1e9, 1), "workers": args.workers, "groups": groups,
+                   "batch_width": 64 * groups, "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items,
+                   "bottom_up": cfg.bottom_up},
+        "qps": sat["qps"],
+        "p50_query_ms": sat["p50_ms"],
+        "p99_query_ms": sat["p99_ms"],
+        "traversed_edges": int(te),
+        "saturation": sat,
+        **poisson,
+        "plain_form": plain,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "bench_wall_s": round(time.perf_counter() - t_start, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def wname_serving(args) -> str:
+    budget = f"{args.hbm_budget_gb:g}GB" if args.hbm_budget_gb > 0 else "freeHBM"
+    return f"rmat22_ef16_serving_sampled_{args.steps * args.queries_per_step}q_{budget}"
+
+
+def plain_form(G, g, r, nsrc):
+    """The plain engine (one source per launch, one launch per BFS level) on
+    the first sources of RV(r)."""
+    from paper_1708_08739_amd import bcd
+    rv = G.rv(r)
+    src = rv[:nsrc]
+    if src.size == 0:
+        return None
+    old = G.config().engine
+    G.set_config(engine=bcd.BCD_ENGINE_PLAIN)
+    G.dependencies(r, src[:2])
+    t = time.perf_counter()
+    G.dependencies(r, src)
+    dt = time.perf_counter() - t
+    G.set_config(engine=old)
+    _, cnt = G.dependencies(r, src, counters=True)
+    te_p = int(cnt[:, 1].sum())
+    return {"gteps": round(te_p / dt / 1e9, 3), "sources": int(src.size), "query": int(r)}
 
 
 def bcd_procedure(G, g, args):
@@ -294,28 +468,84 @@ def bcd_procedure(G, g, args):
     return te_bcd, t_bcd, summary, rows
 
 
-def cpu_baseline(g, r, budget_s: float, threads: int):
+def cpu_info() -> dict:
+    """Model, cores, hardware threads and clock of the host CPU (lscpu)."""
+    import subprocess
+    info = {"threads": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {a.strip(): b.strip() for a, b in (ln.split(":", 1) for ln in out.splitlines() if ":" in ln)}
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "1") or 1)
+        cores = int(kv.get("Core(s) per socket", "0") or 0)
+        info["cores"] = sockets * cores if cores else None
+        info["threads_per_core"] = kv.get("Thread(s) per core")
+        info["max_mhz"] = kv.get("CPU max MHz")
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except OSError:
+        pass
+    return info
+
+
+def cpu_baseline(g, r, src, budget_s: float, threads: int, what: str):
     """The oracle as it stands, on a bounded sample of the same work: the
-    per-source passes of seeded sources of RV(r), in chunks until about
-    ``budget_s`` seconds have been spent."""
+    per-source passes of `src` (sources of one query of the workload), in
+    chunks until about `budget_s` seconds have been spent, on `threads` host
+    threads (0: every thread this process may use, at most 64), then again on
+    one thread for a fifth of the budget."""
+    from oracle import oracle as O
+    info = cpu_info()
+    if threads <= 0:
+        threads = max(1, min(info.get("affinity") or os.cpu_count() or 1, 64))
+
+    def rate(nthreads, budget):
+        te = 0
+        done = 0
+        t0 = time.perf_counter()
+        chunk = max(1, 2 * nthreads)
+        while time.perf_counter() - t0 < budget and done < src.size:
+            part = src[done:done + chunk]
+            _, cnt = O.dependencies(g, r, part, threads=nthreads)
+            te += int(cnt[:, 1].sum())
+            done += part.size
+            chunk = min(chunk * 2, 8192)
+        return te, done, time.perf_counter() - t0
+
+    te, done, dt = rate(threads, budget_s)
+    te1, done1, dt1 = rate(1, budget_s / 5)
+    return {"value": te / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "sample": f"{done} {what}, per-source passes, {te} traversed arcs in {dt:.1f} s on {threads} threads",
+            "one_thread_gteps": te1 / dt1 / 1e9,
+            "one_thread_sample": f"{done1} of the same sources, {te1} traversed arcs in {dt1:.1f} s",
+            "cpu": info}
+
+
+def seeded_rv_sources(g, r):
+    """RV(r) in a seeded order (the CPU baseline's sample of a query)."""
     from oracle import oracle as O
     from paper_1708_08739_amd import graphgen as gg
     rv = O.rv(g, r)
-    order = np.argsort(gg.stream(12345, 0, rv.size), kind="stable")
-    te = 0
-    done = 0
-    t0 = time.perf_counter()
-    chunk = 4 * threads
-    while time.perf_counter() - t0 < budget_s and done < rv.size:
-        src = rv[order[done:done + chunk]]
-        _, cnt = O.dependencies(g, r, src, threads=threads)
-        te += int(cnt[:, 1].sum())
-        done += src.size
-        chunk = min(chunk * 2, 8192)
-    dt = time.perf_counter() - t0
-    return {"value": te / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
-            "sample": f"{done} seeded sources of RV({r}) (|RV| = {rv.size}), per-source passes, "
-                      f"{te} traversed arcs in {dt:.1f} s"}
+    return rv[np.argsort(gg.stream(12345, 0, rv.size), kind="stable")]
+
+
+def config_overrides(args) -> dict:
+    kw = {}
+    if args.groups and args.workload != "rmat22serve":
+        kw["groups"] = args.groups
+    if args.block:
+        kw["block"] = args.block
+    if args.grid_mult:
+        kw["grid_mult"] = args.grid_mult
+    if args.items:
+        kw["items"] = args.items
+    if args.bottom_up >= 0:
+        kw["bottom_up"] = args.bottom_up
+    if args.compress:
+        kw["compress"] = 1
+    return kw
 
 
 def serving_width(workspace_bytes, start: int, budget: int) -> int:
@@ -333,16 +563,18 @@ def serving_width(workspace_bytes, start: int, budget: int) -> int:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat16")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22serve",
+                    choices=["rmat22serve", "rmat16", "er2000", "rmat18w", "rmat20set", "rmat20dagset", "rmat16bcd"])
     ap.add_argument("--groups", type=int, default=0, help="64-source column groups per batch (0 = library default)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=0)
     ap.add_argument("--items", type=int, default=0, help="frontier items per wavefront step (0 = library default)")
     ap.add_argument("--bottom-up", type=int, default=-1,
                     help="bottom-up threshold denominator for the unweighted forward (0 = off, -1 = library default)")
-    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(cores, 16))")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads (0 = every thread this process may use, at most 64)")
     ap.add_argument("--compress", action="store_true",
                     help="exact and set calls fold sources with no in-arcs and one out-arc into their successor")
     ap.add_argument("--engine", choices=["auto", "batched", "lds", "plain"], default="auto",
@@ -352,17 +584,24 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--queries", type=int, default=64, help="serving: number of sampled queries")
-    ap.add_argument("--workers", type=int, default=6, help="serving: concurrent batches")
-    ap.add_argument("--hbm-budget", type=int, default=240, help="serving: HBM budget in GiB (288 GB on the GPU)")
+    ap.add_argument("--queries-per-step", type=int, default=25, help="serving: sampled queries per step")
+    ap.add_argument("--workers", type=int, default=3, help="serving: concurrent batches")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0,
+                    help="serving: HBM budget in GB (1e9 bytes) for workspaces and query buffers; 0 = all free HBM but 8 GiB")
+    ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson-arrival runs")
+    ap.add_argument("--no-probe", action="store_true", help="serving: skip the streaming-copy probe")
     ap.add_argument("--set-size", type=int, default=64)
     ap.add_argument("--probe-bw", action="store_true",
-                    help="also run the library's streaming-copy probe (1 GiB copied, known traffic)")
+                    help="also run the library's streaming-copy probe (4 GiB copied, known traffic)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs the whole path on a single MI355X "
               "(multi-GPU source sharding is designed but not built); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "rmat22serve":
+        serve_bench(args)
+        return
 
     import torch
     from paper_1708_08739_amd import bcd
@@ -370,27 +609,15 @@ def main():
     g, queries, wname = workload(args.workload)
     log(f"[bench] workload {wname}: n={g.n} m={g.m} queries={queries}")
     G = bcd.Graph.from_digraph(g)
-    kw = {}
-    if args.groups:
-        kw["groups"] = args.groups
-    if args.block:
-        kw["block"] = args.block
-    if args.grid_mult:
-        kw["grid_mult"] = args.grid_mult
-    if args.items:
-        kw["items"] = args.items
-    if args.bottom_up >= 0:
-        kw["bottom_up"] = args.bottom_up
-    if args.compress:
-        kw["compress"] = 1
+    kw = config_overrides(args)
     engines = {"batched": bcd.BCD_ENGINE_BATCHED, "lds": bcd.BCD_ENGINE_LDS, "plain": bcd.BCD_ENGINE_PLAIN}
     ename = args.engine if args.engine != "auto" else ("lds" if args.workload == "er2000" else "batched")
     cfg = G.set_config(engine=engines[ename], **kw)
     log(f"[bench] config groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult}")
 
-    if args.workload in ("rmat18w", "rmat20set", "rmat20dagset", "rmat22serve", "rmat16bcd"):
+    if args.workload in ("rmat18w", "rmat20set", "rmat20dagset", "rmat16bcd"):
         extra = {}
-        if not args.no_profile and args.workload != "rmat22serve":
+        if not args.no_profile:
             G.profile_reset()
             G.profile_enable(True)
         if args.workload == "rmat18w":
@@ -425,17 +652,14 @@ def main():
             wall = time.perf_counter() - t0
             extra = {"set_size": len(qs), "rv_sizes": sizes, "distinct_sources": st["distinct_sources"],
                      "steps": args.steps, "bc_first": [float(x) for x in bcs[:4]]}
-        elif args.workload == "rmat16bcd":
+        else:
             te, wall, summary, rows = bcd_procedure(G, g, args)
             lat = [x["t_ms"] / 1e3 for x in rows]
             extra = {"bcd_procedure": summary, "per_query": rows}
-        else:
-            srv = serve(G, g, args)
-            te, wall, lat = srv["saturation"]["gteps"] * 1e9 * srv["saturation"]["wall_s"], srv["saturation"]["wall_s"], [0]
-            extra = {"serving": srv}
-        if not args.no_profile and args.workload != "rmat22serve":
+        if not args.no_profile:
             G.profile_enable(False)
-            extra["roofline"] = roofline_from_profile(G, G.profile(0), G.profile(1), ename, wname)
+            extra["roofline"] = roofline_from_profile(G, G.profile(0), G.profile(1), ename, wname,
+                                                      bottom_up=G.config().bottom_up > 0)
             log(f"[bench] roofline: {extra['roofline']}")
         if not args.no_cpu:
             # the oracle on a bounded sample of one query's sources: for the set,
@@ -444,20 +668,17 @@ def main():
                 rq = queries[0]
             elif args.workload in ("rmat20set", "rmat20dagset"):
                 rq = qs[int(np.argmax(sizes))]
-            elif args.workload == "rmat16bcd":
-                rq = max(rows, key=lambda x: x["rv"])["r"]
             else:
-                rq = srv["query_vertices"][0]
-            threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
-            extra["cpu_baseline"] = cpu_baseline(g, rq, args.cpu_budget, threads)
+                rq = max(rows, key=lambda x: x["rv"])["r"]
+            extra["cpu_baseline"] = cpu_baseline(g, rq, seeded_rv_sources(g, rq), args.cpu_budget,
+                                                 args.cpu_threads, f"seeded sources of RV({rq})")
             log(f"[bench] cpu baseline: {extra['cpu_baseline']}")
         cfg = G.config()
         print(json.dumps({"metric": "GTEPS for RV(r)-pruned BC(r) on one MI355X; p50/p99 query latency",
                           "value": round(te / wall / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
                           "workload": wname, "wall_s": round(wall, 3), "traversed_edges": int(te),
                           "latencies_s": [round(x, 4) for x in lat][:16],
-                          "config": {"workload": wname, "n": g.n, "m": g.m,
-                                     "groups": extra.get("serving", {}).get("groups", cfg.groups),
+                          "config": {"workload": wname, "n": g.n, "m": g.m, "groups": cfg.groups,
                                      "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items,
                                      "bottom_up": cfg.bottom_up, "compress": cfg.compress},
                           **extra}), flush=True)
@@ -492,35 +713,25 @@ def main():
     fwd = G.profile(0)
     bwd = G.profile(1)
 
-    roofline = None if args.no_profile else roofline_from_profile(G, fwd, bwd, ename, wname)
+    bw = None
+    if args.probe_bw:
+        bw = round(bcd.bcd_bandwidth_probe(4 << 30, 5), 1)
+        log(f"[bench] copy probe: {bw} GB/s (4 GiB read + 4 GiB written per launch)")
+    roofline = None if args.no_profile else roofline_from_profile(G, fwd, bwd, ename, wname, probe_gbs=bw,
+                                                                  bottom_up=G.config().bottom_up > 0)
 
     # plain one-source-per-launch form on a sample of the same sources
     plain = None
     if args.plain_sources > 0:
-        r = queries[0]
-        rv = G.rv(r)
-        src = rv[: args.plain_sources]
-        G.set_config(engine=bcd.BCD_ENGINE_PLAIN)
-        G.dependencies(r, src[:8])
-        t = time.perf_counter()
-        G.dependencies(r, src)
-        dt = time.perf_counter() - t
-        G.set_config(engine=engines[ename])
-        _, cnt = G.dependencies(r, src, counters=True)
-        te_p = int(cnt[:, 1].sum())
-        plain = {"gteps": round(te_p / dt / 1e9, 3), "sources": int(src.size), "query": int(r)}
+        plain = plain_form(G, g, queries[0], args.plain_sources)
         log(f"[bench] plain engine: {plain}")
 
     cpu = None
     if not args.no_cpu:
-        threads = args.cpu_threads or min(os.cpu_count() or 1, 16)
-        cpu = cpu_baseline(g, queries[0], args.cpu_budget, threads)
+        r = queries[0]
+        cpu = cpu_baseline(g, r, seeded_rv_sources(g, r), args.cpu_budget, args.cpu_threads,
+                           f"seeded sources of RV({r})")
         log(f"[bench] cpu baseline: {cpu}")
-
-    bw = None
-    if args.probe_bw:
-        bw = round(bcd.bcd_bandwidth_probe(1 << 30, 3), 1)
-        log(f"[bench] copy probe: {bw} GB/s (1 GiB read + 1 GiB written per launch)")
 
     lat_ms = np.array(lat) * 1e3
     value = te_total / wall / 1e9

@@ -57,7 +57,7 @@ typedef enum bcd_status {
   BCD_ERR_BUFFER_TOO_SMALL = 6, /* *count holds the size needed */
   BCD_ERR_UNSUPPORTED = 7,      /* e.g. weighted distances would not fit uint32 */
   BCD_ERR_AGAIN = 8,            /* server: queue full, or poll timed out with nothing ready */
-  BCD_ERR_CANCELLED = 9         /* server: query cancelled by destroy */
+  BCD_ERR_CANCELLED = 9         /* server: query cancelled by shutdown or destroy */
 } bcd_status;
 
 /* Per-call statistics (all optional outputs). */
@@ -79,7 +79,7 @@ typedef struct bcd_stats {
 #define BCD_ENGINE_BATCHED 0 /* 64 sources per wavefront column group, many groups per launch */
 #define BCD_ENGINE_PLAIN 1   /* one source per launch, one launch per BFS level */
 #define BCD_ENGINE_LDS 2     /* small unweighted graphs: a workgroup runs a source's whole pass with its
-                                state in LDS (24 bytes per vertex must fit one workgroup's LDS, n < 2^16);
+                                state in LDS (16 bytes per vertex must fit one workgroup's LDS, n < 2^16);
                                 other graphs return BCD_ERR_UNSUPPORTED.  The server always batches. */
 
 typedef struct bcd_config {
@@ -247,6 +247,14 @@ typedef struct bcd_kernel_profile {
   double union_ms;       /* wall time during which at least one of these launches
                             ran: launches overlapping on concurrent streams
                             (pipelined batches) count once */
+  uint64_t item_arcs;    /* sum over the work items of their vertex's out-degree
+                            (batched unweighted engine; else 0) */
+  double sched_bytes;    /* algorithmic bytes with the graph structure counted once
+                            per work item instead of once per source: 16 per item
+                            (row offsets) + 4 per item arc (column index) + 16 per
+                            (source, vertex) + 4 per (source, arc) + 8 per (source,
+                            DAG arc); equal to alg_bytes for engines that share
+                            nothing across sources; 0 where not counted (weighted) */
 } bcd_kernel_profile;
 
 bcd_status bcd_profile_enable(bcd_graph *g, int32_t on);
@@ -254,7 +262,9 @@ bcd_status bcd_profile_get(const bcd_graph *g, int32_t kind, bcd_kernel_profile 
 bcd_status bcd_profile_reset(bcd_graph *g);
 
 /* Streaming-copy probe: achieved device bandwidth (GB/s, read+write) of a
- * plain copy of `bytes` bytes, best of `reps`. */
+ * copy of `bytes` bytes (rounded down to 16-byte words; 16-byte loads, four
+ * in flight per thread, 8 workgroups of 256 per compute unit), best of `reps`
+ * after one untimed launch. */
 bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps);
 
 /* -------------------------------------------------------------- serving
@@ -332,7 +342,14 @@ bcd_status bcd_server_get_stats(bcd_server *s, bcd_server_stats *out);
 
 /* Library steady-clock time in seconds (the clock of the t_* fields). */
 double bcd_server_now(void);
-/* Stop: queued queries finish with CANCELLED, running batches drain.  NULL is a no-op. */
+/* Stop taking work: later submits fail with CANCELLED; queries not yet
+ * admitted finish with status CANCELLED; admitted queries run to completion.
+ * Returns once nothing is admitted or being planned; every query's result
+ * (value or CANCELLED) can still be collected with bcd_server_poll.  Errors:
+ * INVALID_ARG for NULL. */
+bcd_status bcd_server_shutdown(bcd_server *s);
+/* bcd_server_shutdown, then stop the threads and release every buffer;
+ * results not yet polled are discarded.  NULL is a no-op. */
 bcd_status bcd_server_destroy(bcd_server *s);
 
 #ifdef __cplusplus

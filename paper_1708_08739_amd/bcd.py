@@ -64,7 +64,8 @@ class SampleParams(C.Structure):
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("alg_bytes", C.c_double),
                 ("vertex_pairs", C.c_uint64), ("arc_pairs", C.c_uint64), ("dag_pairs", C.c_uint64),
-                ("items", C.c_uint64), ("union_ms", C.c_double)]
+                ("items", C.c_uint64), ("union_ms", C.c_double), ("item_arcs", C.c_uint64),
+                ("sched_bytes", C.c_double)]
 
 
 class ServerConfig(C.Structure):
@@ -131,6 +132,7 @@ SIGNATURES = {
     "bcd_server_create": [_p, C.POINTER(ServerConfig), C.POINTER(_p)],
     "bcd_server_submit": [_p, C.POINTER(Query), C.POINTER(_u64)],
     "bcd_server_poll": [_p, _p, _i32, C.POINTER(_i32), _i64],
+    "bcd_server_shutdown": [_p],
     "bcd_server_destroy": [_p],
     "bcd_server_get_stats": [_p, C.POINTER(ServerStats)],
     "bcd_server_workspace_bytes": [_p, _i32, _i32, C.POINTER(_u64)],
@@ -407,6 +409,11 @@ class Server:
     @staticmethod
     def now() -> float:
         return load().bcd_server_now()
+
+    def shutdown(self):
+        """Cancel queries not yet admitted, let admitted ones finish; results
+        stay pollable."""
+        check(load().bcd_server_shutdown(self.h), "bcd_server_shutdown")
 
     def close(self):
         if getattr(self, "h", None):

@@ -69,6 +69,35 @@ __device__ __forceinline__ void flush_counters(uint64_t *ctr, int slots, int k0,
   }
 }
 
+// Add wave-uniform counters (the same value on every lane of a wavefront)
+// into this workgroup's slot: counter slot k[i] receives the sum over the
+// workgroup's wavefronts of v[i]; an overflow on any lane raises flags[0].
+// Every thread of the workgroup must call it (once per launch).
+template <int BLOCK, int NV>
+__device__ __forceinline__ void flush_wave_counters(uint64_t *ctr, int slots, const int (&k)[NV],
+                                                    const uint64_t (&v)[NV], bool ovf, uint32_t *flags) {
+  __shared__ uint64_t red[NV][BLOCK / 64];
+  __shared__ int any_ovf;
+  if (threadIdx.x == 0) any_ovf = 0;
+  __syncthreads();
+  if (ovf) any_ovf = 1;
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0)
+    for (int i = 0; i < NV; ++i) red[i][w] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if ((int)blockIdx.x < slots) {
+      uint64_t *p = ctr + (size_t)blockIdx.x * C_COUNT;
+      for (int i = 0; i < NV; ++i) {
+        uint64_t s = 0;
+        for (int j = 0; j < BLOCK / 64; ++j) s += red[i][j];
+        p[k[i]] += s;
+      }
+    }
+    if (any_ovf) atomicOr(&flags[0], 1u);
+  }
+}
+
 // Per-wavefront LDS staging of list appends: values are collected in an LDS
 // buffer and copied out with one tail atomic per block, so a list's shared
 // tail counter is not hit once per appended element.

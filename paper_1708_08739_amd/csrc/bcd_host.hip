@@ -103,6 +103,9 @@ Workspace::~Workspace() { release(); }
 
 void Workspace::release() {
   release_weighted();
+  dfree(d_tgt_list);
+  dfree(d_routes);
+  tgt_list_cap = routes_cap = 0;
   if (lds_dev) (void)hipFree(lds_dev);
   if (lds_host) (void)hipHostFree(lds_host);
   lds_dev = lds_host = nullptr;
@@ -289,6 +292,26 @@ bcd_status Workspace::ensure_res(size_t need) {
   return BCD_OK;
 }
 
+bcd_status Workspace::ensure_server_lists(size_t ntgt, size_t nroutes) {
+  ntgt = std::max<size_t>(ntgt, 1);
+  nroutes = std::max<size_t>(nroutes, 1);
+  if (ntgt > tgt_list_cap) {
+    const size_t cap = std::max<size_t>(ntgt, 2 * tgt_list_cap + 64);
+    dfree(d_tgt_list);
+    tgt_list_cap = 0;
+    STCHK(dalloc(&d_tgt_list, cap));
+    tgt_list_cap = cap;
+  }
+  if (nroutes > routes_cap) {
+    const size_t cap = std::max<size_t>(nroutes, 2 * routes_cap + 1024);
+    dfree(d_routes);
+    routes_cap = 0;
+    STCHK(dalloc(&d_routes, cap));
+    routes_cap = cap;
+  }
+  return BCD_OK;
+}
+
 bcd_status Workspace::ensure_dout() {
   if (S.dout) return BCD_OK;
   return dalloc(&S.dout, (size_t)G * (size_t)n * kLanes);
@@ -460,12 +483,15 @@ bcd_status Graph::mark_profile_origin() {
 }
 
 void Graph::add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
-                        uint64_t items, const std::vector<std::pair<double, double>> *intervals) {
+                        uint64_t items, const std::vector<std::pair<double, double>> *intervals,
+                        uint64_t item_arcs, double sched_bytes) {
   std::lock_guard<std::mutex> lk(prof_mu);
   bcd_kernel_profile &p = prof[kind];
   p.launches += launches;
   p.total_ms += ms;
   p.alg_bytes += alg_bytes;
+  p.item_arcs += item_arcs;
+  p.sched_bytes += sched_bytes < 0 ? alg_bytes : sched_bytes;
   p.vertex_pairs += c3[0];
   p.arc_pairs += c3[1];
   p.dag_pairs += c3[2];
@@ -719,8 +745,9 @@ bcd_status bcd_profile_reset(bcd_graph *gh) {
 bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
   BCD_GUARD_BEGIN
   if (bytes < 1024 || reps < 1 || !gbps) return fail(BCD_ERR_INVALID_ARG, "bad argument");
-  STCHK(device_check(nullptr));
-  const int64_t count = bytes / 8;
+  int cus = 0;
+  STCHK(device_check(&cus));
+  const int64_t count = bytes / 16 * 2;  // doubles, a whole number of 16-byte words
   double *a = nullptr, *b = nullptr;
   STCHK(dalloc(&a, (size_t)count));
   if (dalloc(&b, (size_t)count) != BCD_OK) {
@@ -741,7 +768,8 @@ bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
   double best = 0;
   for (int i = 0; i < reps + 1 && rc == BCD_OK; ++i) {
     (void)hipEventRecord(e0, st);
-    if (launch_copy_probe(a, b, count, st) != hipSuccess) rc = fail(BCD_ERR_DEVICE, "copy probe launch failed");
+    if (launch_copy_probe(a, b, count / 2, std::max(1, cus) * 8, st) != hipSuccess)
+      rc = fail(BCD_ERR_DEVICE, "copy probe launch failed");
     (void)hipEventRecord(e1, st);
     if (hipEventSynchronize(e1) != hipSuccess) rc = fail(BCD_ERR_DEVICE, "copy probe failed");
     float ms = 0;

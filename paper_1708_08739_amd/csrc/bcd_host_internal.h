@@ -110,6 +110,13 @@ struct Workspace {
   uint64_t *h_misc = nullptr;
   uint64_t *h_ctr = nullptr;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  // server batches: target list and result routes, grown on demand and kept
+  // (a free in the batch loop would wait for every stream of the device)
+  int32_t *d_tgt_list = nullptr;
+  size_t tgt_list_cap = 0;
+  ResultRoute *d_routes = nullptr;
+  size_t routes_cap = 0;
+  bcd_status ensure_server_lists(size_t ntgt, size_t nroutes);
   // LDS engine scratch (bcd_lds.hip), grown on demand
   void *lds_dev = nullptr;
   size_t lds_dev_bytes = 0;
@@ -180,7 +187,8 @@ struct Graph {
   void release(std::unique_ptr<Workspace> w);
   void trim_pool();  // free the device memory of idle pooled workspaces
   void add_profile(int kind, int64_t launches, double ms, const uint64_t *c3, double alg_bytes,
-                   uint64_t items = 0, const std::vector<std::pair<double, double>> *intervals = nullptr);
+                   uint64_t items = 0, const std::vector<std::pair<double, double>> *intervals = nullptr,
+                   uint64_t item_arcs = 0, double sched_bytes = -1.0);
   int64_t outdeg(int64_t v) const { return h_rp[(size_t)v + 1] - h_rp[(size_t)v]; }
 };
 
@@ -282,8 +290,14 @@ bcd_status multi_source_pass_lds(Graph *g, Workspace *ws, const int32_t *sources
 // One batch of `k` sources already staged in ws->h_items0 / h_masks0 with
 // ntgt targets installed in ws->S.tgt_of; per-lane target dependencies stay
 // in ws->S.res on the device; per-group overflow lanes go to ovl_out[G].
-bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
-bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf);
+// Launch timings go to *prof when the graph's profiling is on (may be NULL).
+bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf,
+                            ProfAcc *prof);
+bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf,
+                             ProfAcc *prof);
+// Add one run's launch timings and its device counters to the graph's profile.
+void record_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr);
+void record_wprofile(Graph *g, const ProfAcc &p, const uint64_t *ctr);
 double compensated_sum(const double *x, size_t k, size_t stride);
 // Positions of src in the order batches should take them (sources with
 // similar hub-distance signatures together); results never depend on it.

@@ -37,7 +37,11 @@ enum Ctr {
   C_BWD_DPAIRS = 5,  // (source, DAG arc) pairs the backward kernel accumulated
   C_RLX_APAIRS = 6,  // (source, arc) relaxations of the weighted distance rounds (6..8)
   C_SCRATCH = 9,     // unused slots for kernels that only report overflow (9..11)
-  C_COUNT = 12
+  C_FWD_ITEMS = 12,  // work items (64-source group, vertex, level) of the forward
+  C_FWD_IARCS = 13,  // sum over those items of the vertex's out-degree
+  C_BWD_ITEMS = 14,  // work items the backward computed psi for
+  C_BWD_IARCS = 15,  // sum over those items of the vertex's out-degree
+  C_COUNT = 16
 };
 
 // Device state of one batch of G column groups (64 sources each) over an
@@ -183,6 +187,6 @@ hipError_t launch_route_results(const double *res, const ResultRoute *routes, in
 // Add the per-workgroup counter slots into acc[C_COUNT] and zero them (one
 // launch after every completed batch; an aborted batch just zeroes them).
 hipError_t launch_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc, hipStream_t st);
-hipError_t launch_copy_probe(const double *src, double *dst, int64_t n, hipStream_t st);
+hipError_t launch_copy_probe(const void *src, void *dst, int64_t n16, int grid, hipStream_t st);
 
 }  // namespace bcd

@@ -46,7 +46,7 @@ __global__ void k_batch_init(BatchState S, const uint32_t *items0, const ull *ma
 // unsigned wrap on any add means the true sum exceeds 2^64 - 1.
 template <int K, bool HIT = false>
 static __device__ __forceinline__ void pull_slots(const BatchState &S, uint64_t gbase, uint32_t u, ull pm, int lane,
-                                                  ull (&acc)[K], bool (&lov)[K], bool (&hit)[K]) {
+                                                  ull (&acc)[K], bool (&lov)[K], bool (&hit)[K], uint64_t &dag_pairs) {
   constexpr int SUB = kLanes / K;
   ull bits = __ballot(pm != 0ull);
   while (bits != 0ull) {
@@ -65,6 +65,7 @@ static __device__ __forceinline__ void pull_slots(const BatchState &S, uint64_t 
         const uint32_t uq = read_lane(u, j[q]);
         const ull dq = read_lane64(pm, j[q]);
         const uint64_t gq = read_lane64(gbase, j[q]);
+        dag_pairs += (uint64_t)__popcll(dq);  // wave-uniform
         if ((dq >> lane) & 1ull) x[q] = S.sig[(gq + uq) * kLanes + lane];
       }
     }
@@ -206,7 +207,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
   const bool pull = !bottom_up_rule(S.bu_den, level, prev, S.gused, S.n);
   const bool disc = !bottom_up_rule(S.bu_den, level + 1, cur, S.gused, S.n);
 
-  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  // counters, all wave-uniform: (source, vertex), (source, arc) and
+  // (source, DAG arc) pairs; items and the out-degree sum over items
+  uint64_t c_v = 0, c_a = 0, c_d = 0, c_it = 0, c_ia = 0;
   bool ovf = false;
   const uint64_t step = pv.nwaves * (uint64_t)K;
   uint32_t *next_cnt = &S.cnt[(uint64_t)(level + 1) * P + pv.p];
@@ -237,14 +240,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
       if (pull) tg = S.tgt_of[v];
     }
     const int64_t d1 = disc ? e1 : e0;  // end of the out-arcs to scan
-    if (has && sl == 0) {
-      if (pull) {
-        rec[it].vis = rec[it].vis | mask;
-        const uint64_t pc = (uint64_t)__popcll(mask);
-        c_v += pc;
-        c_a += pc * (uint64_t)(e1 - e0);
-      }
-    }
+    if (has && sl == 0 && pull) rec[it].vis = rec[it].vis | mask;
     // first chunk of in-arcs (sigma pull) and of out-arcs (discovery) of
     // every slot, interleaved: 1. both index chunks
     const int64_t mi = f0 + sl, mo = e0 + sl;
@@ -275,11 +271,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
       acc[t] = 0ull;
       lov[t] = false;
     }
-    c_d += (uint64_t)__popcll(pm);
     // a DAG tail's lanes that are a target or below one: the same record
     // line as its level mask, loaded beside the predecessor rows
     const ull pdn = pm != 0ull ? rec[gbase + u].dn : 0ull;
-    pull_slots<K>(S, gbase, u, pm, lane, acc, lov, lov);
+    pull_slots<K>(S, gbase, u, pm, lane, acc, lov, lov, c_d);
     ull dnacc[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) dnacc[t] = 0ull;
@@ -300,6 +295,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
       const uint64_t gbt = read_lane64(gbase, ld);
       const int64_t F1 = (int64_t)read_lane64((ull)f1, ld), E1 = (int64_t)read_lane64((ull)d1, ld);
       const int64_t F0 = (int64_t)read_lane64((ull)f0, ld), E0 = (int64_t)read_lane64((ull)e0, ld);
+      const uint64_t deg = (uint64_t)((int64_t)read_lane64((ull)e1, ld) - E0);
+      c_it += 1;
+      c_ia += deg;
+      if (pull) {  // a level found bottom-up was counted there
+        c_v += (uint64_t)__popcll(mt);
+        c_a += (uint64_t)__popcll(mt) * deg;
+      }
       for (int64_t e = F0 + SUB; e < F1; e += kLanes) {
         const int64_t my = e + lane;
         uint32_t uu = 0;
@@ -309,10 +311,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
           pp = rec[gbt + uu].fr[kp] & mt;
           if (pp != 0ull) pd = rec[gbt + uu].dn;
         }
-        c_d += (uint64_t)__popcll(pp);
         ull a1[1] = {acc[t]};
         bool l1[1] = {lov[t]};
-        pull_slots<1>(S, gbt, uu, pp, lane, a1, l1, l1);
+        pull_slots<1>(S, gbt, uu, pp, lane, a1, l1, l1, c_d);
         acc[t] = a1[0];
         lov[t] = l1[0];
         ull d1[1] = {0ull};
@@ -356,7 +357,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
     }
   }
   flush_stage(S, stage, nst, next_cnt, nbase, rend);
-  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
+  const int ck[5] = {C_FWD_VPAIRS, C_FWD_APAIRS, C_FWD_DPAIRS, C_FWD_ITEMS, C_FWD_IARCS};
+  const uint64_t cv[5] = {c_v, c_a, c_d, c_it, c_ia};
+  flush_wave_counters<BLOCK, 5>(S.ctr, S.ctr_slots, ck, cv, ovf, S.flags);
 }
 
 // 64-bit lane shuffle (ds_bpermute on both halves).
@@ -455,8 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
         lov[t] = false;
         hit[t] = false;
       }
-      c_d += (uint64_t)__popcll(pm);
-      pull_slots<K, true>(S, gbase, u, pm, lane, acc, lov, hit);
+      pull_slots<K, true>(S, gbase, u, pm, lane, acc, lov, hit, c_d);
       ull dnacc[K];
 #pragma unroll
       for (int t = 0; t < K; ++t) dnacc[t] = 0ull;
@@ -475,10 +477,9 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
             pp = rec[gbase + uu].fr[kp] & ut;
             pd = rec[gbase + uu].dn;
           }
-          c_d += (uint64_t)__popcll(pp);
           ull a1[1] = {acc[t]};
           bool l1[1] = {lov[t]}, h1[1] = {hit[t]};
-          pull_slots<1, true>(S, gbase, uu, pp, lane, a1, l1, h1);
+          pull_slots<1, true>(S, gbase, uu, pp, lane, a1, l1, h1, c_d);
           acc[t] = a1[0];
           lov[t] = l1[0];
           hit[t] = h1[0];
@@ -503,17 +504,18 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
           rec[it].fr[kc] = nm;
           rec[it].vis = rec[it].vis | nm;
           if (dnt != 0ull) rec[it].dn = rec[it].dn | dnt;
-          const uint64_t pc = (uint64_t)__popcll(nm);
-          c_v += pc;
-          c_a += pc * (uint64_t)(e1 - e0);
         }
+        c_v += (uint64_t)__popcll(nm);
+        c_a += (uint64_t)__popcll(nm) * (uint64_t)(e1 - e0);
         if (tg >= 0 && lane == 0) atomicMin(S.tmin, (uint32_t)level);
         append_chunk(S, stage, nst, cnt_here, base, rend, gbase, wt, lane == 0);
       }
     }
   }
   flush_stage(S, stage, nst, cnt_here, base, rend);
-  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_FWD_VPAIRS, c_v, c_a, c_d, ovf, S.flags);
+  const int ck[3] = {C_FWD_VPAIRS, C_FWD_APAIRS, C_FWD_DPAIRS};
+  const uint64_t cv[3] = {c_v, c_a, c_d};  // wave-uniform
+  flush_wave_counters<BLOCK, 3>(S.ctr, S.ctr_slots, ck, cv, ovf, S.flags);
 }
 
 // Sum of psi_b(w) over the out-arcs held by one chunk of lanes whose head w
@@ -524,7 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_bu_level(DevGraph G, BatchState S, in
 // Row loads of up to eight successors are issued before any is consumed.
 template <int K>
 static __device__ __forceinline__ void push_sum_slots(const BatchState &S, uint64_t gbase, uint32_t w, ull d,
-                                                      int lane, double (&acc)[K]) {
+                                                      int lane, double (&acc)[K], uint64_t &dag_pairs) {
   constexpr int SUB = kLanes / K;
   ull bits = __ballot(d != 0ull);
   while (bits != 0ull) {
@@ -542,6 +544,7 @@ static __device__ __forceinline__ void push_sum_slots(const BatchState &S, uint6
         const uint32_t wq = read_lane(w, j[q]);
         const ull dq = read_lane64(d, j[q]);
         const uint64_t gq = read_lane64(gbase, j[q]);
+        dag_pairs += (uint64_t)__popcll(dq);  // wave-uniform
         if ((dq >> lane) & 1ull) x[q] = S.psi[(gq + wq) * kLanes + lane];
       }
     }
@@ -587,7 +590,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
   const LevMask *bt_in = S.bt + (uint64_t)((level + 1) & 1) * GN;
   LevMask *bt_out = S.bt + (uint64_t)(level & 1) * GN;
   const uint32_t E = S.epoch;
-  uint64_t c_v = 0, c_a = 0, c_d = 0;
+  uint64_t c_v = 0, c_a = 0, c_d = 0, c_it = 0, c_ia = 0;  // wave-uniform counters
   const uint64_t step = pv.nwaves * (uint64_t)K;
   uint64_t ii = pv.wave * (uint64_t)K + (uint64_t)(lane / SUB);  // this lane's item
   // the next step's ids and masks are loaded while this one is processed
@@ -639,11 +642,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
       const ull mw = (tw.lev == (uint32_t)(level + 1) && tw.epoch == E) ? tw.mask : 0ull;
       d = my_em & mw;
     }
-    c_d += (uint64_t)__popcll(d);
     double acc[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) acc[t] = 0.0;
-    push_sum_slots<K>(S, gbase, w, d, lane, acc);
+    push_sum_slots<K>(S, gbase, w, d, lane, acc, c_d);
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       const ull em = emv[t];
@@ -664,9 +666,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
           const ull mw = (tw.lev == (uint32_t)(level + 1) && tw.epoch == E) ? tw.mask : 0ull;
           dd = em & mw;
         }
-        c_d += (uint64_t)__popcll(dd);
         double a1[1] = {acc[t]};
-        push_sum_slots<1>(S, gbt, ww, dd, lane, a1);
+        push_sum_slots<1>(S, gbt, ww, dd, lane, a1, c_d);
         acc[t] = a1[0];
       }
       const int32_t tgt = (int32_t)read_lane((uint32_t)tg, ld);
@@ -684,13 +685,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
         o.lev = (uint32_t)level;
         o.epoch = E;
         bt_out[itt] = o;
-        const uint64_t pc = (uint64_t)__popcll(em);
-        c_v += pc;
-        c_a += pc * (uint64_t)(E1 - E0);
       }
+      c_v += (uint64_t)__popcll(em);
+      c_a += (uint64_t)__popcll(em) * (uint64_t)(E1 - E0);
+      c_it += 1;
+      c_ia += (uint64_t)(E1 - E0);
     }
   }
-  flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
+  const int ck[5] = {C_BWD_VPAIRS, C_BWD_APAIRS, C_BWD_DPAIRS, C_BWD_ITEMS, C_BWD_IARCS};
+  const uint64_t cv[5] = {c_v, c_a, c_d, c_it, c_ia};
+  flush_wave_counters<BLOCK, 5>(S.ctr, S.ctr_slots, ck, cv, false, S.flags);
 }
 
 // Reset what the batch touched: the masks of every item.  (Path counts need
@@ -920,9 +924,20 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
   stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
 }
 
-__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+// Streaming copy of n16 16-byte words: every thread keeps four 16-byte loads
+// in flight (one per grid stride) before it stores them, so the probe is
+// bound by HBM and not by the latency of one load at a time.
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * nth < n16; i += 4 * nth) {
+    const uint4 a = src[i], b = src[i + nth], c = src[i + 2 * nth], d = src[i + 3 * nth];
+    dst[i] = a;
+    dst[i + nth] = b;
+    dst[i + 2 * nth] = c;
+    dst[i + 3 * nth] = d;
+  }
+  for (; i < n16; i += nth) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------ launchers
@@ -1070,8 +1085,9 @@ hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *b
   return hipGetLastError();
 }
 
-hipError_t launch_copy_probe(const double *src, double *dst, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, st, src, dst, n);
+hipError_t launch_copy_probe(const void *src, void *dst, int64_t n16, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, static_cast<const uint4 *>(src), static_cast<uint4 *>(dst),
+                     n16);
   return hipGetLastError();
 }
 

@@ -361,7 +361,7 @@ bcd_status run_lds(Graph *g, Workspace *ws, const std::vector<int32_t> &src, con
                    bool want_counters, SourceRun &out) {
   if (!lds_fits(g))
     return fail(BCD_ERR_UNSUPPORTED, "the LDS engine needs an unweighted graph whose per-source state fits one "
-                                     "workgroup's LDS (24 bytes per vertex)");
+                                     "workgroup's LDS (16 bytes per vertex)");
   const size_t ns = src.size();
   const int ntgt = (int)tgt.size();
   out.dep.assign(ns * (size_t)ntgt, 0.0);
@@ -400,7 +400,7 @@ bcd_status multi_source_pass_lds(Graph *g, Workspace *ws, const int32_t *sources
                                  uint64_t *sigma, double *delta) {
   if (!lds_fits(g))
     return fail(BCD_ERR_UNSUPPORTED, "the LDS engine needs an unweighted graph whose per-source state fits one "
-                                     "workgroup's LDS (24 bytes per vertex)");
+                                     "workgroup's LDS (16 bytes per vertex)");
   const size_t kn = (size_t)k * (size_t)g->n;
   uint64_t *dd = nullptr;
   unsigned long long *ds = nullptr;

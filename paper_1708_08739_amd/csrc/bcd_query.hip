@@ -389,10 +389,23 @@ static void add_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr) {
   // kernels share reads across sources):
   //   forward : 32 per (source, vertex) + 8 per (source, arc) + 8 per (source, DAG arc)
   //   backward: 32 per (source, vertex) + 8 per (source, arc) + 8 per (source, DAG arc)
+  // of which the graph structure is 16 per vertex (its two row offsets) and
+  // 4 per arc (its column index).  Counted once per work item (64 sources of
+  // a column group at one vertex and level) instead of once per source, the
+  // structure gives the schedule-aware figure.
   const double fb = 32.0 * ctr[C_FWD_VPAIRS] + 8.0 * ctr[C_FWD_APAIRS] + 8.0 * ctr[C_FWD_DPAIRS];
   const double bb = 32.0 * ctr[C_BWD_VPAIRS] + 8.0 * ctr[C_BWD_APAIRS] + 8.0 * ctr[C_BWD_DPAIRS];
-  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb, p.items[0], &p.iv[0]);
-  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb, p.items[1], &p.iv[1]);
+  const bool per_item = ctr[C_FWD_ITEMS] > 0;  // the batched kernels count items on the device
+  const double fs = per_item ? 16.0 * ctr[C_FWD_ITEMS] + 4.0 * ctr[C_FWD_IARCS] + 16.0 * ctr[C_FWD_VPAIRS] +
+                                   4.0 * ctr[C_FWD_APAIRS] + 8.0 * ctr[C_FWD_DPAIRS]
+                             : fb;
+  const double bs = per_item ? 16.0 * ctr[C_BWD_ITEMS] + 4.0 * ctr[C_BWD_IARCS] + 16.0 * ctr[C_BWD_VPAIRS] +
+                                   4.0 * ctr[C_BWD_APAIRS] + 8.0 * ctr[C_BWD_DPAIRS]
+                             : bb;
+  g->add_profile(0, p.launches[0], p.ms[0], ctr + C_FWD_VPAIRS, fb, per_item ? ctr[C_FWD_ITEMS] : p.items[0],
+                 &p.iv[0], ctr[C_FWD_IARCS], fs);
+  g->add_profile(1, p.launches[1], p.ms[1], ctr + C_BWD_VPAIRS, bb, per_item ? ctr[C_BWD_ITEMS] : p.items[1],
+                 &p.iv[1], ctr[C_BWD_IARCS], bs);
 }
 
 // The batches b = first, first + stride, ... of the ordered source list on
@@ -723,9 +736,15 @@ static bcd_status run_plain(Graph *g, Workspace *ws, const std::vector<int32_t> 
   return BCD_OK;
 }
 
-bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
-  if (g->weighted) return run_staged_wbatch(g, ws, k, ntgt, ovl_out, ovf);
-  return run_one_batch(g, ws, k, ntgt, false, nullptr, nullptr, ovf, false, ovl_out);
+bcd_status run_staged_batch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf,
+                            ProfAcc *prof) {
+  if (g->weighted) return run_staged_wbatch(g, ws, k, ntgt, ovl_out, ovf, prof);
+  return run_one_batch(g, ws, k, ntgt, false, nullptr, prof, ovf, false, ovl_out);
+}
+
+void record_profile(Graph *g, const ProfAcc &p, const uint64_t *ctr) {
+  if (g->weighted) record_wprofile(g, p, ctr);
+  else add_profile(g, p, ctr);
 }
 
 bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,

@@ -27,6 +27,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -68,14 +69,22 @@ struct bcd_server {
   std::condition_variable cv_plan;     // planner: new submissions / budget freed / stop
   std::condition_variable cv_work;     // workers: admitted work / stop
   std::condition_variable cv_done;     // pollers
+  std::condition_variable cv_drained;  // shutdown: planner idle and nothing admitted
   std::deque<std::shared_ptr<bcd::SQuery>> submitted;
   std::deque<std::shared_ptr<bcd::SQuery>> active;  // admitted, in admission order
   std::deque<bcd_result> finished;
   size_t outstanding = 0;  // submitted and not yet polled
-  size_t reserved = 0;     // bytes of admitted queries' buffers
+  size_t reserved = 0;     // bytes of the buffers admitted queries hold
+  // device result buffers of finished queries, kept for reuse by size (a
+  // free in the serving loop would wait for every stream of the device);
+  // reserved + cached never exceeds budget_q
+  std::multimap<size_t, double *> cache;
+  size_t cached = 0;
   size_t budget_q = 0;     // budget left for query buffers after workspaces
   uint64_t next_ticket = 1;
   bool stop = false;
+  bool closing = false;    // shutdown: no new submissions, nothing more admitted
+  bool planning = false;   // the planner holds a query it took from `submitted`
   std::thread planner;
   std::vector<std::thread> workers;
   std::vector<std::unique_ptr<bcd::Workspace>> wss;
@@ -153,16 +162,26 @@ static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
     st.rv_size = -1;
     return BCD_OK;
   }
-  STCHK(reach_set(g, ws, r, true, bits, &k, nullptr));
+  const bcd_sample_params &p = q.q.params;
+  // the unpruned baseline of bcd_bc_sampled: every vertex but r is a
+  // candidate source, with n - 1 in Eq.(8) and no exact fallback
+  const bool all_v = q.q.kind == BCD_QUERY_SAMPLED && (p.flags & BCD_SAMPLE_ALL_VERTICES) != 0;
   std::vector<int32_t> rv;
-  bits_to_list(bits, g->n, r, rv);
+  if (all_v) {
+    rv.reserve((size_t)g->n - 1);
+    for (int64_t v = 0; v < g->n; ++v)
+      if (v != r) rv.push_back((int32_t)v);
+    k = (int64_t)rv.size();
+  } else {
+    STCHK(reach_set(g, ws, r, true, bits, &k, nullptr));
+    bits_to_list(bits, g->n, r, rv);
+  }
   st.rv_size = k;
   if (q.q.kind == BCD_QUERY_EXACT) {
     q.sources = std::move(rv);
     st.distinct_sources = (int64_t)q.sources.size();
     return BCD_OK;
   }
-  const bcd_sample_params &p = q.q.params;
   int64_t T = p.T_override;
   if (T <= 0) {
     double K = (double)(g->n - 2);
@@ -178,7 +197,7 @@ static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
   }
   st.samples = T;
   if (k == 0) return BCD_OK;
-  if (T >= k && !(p.flags & BCD_NO_EXACT_FALLBACK)) {
+  if (T >= k && !(p.flags & (BCD_NO_EXACT_FALLBACK | BCD_SAMPLE_ALL_VERTICES))) {
     st.ran_exact = 1;
     q.sources = std::move(rv);
   } else {
@@ -198,6 +217,13 @@ static bcd_status plan_query(bcd_server *S, Workspace *ws, SQuery &q) {
   return BCD_OK;
 }
 
+// The planner has disposed of the query it took (posted or admitted); called
+// with the server lock held.
+static void plan_done(bcd_server *S) {
+  S->planning = false;
+  S->cv_drained.notify_all();
+}
+
 static void planner_loop(bcd_server *S) {
   Workspace *ws = S->plan_ws.get();
   for (;;) {
@@ -208,6 +234,7 @@ static void planner_loop(bcd_server *S) {
       if (S->stop) return;
       q = S->submitted.front();
       S->submitted.pop_front();
+      S->planning = true;
     }
     const double t0 = steady_now();
     bcd_status rc = BCD_OK;
@@ -225,6 +252,12 @@ static void planner_loop(bcd_server *S) {
     std::unique_lock<std::mutex> lk(S->mu);
     if (rc != BCD_OK) {
       post_result(S, q, rc);
+      plan_done(S);
+      continue;
+    }
+    if (S->closing) {
+      post_result(S, q, BCD_ERR_CANCELLED);
+      plan_done(S);
       continue;
     }
     if (cells == 0) {  // nothing to compute (out-degree 0, empty RV)
@@ -233,6 +266,7 @@ static void planner_loop(bcd_server *S) {
       if (q->q.kind == BCD_QUERY_SET)
         for (size_t i = 0; i < q->rs.size(); ++i) q->q.bc_out[i] = 0.0;
       post_result(S, q, BCD_OK);
+      plan_done(S);
       continue;
     }
     if (q->bytes > S->budget_q) {
@@ -240,36 +274,63 @@ static void planner_loop(bcd_server *S) {
       fail(BCD_ERR_OUT_OF_MEMORY, "query result buffer exceeds the server's HBM budget");
       lk.lock();
       post_result(S, q, BCD_ERR_OUT_OF_MEMORY);
+      plan_done(S);
       continue;
     }
     // admission: wait until the buffer fits the budget
-    S->cv_plan.wait(lk, [&] { return S->stop || S->reserved + q->bytes <= S->budget_q; });
-    if (S->stop) {
+    S->cv_plan.wait(lk, [&] { return S->stop || S->closing || S->reserved + q->bytes <= S->budget_q; });
+    if (S->stop || S->closing) {
       post_result(S, q, BCD_ERR_CANCELLED);
-      return;
+      plan_done(S);
+      if (S->stop) return;
+      continue;
+    }
+    // a cached buffer of fitting size (at most twice the need), else a new
+    // one once the cache has given back what the budget needs
+    const size_t need = q->bytes;
+    std::vector<double *> trim;
+    auto it = S->cache.lower_bound(need);
+    if (it != S->cache.end() && it->first <= 2 * need && S->reserved + it->first <= S->budget_q) {
+      q->dres = it->second;
+      q->bytes = it->first;
+      S->cached -= it->first;
+      S->cache.erase(it);
+    } else {
+      while (!S->cache.empty() && S->reserved + S->cached + need > S->budget_q) {
+        auto last = std::prev(S->cache.end());
+        trim.push_back(last->second);
+        S->cached -= last->first;
+        S->cache.erase(last);
+      }
     }
     S->reserved += q->bytes;
     lk.unlock();
+    for (double *p : trim) (void)hipFree(p);
     bcd_status arc = BCD_OK;
-    if (hipMalloc((void **)&q->dres, q->bytes) != hipSuccess) {
+    if (!q->dres && hipMalloc((void **)&q->dres, q->bytes) != hipSuccess) {
       (void)hipGetLastError();
       q->dres = nullptr;
       arc = BCD_ERR_OUT_OF_MEMORY;
-    } else if (hipMemsetAsync(q->dres, 0, q->bytes, ws->stream) != hipSuccess ||
+    } else if (hipMemsetAsync(q->dres, 0, need, ws->stream) != hipSuccess ||
                hipStreamSynchronize(ws->stream) != hipSuccess) {
       arc = BCD_ERR_DEVICE;
     }
     lk.lock();
     if (arc != BCD_OK) {
       S->reserved -= q->bytes;
-      if (q->dres) (void)hipFree(q->dres);
+      if (q->dres) {
+        S->cache.emplace(q->bytes, q->dres);
+        S->cached += q->bytes;
+      }
       q->dres = nullptr;
       post_result(S, q, arc);
+      plan_done(S);
       continue;
     }
     q->res.t_admit_s = steady_now();
     S->active.push_back(q);
     S->cv_work.notify_all();
+    plan_done(S);
   }
 }
 
@@ -278,8 +339,12 @@ struct Lane {
   std::vector<std::pair<std::shared_ptr<SQuery>, uint32_t>> users;  // (query, source slot)
 };
 
+// Called with the server lock held: the buffer goes back to the cache.
 static void release_query(bcd_server *S, SQuery &q) {
-  if (q.dres) (void)hipFree(q.dres);
+  if (q.dres) {
+    S->cache.emplace(q.bytes, q.dres);
+    S->cached += q.bytes;
+  }
   q.dres = nullptr;
   S->reserved -= q.bytes;
   S->cv_plan.notify_all();
@@ -332,6 +397,7 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
     const int k = (int)lanes.size();
     int32_t *d_t = nullptr;
     ResultRoute *d_routes = nullptr;
+    ProfAcc prof;
     bool ovf = false;
     uint64_t ctr[C_COUNT] = {0};
     int ntgt = 0;
@@ -366,13 +432,10 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
               routes.push_back(rr);
             }
           }
-        if (rc == BCD_OK && (hipMalloc((void **)&d_t, (size_t)std::max(ntgt, 1) * sizeof(int32_t)) != hipSuccess ||
-                             hipMalloc((void **)&d_routes, std::max<size_t>(routes.size(), 1) * sizeof(ResultRoute)) !=
-                                 hipSuccess)) {
-          (void)hipGetLastError();
-          rc = BCD_ERR_OUT_OF_MEMORY;
-        }
+        if (rc == BCD_OK) rc = ws->ensure_server_lists((size_t)ntgt, routes.size());
         if (rc == BCD_OK) {
+          d_t = ws->d_tgt_list;
+          d_routes = ws->d_routes;
           hipError_t e = hipMemcpyAsync(d_t, tg.data(), (size_t)ntgt * sizeof(int32_t), hipMemcpyHostToDevice, ws->stream);
           if (e == hipSuccess)
             e = hipMemcpyAsync(d_routes, routes.data(), routes.size() * sizeof(ResultRoute), hipMemcpyHostToDevice,
@@ -380,7 +443,7 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
           if (e == hipSuccess) e = launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 1, ws->stream);
           if (e != hipSuccess) rc = BCD_ERR_DEVICE;
         }
-        if (rc == BCD_OK) rc = run_staged_batch(g, ws, k, ntgt, ovl.data(), &ovf);
+        if (rc == BCD_OK) rc = run_staged_batch(g, ws, k, ntgt, ovl.data(), &ovf, &prof);
         if (rc == BCD_OK) {
           hipError_t e = launch_route_results(ws->S.res, d_routes, (int)routes.size(), ws->stream);
           if (e == hipSuccess) e = hipStreamSynchronize(ws->stream);
@@ -389,12 +452,11 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
         if (d_t) {
           (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
           (void)hipStreamSynchronize(ws->stream);
-          (void)hipFree(d_t);
         }
-        if (d_routes) (void)hipFree(d_routes);
         d_t = nullptr;
         d_routes = nullptr;
         if (rc == BCD_OK) rc = collect_counters(ws, ctr, ws->S.acc);
+        if (rc == BCD_OK && g->profiling.load()) record_profile(g, prof, ctr);
       }
     } catch (const std::bad_alloc &) {
       rc = BCD_ERR_OUT_OF_MEMORY;
@@ -408,8 +470,6 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
       if (d_t) (void)launch_scatter_targets(ws->S.tgt_of, d_t, ntgt, 0, ws->stream);
       (void)ws->reset_batch_dense();
       (void)hipStreamSynchronize(ws->stream);
-      if (d_t) (void)hipFree(d_t);
-      if (d_routes) (void)hipFree(d_routes);
     }
     // account
     std::vector<std::shared_ptr<SQuery>> complete;
@@ -451,6 +511,7 @@ static void worker_loop(bcd_server *S, Workspace *ws) {
       release_query(S, *q);
       S->stats.queries_done += 1;
       post_result(S, q, status);
+      S->cv_drained.notify_all();
     }
   }
 }
@@ -569,7 +630,7 @@ bcd_status bcd_server_submit(bcd_server *S, const bcd_query *q, uint64_t *ticket
   if (q->kind == BCD_QUERY_SET) sq->rs.assign(q->rs, q->rs + q->l);
   sq->q.rs = nullptr;
   std::lock_guard<std::mutex> lk(S->mu);
-  if (S->stop) return fail(BCD_ERR_CANCELLED, "server is stopping");
+  if (S->stop || S->closing) return fail(BCD_ERR_CANCELLED, "server is shutting down");
   if (S->outstanding >= (size_t)S->cfg.queue_capacity) return fail(BCD_ERR_AGAIN, "queue full");
   sq->ticket = S->next_ticket++;
   sq->res.ticket = sq->ticket;
@@ -613,9 +674,26 @@ bcd_status bcd_server_get_stats(bcd_server *S, bcd_server_stats *out) {
   BCD_GUARD_END
 }
 
+bcd_status bcd_server_shutdown(bcd_server *S) {
+  BCD_GUARD_BEGIN
+  if (!S) return fail(BCD_ERR_INVALID_ARG, "NULL argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->closing = true;
+  // queries not yet taken by the planner are cancelled now; the planner
+  // cancels the one it holds unless it was already admitted
+  for (auto &q : S->submitted) post_result(S, q, BCD_ERR_CANCELLED);
+  S->submitted.clear();
+  S->cv_plan.notify_all();
+  // admitted queries run to completion (their batches may already be in flight)
+  S->cv_drained.wait(lk, [&] { return !S->planning && S->submitted.empty() && S->active.empty(); });
+  return BCD_OK;
+  BCD_GUARD_END
+}
+
 bcd_status bcd_server_destroy(bcd_server *S) {
   BCD_GUARD_BEGIN
   if (!S) return BCD_OK;
+  (void)bcd_server_shutdown(S);
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
@@ -631,6 +709,9 @@ bcd_status bcd_server_destroy(bcd_server *S) {
   }
   S->active.clear();
   S->submitted.clear();
+  for (auto &c : S->cache) (void)hipFree(c.second);
+  S->cache.clear();
+  S->cached = 0;
   delete S;
   return BCD_OK;
   BCD_GUARD_END

@@ -745,18 +745,19 @@ static bcd_status wcounters(Workspace *ws, uint64_t *c) { return collect_counter
 
 // Algorithmic bytes per (source, element) pair: 32 per vertex, 12 per arc
 // (head index, arc length, head distance), 8 per DAG arc, in each pass.
-static void wprofile(Graph *g, const ProfAcc &p, const uint64_t *c) {
+void record_wprofile(Graph *g, const ProfAcc &p, const uint64_t *c) {
   const double fb = 32.0 * c[C_FWD_VPAIRS] + 12.0 * c[C_FWD_APAIRS] + 8.0 * c[C_FWD_DPAIRS];
   const double bb = 32.0 * c[C_BWD_VPAIRS] + 12.0 * c[C_BWD_APAIRS] + 8.0 * c[C_BWD_DPAIRS];
-  g->add_profile(0, p.launches[0], p.ms[0], c + C_FWD_VPAIRS, fb, p.items[0], &p.iv[0]);
-  g->add_profile(1, p.launches[1], p.ms[1], c + C_BWD_VPAIRS, bb, p.items[1], &p.iv[1]);
+  g->add_profile(0, p.launches[0], p.ms[0], c + C_FWD_VPAIRS, fb, p.items[0], &p.iv[0], 0, 0.0);
+  g->add_profile(1, p.launches[1], p.ms[1], c + C_BWD_VPAIRS, bb, p.items[1], &p.iv[1], 0, 0.0);
 }
 
-bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf) {
+bcd_status run_staged_wbatch(Graph *g, Workspace *ws, int k, int ntgt, unsigned long long *ovl_out, bool *ovf,
+                             ProfAcc *prof) {
   if ((uint64_t)g->n * (uint64_t)g->max_w >= 0xFFFFFFFFull)
     return fail(BCD_ERR_UNSUPPORTED, "n * max weight must stay below 2^32 - 1 for 32-bit distances");
   STCHK(ws->ensure_weighted());
-  return run_one_wbatch(g, ws, k, ntgt, false, nullptr, nullptr, ovf, false, ovl_out);
+  return run_one_wbatch(g, ws, k, ntgt, false, nullptr, prof, ovf, false, ovl_out);
 }
 
 bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src, const std::vector<int32_t> &tgt,
@@ -821,7 +822,7 @@ bcd_status run_weighted(Graph *g, Workspace *ws, const std::vector<int32_t> &src
   out.te = tot[C_FWD_APAIRS];
   out.reached = tot[C_FWD_VPAIRS];
   out.dag = tot[C_FWD_DPAIRS];
-  if (g->profiling.load()) wprofile(g, prof, tot);
+  if (g->profiling.load()) record_wprofile(g, prof, tot);
   if (ovf) return fail(BCD_ERR_SIGMA_OVERFLOW, "a shortest-path count exceeded 2^64 - 1");
   return BCD_OK;
 }

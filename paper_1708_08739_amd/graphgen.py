@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import functools
 import os
 
 import numpy as np
@@ -307,10 +308,12 @@ def rmat18_weighted() -> tuple[Digraph, list[int]]:
     return g, queries_top_and_random(g, seed=103)
 
 
+@functools.lru_cache(maxsize=1)
 def rmat20() -> Digraph:
     return rmat(20, 16, seed=4)
 
 
+@functools.lru_cache(maxsize=1)
 def rmat22() -> Digraph:
     return rmat(22, 16, seed=5)
 
@@ -457,3 +460,11 @@ def superseded_tie_chain(k: int, final_paths: int) -> tuple[Digraph, dict]:
             src.append(a), dst.append(b), w.append(ln)
     out = from_arcs(g.n + 3 + final_paths, src, dst, w, name=f"supersede{k}_{final_paths}")
     return out, dict(ids, p=p, q=q, t=t, z=zs)
+
+
+def seeded_subset(count: int, k: int, seed: int, skip: int = 0) -> np.ndarray:
+    """Positions ``skip .. skip+k-1`` of a seeded shuffle of ``range(count)``
+    (the order of stream ``seed``'s values), ascending: ``k`` distinct
+    positions, disjoint from those of any other ``skip`` window."""
+    order = np.argsort(stream(seed, 0, count), kind="stable")
+    return np.sort(order[skip: skip + k]).astype(np.int64)

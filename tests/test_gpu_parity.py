@@ -453,7 +453,7 @@ def test_weighted_bc_and_counters(B, oracle):
     g1 = gg.with_unit_weights(gg.rmat(10, 8, seed=3))
     g0 = gg.rmat(10, 8, seed=3)
     r = gg.top_out_degree(g0, 1)[0]
-    assert dev(B, g1).bc_exact(r)[0] == dev(B, g0).bc_exact(r)[0] or close(dev(B, g1).bc_exact(r)[0], dev(B, g0).bc_exact(r)[0])
+    assert dev(B, g1).bc_exact(r)[0] == dev(B, g0).bc_exact(r)[0]
 
 
 def test_weighted_many_batches_two_streams(B, oracle):
@@ -599,6 +599,37 @@ def test_weighted_sigma_overflow(B, oracle, mixed):
         assert int(sg[0][ids40["x"][40]]) == 1 << 40
 
 
+def test_weighted_superseded_tie_is_not_overflow(B, oracle):
+    """The weighted trap graph: t first gets a tentative distance from p and q
+    whose path counts (2^63 each) would wrap, then a shorter distance through
+    z with 2^63 paths.  Only final counts matter: the weighted engine, batched
+    and one source per batch, returns the oracle's distances and counts bit
+    for bit and BC(z) = 190; with a second z the 2^64 final paths of t are an
+    overflow on both engines."""
+    g, ids = gg.superseded_tie_chain(63, 1)
+    od, osg, odl, ovf, _ = oracle.source_pass(g, 0)
+    assert not ovf
+    src = [0, ids["a"][1], ids["x"][40], ids["p"], ids["z"][0]]
+    want = [oracle.source_pass(g, s) for s in src]
+    for cfg in (dict(groups=1), dict(groups=2, block=256), dict(engine=B.BCD_ENGINE_PLAIN)):
+        print("supersede", cfg, flush=True)
+        G = dev(B, g, **cfg)
+        d, sg, dl = G.source_pass(0)
+        assert np.array_equal(d, od) and np.array_equal(sg, osg), cfg
+        assert int(sg[ids["t"]]) == 1 << 63 and close(dl, odl), cfg
+        md, msg, mdl = G.multi_source_pass(src)
+        for i, s in enumerate(src):
+            assert np.array_equal(md[i], want[i][0]) and np.array_equal(msg[i], want[i][1]), (cfg, s)
+            assert close(mdl[i], want[i][2]), (cfg, s)
+        assert G.bc_exact(ids["z"][0])[0] == 190.0 == oracle.bc_exact(g, ids["z"][0])[0]
+    g2, ids2 = gg.superseded_tie_chain(63, 2)
+    for cfg in (dict(groups=1), dict(engine=B.BCD_ENGINE_PLAIN)):
+        G = dev(B, g2, **cfg)
+        with pytest.raises(B.BcdError) as e:
+            G.bc_exact(ids2["z"][0])
+        assert e.value.code == B.BCD_ERR_SIGMA_OVERFLOW, cfg
+
+
 @pytest.mark.parametrize("weighted", [False, True])
 def test_compression_folds_leaf_sources(B, oracle, weighted):
     """Compression on (sources with no in-arcs and one out-arc take their
@@ -652,24 +683,70 @@ def _sampled_parity(B, oracle, g, r, nsrc, seed, **cfg):
     odep, ocnt = oracle.dependencies(g, r, pick)
     assert close(dep, odep)
     assert np.array_equal(cnt, ocnt)
-    # the same sources inside one full-width batch (bench configuration)
-    assert np.array_equal(G.dependencies(r, pick), dep)
     return G, rv
 
 
-def test_rmat18_weighted_sampled_sources(B, oracle):
-    """R-MAT scale 18, edge factor 16, weights in [1,100]."""
+def _full_width(B, g, r, rv, tracked, seed, width):
+    """Dependencies of the tracked sources computed inside one batch of the
+    full width: the list is padded with further seeded sources of RV(r)
+    (positions disjoint from the tracked ones) up to `width`, then the
+    tracked sources' results are picked out."""
+    pad = rv[gg.seeded_subset(rv.size, max(0, width - tracked.size), seed, skip=tracked.size)]
+    allsrc = np.concatenate([tracked, pad]).astype(np.int32)
+    assert allsrc.size == min(width, rv.size) and np.unique(allsrc).size == allsrc.size
+    return allsrc, tracked.size
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    src = np.array([int(x[0]) for x in rows], dtype=np.int32)
+    dep = np.array([float.fromhex(x[1]) for x in rows])
+    cnt = np.array([[int(x[2]), int(x[3]), int(x[4])] for x in rows], dtype=np.uint64)
+    return src, dep, cnt
+
+
+def test_rmat18_weighted_full_width(B, oracle):
+    """R-MAT scale 18, edge factor 16, weights in [1,100], in the bench's
+    width of 128 column groups: 1,024 seeded sources of RV(r) against the
+    oracle inside one batch of 8,192 (the rest seeded padding from RV(r)),
+    and again in a narrow batch."""
     g, q = gg.rmat18_weighted()
-    print("rmat18w", g.m, flush=True)
-    _sampled_parity(B, oracle, g, q[0], 24, 18)
+    r = q[0]
+    G = dev(B, g, groups=128)
+    rv = G.rv(r)
+    assert np.array_equal(rv, oracle.rv(g, r))
+    tracked = rv[gg.seeded_subset(rv.size, 1024, 18)]
+    allsrc, k = _full_width(B, g, r, rv, tracked, 18, 128 * 64)
+    print("rmat18w full width", g.m, allsrc.size, flush=True)
+    dep, cnt = G.dependencies(r, allsrc, counters=True)
+    odep, ocnt = oracle.dependencies(g, r, tracked)
+    assert close(dep[:k], odep) and np.array_equal(cnt[:k], ocnt)
+    assert np.array_equal(dev(B, g, groups=4).dependencies(r, tracked[:256]), dep[:256])
 
 
-def test_rmat20_sampled_sources(B, oracle):
-    """R-MAT scale 20, edge factor 16: a giant-class vertex."""
+def test_rmat20_full_width(B):
+    """R-MAT scale 20, edge factor 16, a giant-class vertex, in the bench's
+    batch (64 column groups, 8 XCD partitions, bottom-up levels on): 1,024
+    seeded sources of RV(r) padded to 4,096 with further RV sources, against
+    the oracle's dependencies and pass counters stored by
+    tests/golden/make_fullwidth_deps.py."""
     g = gg.rmat20()
     r = gg.top_out_degree(g, 1)[0]
-    print("rmat20", g.m, flush=True)
-    _sampled_parity(B, oracle, g, r, 24, 20)
+    src, odep, ocnt = _golden("rmat20_fullwidth_deps.txt")
+    G = dev(B, g)
+    cfg = G.config()
+    assert cfg.groups == 64 and cfg.bottom_up == 4
+    rv = G.rv(r)
+    assert np.array_equal(src, rv[gg.seeded_subset(rv.size, 1024, 2020)])
+    allsrc, k = _full_width(B, g, r, rv, src, 2020, 64 * 64)
+    print("rmat20 full width", g.m, allsrc.size, flush=True)
+    dep, cnt = G.dependencies(r, allsrc, counters=True)
+    assert close(dep[:k], odep)
+    assert np.array_equal(cnt[:k], ocnt)
+    # top-down levels only: the same bits
+    assert np.array_equal(dev(B, g, bottom_up=0).dependencies(r, allsrc)[:k], dep[:k])
 
 
 def test_rmat20_dag_set_uneven(B, oracle):
@@ -695,13 +772,27 @@ def test_rmat20_dag_set_uneven(B, oracle):
     _sampled_parity(B, oracle, g, qs[int(np.argmax(sizes))], 16, 2020)
 
 
-def test_rmat22_sampled_sources_and_draws(B, oracle):
-    """R-MAT scale 22, edge factor 16: sampled sources, and an A-BCD call
-    whose draws the oracle recomputes."""
+def test_rmat22_full_width_and_draws(B, oracle):
+    """R-MAT scale 22, edge factor 16: 1,024 seeded sources of RV(r) (one
+    full batch of the default 16 column groups, 8 partitions, bottom-up
+    levels on) against the oracle's stored dependencies and counters, the
+    same sources in the serving width (3 groups per batch), and an A-BCD
+    call whose draws the oracle recomputes."""
     g = gg.rmat22()
     r = gg.top_out_degree(g, 1)[0]
+    src, odep, ocnt = _golden("rmat22_fullwidth_deps.txt")
     print("rmat22", g.m, flush=True)
-    G, rv = _sampled_parity(B, oracle, g, r, 8, 22)
+    G = dev(B, g)
+    cfg = G.config()
+    assert cfg.groups == 16 and cfg.bottom_up == 4
+    rv = G.rv(r)
+    assert np.array_equal(rv, oracle.rv(g, r))
+    assert np.array_equal(src, rv[gg.seeded_subset(rv.size, 1024, 2022)])
+    dep, cnt = G.dependencies(r, src, counters=True)
+    assert close(dep, odep)
+    assert np.array_equal(cnt, ocnt)
+    G3 = dev(B, g, groups=3)
+    assert np.array_equal(G3.dependencies(r, src[:384]), dep[:384])
     got, st = G.bc_sampled(r, T=12, seed=7, flags=B.BCD_NO_EXACT_FALLBACK)
     want, ost = oracle.bc_sampled(g, r, 12, 7)
     assert close(got, want) and st["distinct_sources"] == ost["distinct_sources"]

@@ -37,6 +37,8 @@ def test_server_mixed_equals_alone(B, oracle, weighted):
     alone = {r: G.bc_exact(r)[0] for r in qs}
     samp = {r: G.bc_sampled(r, T=40, seed=r, flags=B.BCD_NO_EXACT_FALLBACK)[0] for r in qs[:3]}
     sets = G.bc_set(qs[:5])[0]
+    # the unpruned baseline (draws over V minus r) through the server too
+    allv = {r: G.bc_sampled(r, T=30, seed=r + 1, flags=B.BCD_SAMPLE_ALL_VERTICES)[0] for r in qs[:2]}
     S = B.Server(G, workers=2, groups=2)
     tickets = {}
     # staggered arrivals: some queries arrive while earlier batches are running
@@ -44,6 +46,8 @@ def test_server_mixed_equals_alone(B, oracle, weighted):
         tickets[S.submit(B.BCD_QUERY_EXACT, r=r, tag=r)] = ("exact", r)
         if i < 3:
             tickets[S.submit(B.BCD_QUERY_SAMPLED, r=r, T=40, seed=r, flags=B.BCD_NO_EXACT_FALLBACK)] = ("samp", r)
+        if i < 2:
+            tickets[S.submit(B.BCD_QUERY_SAMPLED, r=r, T=30, seed=r + 1, flags=B.BCD_SAMPLE_ALL_VERTICES)] = ("allv", r)
         if i == 4:
             tickets[S.submit(B.BCD_QUERY_SET, rs=qs[:5])] = ("set", None)
         time.sleep(0.002)
@@ -58,11 +62,16 @@ def test_server_mixed_equals_alone(B, oracle, weighted):
             assert out["tag"] == r
         elif kind == "samp":
             assert out["bc"] == samp[r]
+        elif kind == "allv":
+            assert out["bc"] == allv[r] and out["stats"]["rv_size"] == g.n - 1, (r, out["bc"], allv[r])
         else:
             assert np.array_equal(out["bcs"], sets)
     for r in qs[:3]:
         want, _ = oracle.bc_exact(g, r)
         assert abs(alone[r] - want) <= 1e-10 * abs(want)
+    for r in qs[:2]:
+        want = oracle.bc_sampled_all(g, r, 30, r + 1)
+        assert abs(allv[r] - want) <= 1e-10 * abs(want)
 
 
 def test_server_budget_admission_and_errors(B):
@@ -107,3 +116,62 @@ def test_server_overflow_isolated(B):
     S.close()
     assert res[t_bad]["status"] == B.BCD_ERR_SIGMA_OVERFLOW
     assert res[t_ok]["status"] == B.BCD_OK and res[t_ok]["bc"] == want
+
+
+def test_server_shutdown_cancels_queued(B):
+    """bcd_server_shutdown: queries not yet admitted finish CANCELLED, those
+    admitted finish with their standalone value, every result can still be
+    polled, and later submissions are refused with CANCELLED."""
+    g = gg.rmat(12, 8, seed=8)
+    G = B.Graph.from_digraph(g)
+    G.set_config(groups=1)
+    qs = gg.top_out_degree(g, 40)
+    alone = {r: G.bc_exact(r)[0] for r in qs[:4]}
+    # one worker, one group: each query takes many batches, so most are still queued
+    S = B.Server(G, workers=1, groups=1)
+    ts = {S.submit(B.BCD_QUERY_EXACT, r=r): r for r in qs}
+    S.shutdown()
+    res = drain(S, len(ts))
+    assert set(res) == set(ts)
+    st = [res[t]["status"] for t in ts]
+    assert all(x in (B.BCD_OK, B.BCD_ERR_CANCELLED) for x in st)
+    assert st.count(B.BCD_ERR_CANCELLED) >= len(qs) // 2
+    for t, r in ts.items():
+        if res[t]["status"] == B.BCD_OK and r in alone:
+            assert res[t]["bc"] == alone[r]
+    with pytest.raises(B.BcdError) as e:
+        S.submit(B.BCD_QUERY_EXACT, r=qs[0])
+    assert e.value.code == B.BCD_ERR_CANCELLED
+    S.close()
+
+
+def test_server_rmat22_serving_config(B, oracle):
+    """R-MAT scale 22, edge factor 16, in the serving benchmark's shape (3
+    workers x 3 column groups, a 64 GB budget): sampled queries with Eq.(8)'s
+    sample count and with 12 draws, all submitted at once, each equal bit for
+    bit to the standalone call; the 12-draw values equal the oracle's A-BCD
+    on the same draws."""
+    g = gg.rmat22()
+    G = B.Graph.from_digraph(g)
+    ind, outd = g.in_degree(), g.out_degree()
+    pool = [v for v in gg.uniform_vertices(g.n, 400, seed=105) if ind[v] > 0 and outd[v] > 0]
+    big, small = pool[:3], pool[3:7]
+    print("rmat22 serving", big, small, flush=True)
+    alone = {("b", r): G.bc_sampled(r, eps=0.01, delta=0.1, seed=305 + i)[0] for i, r in enumerate(big)}
+    alone.update({("s", r): G.bc_sampled(r, T=12, seed=7 + i, flags=B.BCD_NO_EXACT_FALLBACK)[0]
+                  for i, r in enumerate(small)})
+    S = B.Server(G, workers=3, groups=3, hbm_budget_bytes=64 * 10 ** 9)
+    ts = {}
+    for i, r in enumerate(big):
+        ts[S.submit(B.BCD_QUERY_SAMPLED, r=r, eps=0.01, delta=0.1, seed=305 + i)] = ("b", r)
+    for i, r in enumerate(small):
+        ts[S.submit(B.BCD_QUERY_SAMPLED, r=r, T=12, seed=7 + i, flags=B.BCD_NO_EXACT_FALLBACK)] = ("s", r)
+    res = drain(S, len(ts), timeout=300)
+    S.close()
+    for t, key in ts.items():
+        assert res[t]["status"] == B.BCD_OK, (key, res[t])
+        assert res[t]["bc"] == alone[key], (key, res[t]["bc"], alone[key])
+    for i, r in enumerate(small[:2]):
+        want, _ = oracle.bc_sampled(g, r, 12, 7 + i)
+        got = alone[("s", r)]
+        assert abs(got - want) <= 1e-10 * abs(want) and (got == 0) == (want == 0), (r, got, want)
