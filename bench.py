@@ -22,7 +22,10 @@ queries, one step = the 8 queries), er2000 (ER n=2,000, m=10,000, one
 exact query; LDS engine), rmat18w (weighted R-MAT 18), rmat20set (set of
 64 vertices on R-MAT 20), rmat20dagset (set of 64 vertices with |RV(r)|
 spread from 15 to 1e5 on an acyclic R-MAT 20), rmat16bcd (the paper's BCD
-procedure and the unpruned sampling baseline on R-MAT 16, per query).
+procedure and the unpruned sampling baseline on R-MAT 16, per query),
+oracle (the CPU oracle alone on the host cores: the ER 2,000 and R-MAT 16
+queries in full, seeded samples of R-MAT 18 weighted, 20 and 22 queries
+with extrapolated full-query times, and one-thread rates).
 
 The JSON line also carries the forward kernels' HBM roofline figures, the
 plain one-source-per-launch engine on a sample of sources, and the CPU
@@ -320,7 +323,7 @@ def serve_bench(args):
     log(f"[bench] saturation: {sat}")
     roof = None
     if not args.no_profile:
-        roof = roofline_from_profile(G, G.profile(0), G.profile(1), "batched", wname_serving(args),
+        roof = roofline_from_profile(G, G.profile(0), G.profile(1), "batched", traffic_key_serving(args),
                                      batch_width=64 * groups, probe_gbs=probe, bottom_up=cfg.bottom_up > 0)
         log(f"[bench] roofline: {roof}")
     poisson = {}
@@ -390,6 +393,14 @@ def serve_bench(args):
 def wname_serving(args) -> str:
     budget = f"{args.hbm_budget_gb:g}GB" if args.hbm_budget_gb > 0 else "freeHBM"
     return f"rmat22_ef16_serving_sampled_{args.steps * args.queries_per_step}q_{budget}"
+
+
+def traffic_key_serving(args) -> str:
+    """Workload key of counter-measured traffic: the batches do not depend on
+    how many queries a run serves, only on the graph, the query kind and the
+    width (which the lookup also matches)."""
+    budget = f"{args.hbm_budget_gb:g}GB" if args.hbm_budget_gb > 0 else "freeHBM"
+    return f"rmat22_ef16_serving_sampled_{budget}"
 
 
 def plain_form(G, g, r, nsrc):
@@ -515,7 +526,7 @@ def cpu_baseline(g, r, src, budget_s: float, threads: int, what: str):
         return te, done, time.perf_counter() - t0
 
     te, done, dt = rate(threads, budget_s)
-    te1, done1, dt1 = rate(1, budget_s / 5)
+    te1, done1, dt1 = rate(1, max(5.0, budget_s / 4))
     return {"value": te / dt / 1e9, "unit": "GTEPS", "cores": threads, "kind": "oracle",
             "sample": f"{done} {what}, per-source passes, {te} traversed arcs in {dt:.1f} s on {threads} threads",
             "one_thread_gteps": te1 / dt1 / 1e9,
@@ -548,6 +559,74 @@ def config_overrides(args) -> dict:
     return kw
 
 
+def oracle_timing(args):
+    """The CPU oracle on the host cores alone (no GPU), per workload: the
+    ER 2,000 query and the 8 R-MAT 16 queries run in full on every thread;
+    for R-MAT 18 weighted, 20 and 22 a seeded sample of sources of the
+    largest-out-degree vertex's RV(r) is timed and the full query's time is
+    extrapolated from the sample's traversed-arc rate (labelled as such).
+    Every workload also gets a one-thread rate on a sample.  The RV(r)
+    search is outside the timed window (as t_BC excludes t_RV)."""
+    from oracle import oracle as O
+    from paper_1708_08739_amd import graphgen as gg
+    info = cpu_info()
+    threads = args.cpu_threads or max(1, min(info.get("affinity") or os.cpu_count() or 1, 64))
+    out = {"kind": "oracle_timing", "cpu": info, "threads": threads, "workloads": {}}
+
+    def timed(g, r, src, nthreads):
+        t0 = time.perf_counter()
+        _, cnt = O.dependencies(g, r, src, threads=nthreads)
+        dt = time.perf_counter() - t0
+        return int(cnt[:, 1].sum()), dt
+
+    def one_thread(g, r, rv, budget):
+        te = 0
+        done = 0
+        t0 = time.perf_counter()
+        order = rv[np.argsort(gg.stream(777, 0, rv.size), kind="stable")]
+        while time.perf_counter() - t0 < budget and done < order.size:
+            part = order[done:done + 4]
+            a, _ = timed(g, r, part, 1)
+            te += a
+            done += part.size
+        dt = time.perf_counter() - t0
+        return {"gteps": te / dt / 1e9, "sources": done, "traversed_edges": te, "seconds": round(dt, 2)}
+
+    full = [("er2000", *gg.er_2000()), ("rmat16", *gg.rmat16())]
+    for name, g, qs in full:
+        te = 0
+        dt = 0.0
+        for r in qs:
+            rv = O.rv(g, r)
+            if rv.size == 0:
+                continue
+            a, b = timed(g, r, rv, threads)
+            te += a
+            dt += b
+            log(f"[oracle] {name} r={r} |RV|={rv.size} {a} arcs in {b:.1f} s")
+        big = max(qs, key=lambda r: O.rv(g, r).size)
+        out["workloads"][name] = {"queries": len(qs), "full_run": True, "traversed_edges": te,
+                                  "seconds": round(dt, 3), "gteps": te / dt / 1e9 if dt else None,
+                                  "one_thread": one_thread(g, big, O.rv(g, big), args.cpu_budget / 4)}
+    samp = [("rmat18w", gg.rmat18_weighted()[0]), ("rmat20", gg.rmat20()), ("rmat22", gg.rmat22())]
+    for name, g in samp:
+        r = gg.top_out_degree(g, 1)[0]
+        rv = O.rv(g, r)
+        src = rv[gg.seeded_subset(rv.size, min(args.oracle_sample, rv.size), 4242)]
+        a, b = timed(g, r, src, threads)
+        rate = a / b
+        per_source = a / src.size
+        est_s = per_source * rv.size / rate
+        log(f"[oracle] {name} r={r} |RV|={rv.size}: {src.size} sources, {a} arcs in {b:.1f} s")
+        out["workloads"][name] = {"query": int(r), "rv_size": int(rv.size), "sample_sources": int(src.size),
+                                  "sample_traversed_edges": a, "sample_seconds": round(b, 3),
+                                  "gteps": rate / 1e9,
+                                  "extrapolated_full_query_seconds": round(est_s, 1),
+                                  "extrapolated": "full-query time = |RV| x mean arcs per sampled source / sample rate",
+                                  "one_thread": one_thread(g, r, rv, args.cpu_budget / 4)}
+    print(json.dumps(out), flush=True)
+
+
 def serving_width(workspace_bytes, start: int, budget: int) -> int:
     """Largest group count <= start whose workspaces (workspace_bytes(groups),
     all workers) fit in 85 % of the budget (the rest holds the queries'
@@ -566,7 +645,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22serve",
-                    choices=["rmat22serve", "rmat16", "er2000", "rmat18w", "rmat20set", "rmat20dagset", "rmat16bcd"])
+                    choices=["rmat22serve", "rmat16", "er2000", "rmat18w", "rmat20set", "rmat20dagset", "rmat16bcd",
+                             "oracle"])
     ap.add_argument("--groups", type=int, default=0, help="64-source column groups per batch (0 = library default)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=0)
@@ -591,6 +671,8 @@ def main():
     ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson-arrival runs")
     ap.add_argument("--no-probe", action="store_true", help="serving: skip the streaming-copy probe")
     ap.add_argument("--set-size", type=int, default=64)
+    ap.add_argument("--oracle-sample", type=int, default=512,
+                    help="oracle workload: sources timed per large query (extrapolated to the full query)")
     ap.add_argument("--probe-bw", action="store_true",
                     help="also run the library's streaming-copy probe (4 GiB copied, known traffic)")
     args = ap.parse_args()
@@ -601,6 +683,9 @@ def main():
 
     if args.workload == "rmat22serve":
         serve_bench(args)
+        return
+    if args.workload == "oracle":
+        oracle_timing(args)
         return
 
     import torch

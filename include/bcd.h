@@ -100,14 +100,20 @@ typedef struct bcd_config {
                          least 1/bottom_up of the batch's (group, vertex)
                          pairs; 0 = always top-down, -1 = default (4 on
                          graphs of 2^19 vertices or more, else 0) */
-  int32_t compress;   /* exact and set calls: 1 = a source with no in-arcs and
-                         one out-arc (s, v) gets no pass of its own (the
-                         compression the paper says composes with RV(r),
-                         Section 4.2): delta_s(t) = delta_v(t) for t != v, and
-                         delta_s(v) = the number of vertices v reaches, so
-                         values equal the uncompressed ones up to rounding;
-                         stats count only the sources that ran.  0 = off (the
-                         default) */
+  int32_t compress;   /* exact and set calls: 1 = a source s gated into a
+                         vertex a gets no pass of its own (the compression the
+                         paper says composes with RV(r), Section 4.2).  s is
+                         gated into a when s lies on no directed cycle and every
+                         out-neighbour of s is a or is itself gated into a (a
+                         source with no in-arcs and one out-arc (s, v) is the
+                         simplest case); every path from s then leaves through
+                         a, so delta_s(t) = delta_a(t) for t != a, and
+                         delta_s(a) = the number of vertices a reaches.  Used
+                         only when no target is gated into a.  Values equal
+                         the uncompressed ones up to rounding; stats count only
+                         the sources that ran; the gates are computed on the
+                         host on the first compressed call (strongly connected
+                         components, O(n + m)).  0 = off (the default) */
 } bcd_config;
 
 /* Sampled estimate (Alg.2).  T comes from Eq.(8) unless T_override > 0. */

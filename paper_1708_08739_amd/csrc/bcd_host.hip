@@ -590,10 +590,6 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   std::vector<int64_t> irp((size_t)n + 1, 0);
   for (int64_t e = 0; e < m; ++e) irp[(size_t)col[e] + 1]++;
   for (int64_t v = 0; v < n; ++v) irp[(size_t)v + 1] += irp[(size_t)v];
-  // sources that can be folded into their only successor (no in-arcs, one out-arc)
-  g->leaf_next.assign((size_t)n, -1);
-  for (int64_t v = 0; v < n; ++v)
-    if (irp[(size_t)v + 1] == irp[(size_t)v] && row_ptr[v + 1] - row_ptr[v] == 1) g->leaf_next[(size_t)v] = col[row_ptr[v]];
   std::vector<int32_t> icol((size_t)std::max<int64_t>(m, 1));
   std::vector<uint32_t> iw(weight ? (size_t)std::max<int64_t>(m, 1) : 0);
   {

@@ -156,7 +156,12 @@ struct Graph {
   int cus = 1;
   size_t lds_block_bytes = 0;  // LDS one workgroup may allocate
   std::vector<int64_t> h_rp;
-  std::vector<int32_t> leaf_next;  // head of the only out-arc of a vertex with no in-arcs, else -1
+  // compression (computed on the first compressed call): gate[v] = the vertex
+  // every path from v leaves through when v lies on no cycle and all its
+  // out-neighbours funnel into that one vertex, else -1
+  std::mutex gate_mu;
+  bool gates_ready = false;
+  std::vector<int32_t> gate;
   int64_t *d_rp = nullptr;
   int32_t *d_col = nullptr;
   uint32_t *d_w = nullptr;

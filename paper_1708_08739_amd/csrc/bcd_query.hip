@@ -755,25 +755,118 @@ bcd_status run_sources(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
   return run_batched(g, ws, src, tgt, want_counters, out);
 }
 
-// Exact and set calls with compression on: a source s with no in-arcs and
-// a single out-arc (s, v) runs no pass.  Every path from s leaves through
-// v, and s is reached from nowhere, so for a target t != v the dependency
-// delta_s(t) equals delta_v(t) bit for bit (the same path counts and arc
-// order below v); when v is not among the sources that run, v reaches no
-// target but itself and delta_s(t) = 0; and delta_s(v) is the number of
-// vertices v reaches (every one of them is reached through v).  `src` and
-// the sources that run are ascending; dep is filled for all of `src`.
+// ------------------------------------------------------- compression
+//
+// Gates (the fold that compression uses).  Call a vertex x gated into a
+// when x lies on no directed cycle (its strongly connected component is
+// {x}) and every out-neighbour y of x funnels into a: y = a, or y is itself
+// gated into a.  Then every path from x that leaves the set H of vertices
+// gated into a passes through a, and a reaches no vertex of H (a vertex of
+// H reached from a would share a cycle with a).  So for a source s gated
+// into a and any t outside H with t != a, every shortest s-u path to a
+// vertex u beyond a is a shortest s-a path followed by a shortest a-u path:
+// sigma_su = sigma_sa sigma_au and sigma_su(t) = sigma_sa sigma_au(t), and
+// vertices of H contribute nothing through t.  Hence
+//   delta_s(t) = delta_a(t)          (t not in H, t != a),
+//   delta_s(a) = |vertices a reaches|  (every path past a passes a),
+// for positive arc lengths as for unit ones.  A source with no in-arcs and
+// one out-arc (s, v) is the simplest case (a = v, or v's own gate).  The
+// gate is a vertex separator of s's paths valid for shortest paths in a
+// digraph, in the spirit of the shattering at cut vertices the paper
+// says composes with RV(r) (Section 4.2).
+//
+// Computed once per graph on the host: Tarjan's strongly connected
+// components, iteratively, over the out-CSR; a component is completed only
+// after every component it reaches, so each singleton's gate is decided
+// from final gates of its out-neighbours.
+static bcd_status ensure_gates(Graph *g) {
+  std::lock_guard<std::mutex> lk(g->gate_mu);
+  if (g->gates_ready) return BCD_OK;
+  const int64_t n = g->n, m = g->m;
+  std::vector<int32_t> col((size_t)std::max<int64_t>(m, 1));
+  if (m > 0) HIPCHK(hipMemcpy(col.data(), g->d_col, (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost));
+  const std::vector<int64_t> &rp = g->h_rp;
+  std::vector<int32_t> gate((size_t)n, -1);
+  std::vector<int64_t> index((size_t)n, -1), low((size_t)n, 0), edge((size_t)n, 0);
+  std::vector<int32_t> stack, call;
+  std::vector<uint8_t> on_stack((size_t)n, 0);
+  int64_t next_index = 0;
+  auto funnel = [&](int32_t y) { return gate[(size_t)y] >= 0 ? gate[(size_t)y] : y; };
+  for (int64_t root = 0; root < n; ++root) {
+    if (index[(size_t)root] >= 0) continue;
+    call.push_back((int32_t)root);
+    index[(size_t)root] = low[(size_t)root] = next_index++;
+    edge[(size_t)root] = rp[(size_t)root];
+    stack.push_back((int32_t)root);
+    on_stack[(size_t)root] = 1;
+    while (!call.empty()) {
+      const int32_t v = call.back();
+      if (edge[(size_t)v] < rp[(size_t)v + 1]) {
+        const int32_t w = col[(size_t)edge[(size_t)v]++];
+        if (index[(size_t)w] < 0) {
+          index[(size_t)w] = low[(size_t)w] = next_index++;
+          edge[(size_t)w] = rp[(size_t)w];
+          stack.push_back(w);
+          on_stack[(size_t)w] = 1;
+          call.push_back(w);
+        } else if (on_stack[(size_t)w]) {
+          low[(size_t)v] = std::min(low[(size_t)v], index[(size_t)w]);
+        }
+        continue;
+      }
+      call.pop_back();
+      if (!call.empty()) low[(size_t)call.back()] = std::min(low[(size_t)call.back()], low[(size_t)v]);
+      if (low[(size_t)v] != index[(size_t)v]) continue;
+      // v roots a component: pop it
+      int32_t x;
+      int64_t size = 0;
+      do {
+        x = stack.back();
+        stack.pop_back();
+        on_stack[(size_t)x] = 0;
+        ++size;
+      } while (x != v);
+      if (size != 1 || rp[(size_t)v + 1] == rp[(size_t)v]) continue;
+      // a singleton with out-arcs: gated if every out-neighbour funnels alike
+      const int32_t a = funnel(col[(size_t)rp[(size_t)v]]);
+      bool same = true;
+      for (int64_t e = rp[(size_t)v] + 1; e < rp[(size_t)v + 1] && same; ++e) same = funnel(col[(size_t)e]) == a;
+      if (same) gate[(size_t)v] = a;
+    }
+  }
+  g->gate.swap(gate);
+  g->gates_ready = true;
+  return BCD_OK;
+}
+
+// Exact and set calls with compression on: a source s gated into a runs no
+// pass when no target is gated into a (so no target lies in the set H of
+// vertices gated into a): delta_s(t) = delta_a(t) for a target t != a,
+// where a runs when it is a source, and otherwise reaches no target but
+// itself, so delta_s(t) = 0; and delta_s(a) = the number of vertices a
+// reaches.  `src` and the sources that run are ascending; dep is filled for
+// all of `src`.
 static bcd_status run_sources_folded(Graph *g, Workspace *ws, const std::vector<int32_t> &src,
                                      const std::vector<int32_t> &tgt, SourceRun &out, int64_t *ran) {
   if (g->config().compress == 0) {
     *ran = (int64_t)src.size();
     return run_sources(g, ws, src, tgt, false, out);
   }
+  STCHK(ensure_gates(g));
   const size_t ns = src.size(), nt = tgt.size();
+  // gates that some target is gated into: sources gated there run
+  std::vector<int32_t> held;
+  for (int32_t t : tgt)
+    if (g->gate[(size_t)t] >= 0) held.push_back(g->gate[(size_t)t]);
+  std::sort(held.begin(), held.end());
+  auto fold_of = [&](int32_t s) {
+    const int32_t a = g->gate[(size_t)s];
+    return (a >= 0 && !std::binary_search(held.begin(), held.end(), a)) ? a : -1;
+  };
   std::vector<int32_t> runs;
   runs.reserve(ns);
   for (int32_t s : src)
-    if (g->leaf_next[(size_t)s] < 0) runs.push_back(s);
+    if (fold_of(s) < 0) runs.push_back(s);
   SourceRun run;
   if (!runs.empty()) STCHK(run_sources(g, ws, runs, tgt, false, run));
   std::vector<int64_t> reach(nt, -1);  // vertices a target reaches, when needed
@@ -781,7 +874,7 @@ static bcd_status run_sources_folded(Graph *g, Workspace *ws, const std::vector<
   size_t j = 0;
   for (size_t i = 0; i < ns; ++i) {
     const int32_t s = src[i];
-    const int32_t v = g->leaf_next[(size_t)s];
+    const int32_t v = fold_of(s);
     if (v < 0) {
       for (size_t t = 0; t < nt; ++t) out.dep[i * nt + t] = run.dep[j * nt + t];
       ++j;

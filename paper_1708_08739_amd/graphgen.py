@@ -468,3 +468,52 @@ def seeded_subset(count: int, k: int, seed: int, skip: int = 0) -> np.ndarray:
     positions, disjoint from those of any other ``skip`` window."""
     order = np.argsort(stream(seed, 0, count), kind="stable")
     return np.sort(order[skip: skip + k]).astype(np.int64)
+
+
+def headed_random(n_core: int, heads: int, seed: int, max_weight: int = 0, p_core: float = 0.25) -> Digraph:
+    """A small random core (each ordered pair an arc with probability
+    ``p_core``) with ``heads`` acyclic pieces hanging off it.  Piece j has
+    2-4 vertices h_1.. h_k and an exit core vertex a_j: each h_i has arcs to
+    a seeded nonempty subset of {h_i+1 .. h_k, a_j} (h_k always to a_j), so
+    every path out of the piece passes a_j; nothing points into a piece
+    from outside it.  One extra vertex per piece points to two different
+    core vertices (a vertex on no cycle whose paths do not funnel).
+    Optional weights uniform in [1, max_weight]."""
+    x = unit(stream(seed, 0, n_core * n_core + 32 * heads + 64))
+    pos = 0
+
+    def nxt():
+        nonlocal pos
+        v = float(x[pos])
+        pos += 1
+        return v
+
+    src, dst = [], []
+    for u in range(n_core):
+        for v in range(n_core):
+            if u != v and nxt() < p_core:
+                src.append(u)
+                dst.append(v)
+    n = n_core
+    for _ in range(heads):
+        a = int(nxt() * n_core)
+        k = 2 + int(nxt() * 3)
+        ids = list(range(n, n + k))
+        n += k
+        for i, h in enumerate(ids):
+            later = ids[i + 1:] + [a]
+            chosen = [w for w in later if nxt() < 0.5]
+            if not chosen or h == ids[-1]:
+                chosen = sorted(set(chosen + [later[-1]]))
+            for w in chosen:
+                src.append(h)
+                dst.append(w)
+        b = int(nxt() * n_core)
+        c = (b + 1 + int(nxt() * (n_core - 1))) % n_core
+        src += [n, n]
+        dst += [b, c]
+        n += 1
+    w = None
+    if max_weight:
+        w = (below(stream(seed + 7, 0, len(src)), max_weight) + np.uint64(1)).astype(np.uint32)
+    return from_arcs(n, src, dst, w, name=f"headed{n_core}_{heads}_{seed}")

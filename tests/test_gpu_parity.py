@@ -659,6 +659,32 @@ def test_compression_folds_leaf_sources(B, oracle, weighted):
     assert got == 35.0 and st["distinct_sources"] == 0
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_compression_gates_of_acyclic_pieces(B, oracle, weighted):
+    """Sources in acyclic pieces that funnel into one vertex (gated sources
+    with several out-arcs, chains) fold into that vertex: exact and set
+    values equal the oracle's and the uncompressed run's, targets include
+    the pieces' exits and vertices inside pieces (whose pieces then run)."""
+    g = gg.headed_random(300, 60, seed=17, max_weight=20 if weighted else 0, p_core=0.012)
+    n_core = 300
+    outd = g.out_degree()
+    exits = sorted({int(g.col[e]) for v in range(n_core, g.n) for e in range(g.row_ptr[v], g.row_ptr[v + 1])
+                    if g.col[e] < n_core})
+    inside = [v for v in range(n_core, g.n) if outd[v] > 0][:3]
+    qs = exits[:6] + gg.uniform_vertices(n_core, 4, seed=5) + inside
+    G0, G1 = dev(B, g, groups=2), dev(B, g, groups=2, compress=1)
+    folded = 0
+    for r in qs:
+        a, sa = G0.bc_exact(r)
+        b, sb = G1.bc_exact(r)
+        want, _ = oracle.bc_exact(g, r)
+        print("gates r", r, sa["distinct_sources"], sb["distinct_sources"], a, b, flush=True)
+        assert close(b, want) and close(b, a), (r, a, b, want)
+        folded += sa["distinct_sources"] - sb["distinct_sources"]
+    assert folded > 20
+    assert close(G1.bc_set(qs)[0], oracle.bc_set(g, qs)[0])
+
+
 def test_bcd_procedure_and_unpruned_sampling(B, oracle):
     g = gg.rmat(12, 8, seed=7)
     G = dev(B, g)

@@ -464,6 +464,61 @@ def test_bcd_procedure_oracle(oracle):
     assert not ex and v == oracle.bc_sampled(g, r, k - 1, 1)[0]
 
 
+def bf_gates(g, reach):
+    """Gates by definition, from the transitive closure: x is gated into a
+    when x lies on no cycle (not reach[x][x]) and every out-neighbour y is a
+    or is gated into a."""
+    memo = {}
+
+    def gate(x):
+        if x in memo:
+            return memo[x]
+        out = [int(g.col[e]) for e in range(int(g.row_ptr[x]), int(g.row_ptr[x + 1]))]
+        res = None
+        if out and not reach[x][x]:
+            fun = {gate(y) if gate(y) is not None else y for y in out}
+            if len(fun) == 1:
+                res = fun.pop()
+        memo[x] = res
+        return res
+
+    return [gate(x) for x in range(g.n)]
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gate_fold_identity(weighted):
+    """The identity compression relies on, by brute-force path enumeration
+    (Eq.(2) with exact rationals): a source s gated into a has
+    delta_s(t) = delta_a(t) for every t != a not gated into a, and
+    delta_s(a) = the number of vertices a reaches.  Graphs: random cores with
+    acyclic pieces that funnel into one core vertex, and random sparse
+    graphs (whose gated vertices are mostly sources with one out-arc)."""
+    checked = 0
+    graphs = [gg.headed_random(5, 2, seed=40 + i, max_weight=3 if weighted else 0) for i in range(8)]
+    graphs += [gg.random_small(9, 0.18, seed=s, max_weight=3 if weighted else 0) for s in range(1, 7)]
+    deep = 0
+    for g in graphs:
+        reach = BF.closure(g)
+        gates = bf_gates(g, reach)
+        paths = BF.all_pairs_paths(g)
+        for s in range(g.n):
+            a = gates[s]
+            if a is None:
+                continue
+            if g.out_degree()[s] > 1:
+                deep += 1
+            H = {x for x in range(g.n) if gates[x] == a}
+            reach_a = len(BF.reached_from(g, a, reach))
+            for t in range(g.n):
+                if t == s or t in H:
+                    continue
+                got = BF.dependency(g, s, t, paths)
+                want = Fraction(reach_a) if t == a else BF.dependency(g, a, t, paths)
+                assert got == want, (g.name, s, a, t, got, want)
+                checked += 1
+    assert checked > 200 and deep > 3
+
+
 @pytest.mark.parametrize("weighted", [False, True])
 def test_leaf_source_identity(oracle, weighted):
     """The identity compression relies on, by brute-force path enumeration:
