@@ -181,6 +181,19 @@ bcd_status bcd_autotune(bcd_graph *g, bcd_vid r, int32_t max_groups, int64_t max
  * query the size (then BCD_OK with *count). */
 bcd_status bcd_rv(const bcd_graph *g, bcd_vid r, bcd_vid *out, int64_t cap, int64_t *count);
 
+/* bcd_rv without allocation, for callers that cannot allocate device or
+ * pinned host memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid it).  Same arguments, result and errors as bcd_rv.
+ * The traversal's working memory (visited bitmap, two frontier queues,
+ * counters: 8 bytes per vertex plus n/8) is one static device array of
+ * 34,079,000 bytes that each GPU holds from library load until the process
+ * ends; graphs of more than 2^22 vertices return BCD_ERR_UNSUPPORTED.  The
+ * graph's device must be current.  Calls in one process are serialized on
+ * that array by a lock (they run one at a time); each call clears what it
+ * reads, so no earlier call's contents reach its result.  Blocks until the
+ * ids are in out. */
+bcd_status bcd_rv_noalloc(const bcd_graph *g, bcd_vid r, bcd_vid *out, int64_t cap, int64_t *count);
+
 /* Exact BC(r), Alg.1 (E-BCD): 0 if r has out-degree 0 (Prop.1); otherwise
  * the sum over s in RV(r) of delta_s.(r) (Eq.(5)), each from one shortest-
  * path pass from s (BFS levels, or positive-weight relaxation when the

@@ -116,6 +116,7 @@ SIGNATURES = {
     "bcd_set_config": [_p, C.POINTER(Config)],
     "bcd_get_config": [_p, C.POINTER(Config)],
     "bcd_rv": [_p, _i32, _p, _i64, C.POINTER(_i64)],
+    "bcd_rv_noalloc": [_p, _i32, _p, _i64, C.POINTER(_i64)],
     "bcd_bc_exact": [_p, _i32, C.POINTER(_d), C.POINTER(Stats)],
     "bcd_bc_sampled": [_p, _i32, C.POINTER(SampleParams), C.POINTER(_d), C.POINTER(Stats)],
     "bcd_bc_set": [_p, _p, _i64, _p, C.POINTER(Stats)],

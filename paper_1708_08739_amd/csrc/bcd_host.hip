@@ -25,10 +25,23 @@
 
 namespace bcd {
 
-static thread_local std::string t_last_error;
+// Message of the calling thread's last failing call, in a fixed buffer so
+// that recording it never allocates.
+static thread_local char t_last_error[512];
+
+static void set_last_error(const char *msg, size_t len) {
+  if (len >= sizeof(t_last_error)) len = sizeof(t_last_error) - 1;
+  std::memcpy(t_last_error, msg, len);
+  t_last_error[len] = '\0';
+}
 
 bcd_status fail(bcd_status s, const std::string &msg) {
-  t_last_error = msg;
+  set_last_error(msg.data(), msg.size());
+  return s;
+}
+
+bcd_status fail_static(bcd_status s, const char *msg) {
+  set_last_error(msg, std::strlen(msg));
   return s;
 }
 
@@ -526,7 +539,7 @@ const char *bcd_status_string(bcd_status s) {
   return "unknown status";
 }
 
-const char *bcd_last_error(void) { return t_last_error.c_str(); }
+const char *bcd_last_error(void) { return t_last_error; }
 
 bcd_status bcd_sample_count(double eps_abs, double delta, double K, int64_t rv_size, int64_t *T) {
   BCD_GUARD_BEGIN

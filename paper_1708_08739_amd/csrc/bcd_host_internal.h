@@ -51,6 +51,7 @@ constexpr int kMaxParts = 8;          // item-list partitions (one per XCD)
 constexpr int kCntStage = (kLevelChunkMax + 2) * kMaxParts;  // pinned slots for level counts
 
 bcd_status fail(bcd_status s, const std::string &msg);
+bcd_status fail_static(bcd_status s, const char *msg);  // records the message without allocating
 bcd_status hip_fail(hipError_t e, const char *what);
 bcd_status device_check(int *cus, size_t *lds_block_bytes = nullptr);
 
