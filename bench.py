@@ -86,7 +86,8 @@ def measured_traffic(kernel: str, workload_name: str, batch_width: int):
 
 
 def roofline_from_profile(G, fwd: dict, bwd: dict, ename: str, wname: str, batch_width: int | None = None,
-                          probe_gbs: float | None = None, bottom_up: bool = False):
+                          probe_gbs: float | None = None, bottom_up: bool = False,
+                          probe_copy_gbs: float | None = None):
     """HBM roofline of the dominant pass from the library's kernel profile.
 
     Bytes: the per-source model (32 per (source, vertex) + 8 per (source,
@@ -97,7 +98,9 @@ def roofline_from_profile(G, fwd: dict, bwd: dict, ename: str, wname: str, batch
     union of the launch intervals (each instant counted once); the
     per-launch figures divide by the summed durations.  `traffic` is the
     counter-measured HBM bytes per launch recorded in profiles/ for this
-    workload and width, or None."""
+    workload and width, or None.  `probe_gbs` is the measured streaming-read
+    bandwidth (the traversal kernels' traffic is mostly reads), the
+    achievable reference for the probe-relative fractions."""
     if fwd["launches"] == 0:
         return None
     dom, kind = (fwd, "forward") if fwd["total_ms"] >= bwd["total_ms"] else (bwd, "backward")
@@ -139,10 +142,14 @@ def roofline_from_profile(G, fwd: dict, bwd: dict, ename: str, wname: str, batch
         out["traffic_achieved"] = round(traffic * dom["launches"] / (busy_ms * 1e-3) / 1e9, 2)
         out["traffic_frac"] = round(out["traffic_achieved"] / HBM_PEAK_GBS, 4)
     if probe_gbs:
-        out["probe_gbs"] = round(probe_gbs, 1)
+        out["probe_read_gbs"] = round(probe_gbs, 1)
         out["probe_frac"] = round(achieved / probe_gbs, 4)
         if sched > 0:
             out["sched_probe_frac"] = round(out["sched_achieved"] / probe_gbs, 4)
+        if traffic is not None:
+            out["traffic_probe_frac"] = round(out["traffic_achieved"] / probe_gbs, 4)
+    if probe_copy_gbs:
+        out["probe_copy_gbs"] = round(probe_copy_gbs, 1)
     return out
 
 
@@ -185,9 +192,10 @@ def run_weighted(G, g, queries, args):
     """R-MAT scale 18, edge factor 16, weights in [1,100]: the four top
     out-degree vertices through one set call (they share RV), the others
     one exact call each."""
-    from paper_1708_08739_amd import bcd
-    if args.autotune:
-        cfg, rate = G.autotune(queries[0], max_groups=8, max_sources=2048)
+    if not args.no_autotune:
+        # batch width from {32, 64, 128, 256} column groups (and launch shape),
+        # timed on 16,384 sources of the first query, before the timed region
+        cfg, rate = G.autotune(queries[0], max_groups=256, max_sources=16384)
         log(f"[bench] autotune: groups={cfg.groups} block={cfg.block} grid_mult={cfg.grid_mult} ({rate:.2f} GTEPS)")
         G.profile_reset()
     t0 = time.perf_counter()
@@ -293,10 +301,12 @@ def serve_bench(args):
         _, tk = submit_all(warm, 905)
         drain(tk)
         log(f"[bench] warm-up: {W} steps ({len(warm)} queries) done")
-    probe = None
+    probe = probe_copy = None
     if not args.no_probe:
-        probe = bcd.bcd_bandwidth_probe(4 << 30, 5)
-        log(f"[bench] copy probe: {probe:.1f} GB/s (4 GiB read + 4 GiB written per launch)")
+        probe_copy = bcd.bcd_bandwidth_probe(4 << 30, 5)
+        probe = bcd.bcd_read_bandwidth_probe(4 << 30, 5)
+        log(f"[bench] probes: copy {probe_copy:.1f} GB/s (4 GiB read + 4 GiB written per launch), "
+            f"read {probe:.1f} GB/s (4 GiB per launch)")
     if not args.no_profile:
         G.profile_reset()
         G.profile_enable(True)
@@ -324,7 +334,8 @@ def serve_bench(args):
     roof = None
     if not args.no_profile:
         roof = roofline_from_profile(G, G.profile(0), G.profile(1), "batched", traffic_key_serving(args),
-                                     batch_width=64 * groups, probe_gbs=probe, bottom_up=cfg.bottom_up > 0)
+                                     batch_width=64 * groups, probe_gbs=probe, bottom_up=cfg.bottom_up > 0,
+                                     probe_copy_gbs=probe_copy)
         log(f"[bench] roofline: {roof}")
     poisson = {}
     if not args.no_poisson:
@@ -375,7 +386,7 @@ def serve_bench(args):
                    "queries": len(qs), "queries_per_step": Q, "query": "sampled eps=0.01 (normalised) delta=0.1",
                    "hbm_budget_gb": round(budget / 1e9, 1), "workers": args.workers, "groups": groups,
                    "batch_width": 64 * groups, "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items,
-                   "bottom_up": cfg.bottom_up},
+                   "bottom_up": cfg.bottom_up, "push": cfg.push},
         "qps": sat["qps"],
         "p50_query_ms": sat["p50_ms"],
         "p99_query_ms": sat["p99_ms"],
@@ -556,6 +567,8 @@ def config_overrides(args) -> dict:
         kw["bottom_up"] = args.bottom_up
     if args.compress:
         kw["compress"] = 1
+    if args.push >= 0:
+        kw["push"] = args.push
     return kw
 
 
@@ -653,6 +666,9 @@ def main():
     ap.add_argument("--items", type=int, default=0, help="frontier items per wavefront step (0 = library default)")
     ap.add_argument("--bottom-up", type=int, default=-1,
                     help="bottom-up threshold denominator for the unweighted forward (0 = off, -1 = library default)")
+    ap.add_argument("--push", type=int, default=-1,
+                    help="unweighted forward: 1 = add path counts along DAG arcs, 0 = pull them over in-arcs, "
+                         "-1 = library default")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (0 = every thread this process may use, at most 64)")
     ap.add_argument("--compress", action="store_true",
@@ -663,7 +679,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="rmat20set: autotune the configuration first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="rmat18w: keep the library's default width instead of autotuning it")
     ap.add_argument("--queries-per-step", type=int, default=25, help="serving: sampled queries per step")
     ap.add_argument("--workers", type=int, default=3, help="serving: concurrent batches")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0,
@@ -671,6 +689,8 @@ def main():
     ap.add_argument("--no-poisson", action="store_true", help="serving: skip the Poisson-arrival runs")
     ap.add_argument("--no-probe", action="store_true", help="serving: skip the streaming-copy probe")
     ap.add_argument("--set-size", type=int, default=64)
+    ap.add_argument("--max-queries", type=int, default=0,
+                    help="rmat16, rmat18w, er2000: run only the first N query vertices (profiling runs)")
     ap.add_argument("--oracle-sample", type=int, default=512,
                     help="oracle workload: sources timed per large query (extrapolated to the full query)")
     ap.add_argument("--probe-bw", action="store_true",
@@ -692,6 +712,9 @@ def main():
     from paper_1708_08739_amd import bcd
 
     g, queries, wname = workload(args.workload)
+    if args.max_queries > 0 and queries is not None and len(queries) > args.max_queries:
+        queries = queries[: args.max_queries]
+        wname += f"_first{args.max_queries}"
     log(f"[bench] workload {wname}: n={g.n} m={g.m} queries={queries}")
     G = bcd.Graph.from_digraph(g)
     kw = config_overrides(args)
@@ -798,12 +821,14 @@ def main():
     fwd = G.profile(0)
     bwd = G.profile(1)
 
-    bw = None
+    bw = bwr = None
     if args.probe_bw:
         bw = round(bcd.bcd_bandwidth_probe(4 << 30, 5), 1)
-        log(f"[bench] copy probe: {bw} GB/s (4 GiB read + 4 GiB written per launch)")
-    roofline = None if args.no_profile else roofline_from_profile(G, fwd, bwd, ename, wname, probe_gbs=bw,
-                                                                  bottom_up=G.config().bottom_up > 0)
+        bwr = round(bcd.bcd_read_bandwidth_probe(4 << 30, 5), 1)
+        log(f"[bench] probes: copy {bw} GB/s (4 GiB read + 4 GiB written per launch), read {bwr} GB/s")
+    roofline = None if args.no_profile else roofline_from_profile(G, fwd, bwd, ename, wname, probe_gbs=bwr,
+                                                                  bottom_up=G.config().bottom_up > 0,
+                                                                  probe_copy_gbs=bw)
 
     # plain one-source-per-launch form on a sample of the same sources
     plain = None

@@ -114,6 +114,12 @@ typedef struct bcd_config {
                          the sources that ran; the gates are computed on the
                          host on the first compressed call (strongly connected
                          components, O(n + m)).  0 = off (the default) */
+  int32_t push;       /* batched engine, unweighted forward: 1 = a level found
+                         top-down adds each path count along its DAG arcs
+                         (one 64-bit atomic add per (source, DAG arc), no
+                         in-arc read), 0 = each vertex pulls its count over its
+                         in-arcs; the same values either way (exact integer
+                         sums); -1 = default */
 } bcd_config;
 
 /* Sampled estimate (Alg.2).  T comes from Eq.(8) unless T_override > 0. */
@@ -162,10 +168,11 @@ bcd_status bcd_get_config(const bcd_graph *g, bcd_config *cfg);
 /* Autotuner: times the per-source passes of a fixed seeded sample of RV(r)
  * (at most max_sources sources) under each candidate and keeps the one with
  * the highest traversed arcs per second: first the batched engine with
- * groups in {1,2,4,...,max_groups} x grid_mult in {8,16,32} (block 256, or
- * 64 on weighted graphs; 2 items per step, top-down), then around the best
- * block 512 (weighted: 128 and 256) and, on unweighted graphs, items 1 and 4
- * and bottom-up levels (16, 4), then the
+ * groups in the powers of two from the largest one <= max_groups / 8 (at
+ * least 1) to max_groups, x grid_mult in {8,16,32} (block 256, or 64 on
+ * weighted graphs; 2 items per step, top-down), then around the best block
+ * 512 (weighted: 128 and 256) and, on unweighted graphs, items 1 and 4,
+ * bottom-up levels (16, 4) and the other path-count form (push), then the
  * LDS engine when the graph fits it.  Installs the choice on the graph and
  * returns it in *best (and its rate in *gteps, may be NULL).  Results of
  * later calls do not depend on the choice (every engine and setting gives
@@ -281,10 +288,13 @@ bcd_status bcd_profile_get(const bcd_graph *g, int32_t kind, bcd_kernel_profile 
 bcd_status bcd_profile_reset(bcd_graph *g);
 
 /* Streaming-copy probe: achieved device bandwidth (GB/s, read+write) of a
- * copy of `bytes` bytes (rounded down to 16-byte words; 16-byte loads, four
- * in flight per thread, 8 workgroups of 256 per compute unit), best of `reps`
- * after one untimed launch. */
+ * copy of `bytes` bytes (rounded down to 16-byte words; non-temporal 16-byte
+ * loads and stores, four in flight per thread, 64 workgroups of 256 per
+ * compute unit), best of `reps` after one untimed launch. */
 bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps);
+/* The same for a read of `bytes` bytes (GB/s read): the reference for kernels
+ * whose traffic is mostly reads, as the traversal kernels' is. */
+bcd_status bcd_read_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps);
 
 /* -------------------------------------------------------------- serving
  * A request loop for many BC(r) queries on one resident graph (the calls of

@@ -53,7 +53,7 @@ class Stats(C.Structure):
 class Config(C.Structure):
     _fields_ = [("engine", C.c_int32), ("groups", C.c_int32), ("block", C.c_int32),
                 ("grid_mult", C.c_int32), ("items", C.c_int32), ("bottom_up", C.c_int32),
-                ("compress", C.c_int32)]
+                ("compress", C.c_int32), ("push", C.c_int32)]
 
 
 class SampleParams(C.Structure):
@@ -129,6 +129,7 @@ SIGNATURES = {
     "bcd_profile_get": [_p, _i32, C.POINTER(KernelProfile)],
     "bcd_profile_reset": [_p],
     "bcd_bandwidth_probe": [_i64, _i32, C.POINTER(_d)],
+    "bcd_read_bandwidth_probe": [_i64, _i32, C.POINTER(_d)],
     "bcd_autotune": [_p, _i32, _i32, _i64, C.POINTER(Config), C.POINTER(_d)],
     "bcd_server_create": [_p, C.POINTER(ServerConfig), C.POINTER(_p)],
     "bcd_server_submit": [_p, C.POINTER(Query), C.POINTER(_u64)],
@@ -195,6 +196,12 @@ def bcd_bandwidth_probe(nbytes: int = 1 << 30, reps: int = 5) -> float:
     return g.value
 
 
+def bcd_read_bandwidth_probe(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    g = C.c_double()
+    check(load().bcd_read_bandwidth_probe(nbytes, reps, C.byref(g)), "bcd_read_bandwidth_probe")
+    return g.value
+
+
 class Graph:
     """A digraph resident on the GPU (``bcd_graph_load_csr``)."""
 
@@ -244,10 +251,12 @@ class Graph:
         return c
 
     def set_config(self, engine=None, groups=None, block=None, grid_mult=None, items=None,
-                   bottom_up=None, compress=None) -> Config:
+                   bottom_up=None, compress=None, push=None) -> Config:
         c = self.config()
         if compress is not None:
             c.compress = int(compress)
+        if push is not None:
+            c.push = int(push)
         if items is not None:
             c.items = items
         if bottom_up is not None:

@@ -269,6 +269,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   HIPCHK(hipMemsetAsync(S.ctr, 0, (size_t)kCtrSlots * C_COUNT * sizeof(uint64_t), stream));
   HIPCHK(hipStreamSynchronize(stream));
   S.epoch = 0;
+  sig_zero = true;
   batch_ready = true;
   return BCD_OK;
 }
@@ -352,6 +353,7 @@ bcd_status Workspace::grow_items() {
 bcd_status Workspace::reset_batch_dense() {
   const size_t GN = (size_t)G * (size_t)n;
   HIPCHK(hipMemsetAsync(S.sig, 0, GN * kLanes * sizeof(uint64_t), stream));
+  sig_zero = true;
   if (S.vis) HIPCHK(hipMemsetAsync(S.vis, 0, GN * sizeof(uint64_t), stream));
   if (S.fr) HIPCHK(hipMemsetAsync(S.fr, 0, 3 * GN * sizeof(uint64_t), stream));
   if (S.rec) HIPCHK(hipMemsetAsync(S.rec, 0, GN * sizeof(MaskRec), stream));
@@ -640,6 +642,7 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   g->cfg.grid_mult = 32;
   g->cfg.items = kDefaultItems;
   g->cfg.bottom_up = default_bottom_up(n);
+  g->cfg.push = kDefaultPush;
   *out = reinterpret_cast<bcd_graph *>(g.release());
   return BCD_OK;
   BCD_GUARD_END
@@ -680,10 +683,12 @@ bcd_status bcd_set_config(bcd_graph *gh, const bcd_config *cfg) {
   if (cfg->bottom_up < -1 || cfg->bottom_up > 4096)
     return fail(BCD_ERR_INVALID_ARG, "bottom_up must be in [-1, 4096]");
   if (cfg->compress != 0 && cfg->compress != 1) return fail(BCD_ERR_INVALID_ARG, "compress must be 0 or 1");
+  if (cfg->push < -1 || cfg->push > 1) return fail(BCD_ERR_INVALID_ARG, "push must be -1, 0 or 1");
   std::lock_guard<std::mutex> lk(g->cfg_mu);
   g->cfg = *cfg;
   if (g->cfg.items == 0) g->cfg.items = kDefaultItems;
   if (g->cfg.bottom_up < 0) g->cfg.bottom_up = default_bottom_up(g->n);
+  if (g->cfg.push < 0) g->cfg.push = kDefaultPush;
   return BCD_OK;
   BCD_GUARD_END
 }
@@ -751,47 +756,65 @@ bcd_status bcd_profile_reset(bcd_graph *gh) {
   BCD_GUARD_END
 }
 
-bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
-  BCD_GUARD_BEGIN
+// Best-of-reps bandwidth of a copy (read = false: `bytes` read and `bytes`
+// written per launch) or a read (`bytes` read per launch) over 16-byte words,
+// 64 workgroups of 256 threads per compute unit, after one untimed launch.
+static bcd_status stream_probe(int64_t bytes, int32_t reps, bool read, double *gbps) {
   if (bytes < 1024 || reps < 1 || !gbps) return fail(BCD_ERR_INVALID_ARG, "bad argument");
   int cus = 0;
   STCHK(device_check(&cus));
-  const int64_t count = bytes / 16 * 2;  // doubles, a whole number of 16-byte words
-  double *a = nullptr, *b = nullptr;
-  STCHK(dalloc(&a, (size_t)count));
-  if (dalloc(&b, (size_t)count) != BCD_OK) {
+  const int64_t n16 = bytes / 16;
+  const int grid = std::max(1, cus) * 64;
+  uint8_t *a = nullptr, *b = nullptr;
+  unsigned *sink = nullptr;
+  STCHK(dalloc(&a, (size_t)n16 * 16));
+  bcd_status rc = read ? dalloc(&sink, 4) : dalloc(&b, (size_t)n16 * 16);
+  if (rc != BCD_OK) {
     dfree(a);
-    return BCD_ERR_OUT_OF_MEMORY;
+    return rc;
   }
   hipStream_t st;
   hipEvent_t e0, e1;
-  bcd_status rc = BCD_OK;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
     dfree(a);
     dfree(b);
+    dfree(sink);
     return fail(BCD_ERR_DEVICE, "stream create failed");
   }
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  (void)hipMemsetAsync(a, 0, (size_t)count * 8, st);
+  (void)hipMemsetAsync(a, 1, (size_t)n16 * 16, st);
   double best = 0;
+  const double moved = (read ? 1.0 : 2.0) * (double)n16 * 16;
   for (int i = 0; i < reps + 1 && rc == BCD_OK; ++i) {
     (void)hipEventRecord(e0, st);
-    if (launch_copy_probe(a, b, count / 2, std::max(1, cus) * 8, st) != hipSuccess)
-      rc = fail(BCD_ERR_DEVICE, "copy probe launch failed");
+    const hipError_t e = read ? launch_read_probe(a, n16, sink, grid, st) : launch_copy_probe(a, b, n16, grid, st);
+    if (e != hipSuccess) rc = fail(BCD_ERR_DEVICE, "probe launch failed");
     (void)hipEventRecord(e1, st);
-    if (hipEventSynchronize(e1) != hipSuccess) rc = fail(BCD_ERR_DEVICE, "copy probe failed");
+    if (hipEventSynchronize(e1) != hipSuccess) rc = fail(BCD_ERR_DEVICE, "probe failed");
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (i > 0 && ms > 0) best = std::max(best, 2.0 * (double)count * 8 / (ms * 1e-3) / 1e9);
+    if (i > 0 && ms > 0) best = std::max(best, moved / (ms * 1e-3) / 1e9);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(st);
   dfree(a);
   dfree(b);
+  dfree(sink);
   if (rc == BCD_OK) *gbps = best;
   return rc;
+}
+
+bcd_status bcd_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
+  BCD_GUARD_BEGIN
+  return stream_probe(bytes, reps, false, gbps);
+  BCD_GUARD_END
+}
+
+bcd_status bcd_read_bandwidth_probe(int64_t bytes, int32_t reps, double *gbps) {
+  BCD_GUARD_BEGIN
+  return stream_probe(bytes, reps, true, gbps);
   BCD_GUARD_END
 }
 

@@ -47,6 +47,9 @@ constexpr int kDefaultItems = 2;      // frontier items per wavefront step, unwe
 // only).  Bottom-up levels pay on large graphs (R-MAT 20 and 22, acyclic
 // R-MAT 20: +4 to +14 %) and cost a little on small ones (R-MAT 16: -4 %).
 inline int default_bottom_up(int64_t n) { return n >= (int64_t(1) << 19) ? 4 : 0; }
+// Top-down levels of the unweighted forward add path counts along DAG arcs
+// (1) instead of pulling them over in-arcs (0).
+constexpr int kDefaultPush = 0;
 constexpr int kMaxParts = 8;          // item-list partitions (one per XCD)
 constexpr int kCntStage = (kLevelChunkMax + 2) * kMaxParts;  // pinned slots for level counts
 
@@ -87,6 +90,10 @@ struct Workspace {
   int G = 0;
   BatchState S{};
   size_t res_cap = 0;
+  // every path count of S.sig is zero (after creation, a dense reset or a
+  // batch whose counts were pushed and then cleared); a batch that pulls its
+  // counts leaves them behind, and a pushing batch needs them zero
+  bool sig_zero = false;
   uint32_t *d_items0 = nullptr;
   unsigned long long *d_masks0 = nullptr;
   uint32_t *d_dest0 = nullptr;

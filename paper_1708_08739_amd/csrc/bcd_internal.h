@@ -84,6 +84,7 @@ struct BatchState {
   unsigned long long last_lanes; // lanes of group gused-1 that hold a source
   int bu_den;                    // bottom-up levels: see level_bottom_up (0 = never)
   int keep_all;                  // 1: the backward runs on every lane (exports), else only below a target
+  int push;                      // 1: top-down levels push path counts along DAG arcs (k_fwd_push), 0: pull
   // weighted graphs only
   uint32_t *wd;              // [G][n][64] distances, 0xFFFFFFFF unreached
   uint32_t *wc;              // [G][n][64] shortest-path-DAG in-arcs not yet pushed
@@ -188,5 +189,6 @@ hipError_t launch_route_results(const double *res, const ResultRoute *routes, in
 // launch after every completed batch; an aborted batch just zeroes them).
 hipError_t launch_ctr_fold(uint64_t *ctr, int slots, uint64_t *acc, hipStream_t st);
 hipError_t launch_copy_probe(const void *src, void *dst, int64_t n16, int grid, hipStream_t st);
+hipError_t launch_read_probe(const void *src, int64_t n16, unsigned *sink, int grid, hipStream_t st);
 
 }  // namespace bcd

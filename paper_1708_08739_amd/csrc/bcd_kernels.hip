@@ -362,6 +362,209 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
   flush_wave_counters<BLOCK, 5>(S.ctr, S.ctr_slots, ck, cv, ovf, S.flags);
 }
 
+// Push form of the path counts: sigma_b(w) += sigma_b(v) for every DAG arc
+// (v, w) of lane b, one 64-bit atomic add per (lane, DAG arc).  The chunk
+// holds the out-arcs of up to K items (slot t = arc lane / (64 / K));
+// `push` on an arc lane holds the lanes for which that arc is a DAG arc, sv[t]
+// is this lane's path count at item t and dn[t] (wave-uniform) the item's
+// lanes that are a target or lie below one, which follow the count to the
+// head.  Adds of up to eight arcs are issued before their results are
+// checked; an add whose result wraps means the exact count exceeds 2^64 - 1
+// (every addend is nonnegative, so the running sum crosses 2^64 once).
+template <int K>
+static __device__ __forceinline__ void push_slots(const BatchState &S, uint64_t gbase, uint32_t w, ull push,
+                                                  int lane, const ull (&sv)[K], const ull (&dn)[K], bool &ovf,
+                                                  uint64_t &dag_pairs) {
+  constexpr int SUB = kLanes / K;
+  ull bits = __ballot(push != 0ull);
+  while (bits != 0ull) {
+    int j[8];
+    int c = 0;
+    for (; c < 8 && bits != 0ull; ++c) {
+      j[c] = __ffsll((long long)bits) - 1;
+      bits &= bits - 1ull;
+    }
+    ull old[8], add[8];
+    uint64_t gq8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      old[q] = 0ull;
+      add[q] = 0ull;
+      gq8[q] = 0;
+      if (q < c) {
+        const uint32_t wq = read_lane(w, j[q]);
+        const ull dq = read_lane64(push, j[q]);
+        const uint64_t gq = read_lane64(gbase, j[q]);
+        const int slot = j[q] / SUB;
+        ull x = sv[0], dnq = dn[0];
+#pragma unroll
+        for (int t = 1; t < K; ++t)
+          if (slot == t) {
+            x = sv[t];
+            dnq = dn[t];
+          }
+        dag_pairs += (uint64_t)__popcll(dq);  // wave-uniform
+        gq8[q] = gq + wq;
+        if ((dq >> lane) & 1ull) {
+          add[q] = x;
+          old[q] = atomicAdd(&S.sig[(gq + wq) * kLanes + lane], x);
+        }
+        // the head's lanes below a target on this arc (one atomic per arc)
+        const ull dd = dnq & dq;
+        if (dd != 0ull && lane == 0) atomicOr(&S.rec[gq + wq].dn, dd);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < c && old[q] + add[q] < old[q]) {
+        ovf = true;
+        atomicOr(&S.ovl[(uint32_t)(gq8[q] / (uint64_t)S.n)], 1ull << lane);
+      }
+  }
+}
+
+// One BFS level of the batched forward pass with pushed path counts (the
+// alternative to k_fwd_level's pull; same results bit for bit, since the
+// counts are exact integer sums).  For every item (g, v, mask) on `level`:
+// sigma_b(v) is final (pushed by the level before, or pulled by k_bu_level
+// when this level was found bottom-up); every out-arc (v, w) whose head is
+// not settled on a level <= `level` for lane b of mask is a DAG arc of lane
+// b: w is flagged for level+1 (one atomicOr per arc, the first flagger
+// appends it) and sigma_b(v) is added into sigma_b(w).  No in-arc is read.
+// Path-count rows must start at zero on every lane (k_batch_cleanup resets
+// the lanes a batch settled).
+template <int BLOCK, int K>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_fwd_push(DevGraph G,
+                                                                                                BatchState S,
+                                                                                                int level) {
+  constexpr int SUB = kLanes / K;
+  const uint64_t n = (uint64_t)S.n;
+  const int P = S.P;
+  const PartView pv = part_view<BLOCK>(P);
+  const uint64_t base = S.off[(uint64_t)level * P + pv.p];
+  const uint64_t count = S.cnt[(uint64_t)level * P + pv.p];
+  const uint64_t nbase = base + count;
+  const uint64_t rend = (uint64_t)(pv.p + 1) * S.capP;
+  if (pv.thread == 0) S.off[(uint64_t)(level + 1) * P + pv.p] = nbase;
+  if (nbase > rend) return;  // capacity exceeded (workgroup-uniform test): the batch is redone
+  const int lane = lane_id();
+  const int sl = lane % SUB;
+  MaskRec *rec = S.rec;
+  const int kc = level & 3, kn = (level + 1) & 3, ko = (level + 2) & 3;
+  if (level >= 2) {  // retire the masks of level-2
+    const uint64_t pb = S.off[(uint64_t)(level - 2) * P + pv.p];
+    const uint64_t pc = S.cnt[(uint64_t)(level - 2) * P + pv.p];
+    for (uint64_t i = pv.thread; i < pc; i += pv.nthreads) rec[S.items[pb + i]].fr[ko] = 0ull;
+  }
+  uint64_t prev = 0;
+  if (level >= 1)
+    for (int p = 0; p < P; ++p) prev += S.cnt[(uint64_t)(level - 1) * P + p];
+  uint64_t cur = 0;
+  for (int p = 0; p < P; ++p) cur += S.cnt[(uint64_t)level * P + p];
+  const bool own = !bottom_up_rule(S.bu_den, level, prev, S.gused, S.n);  // found top-down
+  const bool disc = !bottom_up_rule(S.bu_den, level + 1, cur, S.gused, S.n);
+
+  uint64_t c_v = 0, c_a = 0, c_d = 0, c_it = 0, c_ia = 0;  // wave-uniform counters
+  bool ovf = false;
+  const uint64_t step = pv.nwaves * (uint64_t)K;
+  uint32_t *next_cnt = &S.cnt[(uint64_t)(level + 1) * P + pv.p];
+  __shared__ uint32_t stage_all[(BLOCK / 64) * kStage];
+  uint32_t *stage = stage_all + (threadIdx.x >> 6) * kStage;
+  int nst = 0;
+  uint64_t ii = pv.wave * (uint64_t)K + (uint64_t)(lane / SUB);  // this lane's item
+  uint32_t it_next = ii < count ? S.items[base + ii] : 0u;
+  for (uint64_t i0 = pv.wave * (uint64_t)K; i0 < count; i0 += step, ii += step) {
+    const bool has = ii < count;
+    const uint32_t it = it_next;
+    if (ii + step < count) it_next = S.items[base + ii + step];
+    const uint32_t g = (uint32_t)(it / n);
+    const uint32_t v = (uint32_t)(it - (uint64_t)g * n);
+    const uint64_t gbase = (uint64_t)g * n;
+    ull mask = 0ull, dnr = 0ull;
+    int64_t e0 = 0, e1 = 0;
+    int32_t tg = -1;
+    if (has) {
+      mask = rec[it].fr[kc];
+      dnr = rec[it].dn;
+      e0 = G.rp[v];
+      e1 = G.rp[v + 1];
+      if (own) tg = S.tgt_of[v];
+    }
+    const int64_t d1 = disc ? e1 : e0;  // end of the out-arcs to scan
+    if (has && sl == 0 && own) rec[it].vis = rec[it].vis | mask;
+    // per slot: the item's lanes, their marks, and this lane's path count
+    ull mt[K], dn[K], sv[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int ld = t * SUB;
+      mt[t] = read_lane64(mask, ld);
+      const bool is_tgt = (int32_t)read_lane((uint32_t)tg, ld) >= 0;
+      dn[t] = (read_lane64(dnr, ld) | (is_tgt ? mt[t] : 0ull)) & mt[t];
+      sv[t] = ((mt[t] >> lane) & 1ull) ? S.sig[(uint64_t)read_lane(it, ld) * kLanes + lane] : 0ull;
+    }
+    // first chunk of every slot's out-arcs: heads, their records, the flags
+    const int64_t mo = e0 + sl;
+    uint32_t w = 0;
+    ull push = 0ull;
+    bool enq = false;
+    if (mo < d1) {
+      w = (uint32_t)G.col[mo];
+      const MaskRec &R = rec[gbase + w];
+      const ull settled = R.vis | R.fr[kc];
+      push = mask & ~settled;  // the DAG lanes of this arc
+      const ull dag = push & ~R.fr[kn];  // lanes already flagged by another wavefront need no atomic
+      if (dag != 0ull) enq = (atomicOr(&rec[gbase + w].fr[kn], dag) == 0ull);
+    }
+    push_slots<K>(S, gbase, w, push, lane, sv, dn, ovf, c_d);
+    append_chunk(S, stage, nst, next_cnt, nbase, rend, gbase, w, enq);
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const int ld = t * SUB;
+      const ull m = mt[t];
+      if (m == 0ull) {  // slot past the end of the list (or an empty item)
+        if (lane == 0 && i0 + (uint64_t)t < count) S.imask[base + i0 + t] = 0ull;
+        continue;
+      }
+      const uint32_t itt = read_lane(it, ld);
+      const uint64_t gbt = read_lane64(gbase, ld);
+      const int64_t E0 = (int64_t)read_lane64((ull)e0, ld), E1 = (int64_t)read_lane64((ull)d1, ld);
+      const uint64_t deg = (uint64_t)((int64_t)read_lane64((ull)e1, ld) - E0);
+      c_it += 1;
+      c_ia += deg;
+      if (own) {  // a level found bottom-up was counted and marked there
+        c_v += (uint64_t)__popcll(m);
+        c_a += (uint64_t)__popcll(m) * deg;
+        const bool is_tgt = (int32_t)read_lane((uint32_t)tg, ld) >= 0;
+        if (is_tgt && lane == 0) {
+          atomicMin(S.tmin, (uint32_t)level);
+          rec[itt].dn = rec[itt].dn | m;
+        }
+      }
+      if (lane == 0) S.imask[base + i0 + t] = S.keep_all ? m : dn[t];
+      ull s1[1] = {sv[t]}, d1m[1] = {dn[t]};
+      for (int64_t e = E0 + SUB; e < E1; e += kLanes) {
+        const int64_t my = e + lane;
+        uint32_t ww = 0;
+        ull pp = 0ull;
+        bool eq = false;
+        if (my < E1) {
+          ww = (uint32_t)G.col[my];
+          const MaskRec &R = rec[gbt + ww];
+          pp = m & ~(R.vis | R.fr[kc]);
+          const ull dd = pp & ~R.fr[kn];
+          if (dd != 0ull) eq = (atomicOr(&rec[gbt + ww].fr[kn], dd) == 0ull);
+        }
+        push_slots<1>(S, gbt, ww, pp, lane, s1, d1m, ovf, c_d);
+        append_chunk(S, stage, nst, next_cnt, nbase, rend, gbt, ww, eq);
+      }
+    }
+  }
+  flush_stage(S, stage, nst, next_cnt, nbase, rend);
+  const int ck[5] = {C_FWD_VPAIRS, C_FWD_APAIRS, C_FWD_DPAIRS, C_FWD_ITEMS, C_FWD_IARCS};
+  const uint64_t cv[5] = {c_v, c_a, c_d, c_it, c_ia};
+  flush_wave_counters<BLOCK, 5>(S.ctr, S.ctr_slots, ck, cv, ovf, S.flags);
+}
+
 // 64-bit lane shuffle (ds_bpermute on both halves).
 static __device__ __forceinline__ ull shfl64(ull x, int src) {
   const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src);
@@ -697,22 +900,34 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7, 8))) v
   flush_wave_counters<BLOCK, 5>(S.ctr, S.ctr_slots, ck, cv, false, S.flags);
 }
 
-// Reset what the batch touched: the masks of every item.  (Path counts need
-// no reset: every lane's count is written by the pull before anything reads
-// it, and only lanes named by a mask are ever read.)
+// Reset what the batch touched: the masks of every item and, when the path
+// counts were pushed (added into), the counts of every lane the batch
+// settled, so the next batch's adds start from zero.  (Pulled counts need no
+// reset: every lane's count is written before anything reads it, and only
+// lanes named by a mask are ever read.)  A wavefront per item, lanes over
+// the 64 counts of its row; an item repeated on several levels clears the
+// row again or finds the record already cleared, and either way every
+// settled lane is zeroed by the first wavefront that read the record.
 __global__ void k_batch_cleanup(BatchState S, PartTotals tot) {
+  const int lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   for (int p = 0; p < S.P; ++p) {
     uint64_t total = tot.t[p];
     if (total > S.capP) total = S.capP;
     const uint32_t *items = S.items + (uint64_t)p * S.capP;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = wave; i < total; i += nwaves) {
       const uint32_t it = items[i];
       MaskRec &R = S.rec[it];
-      R.vis = 0ull;
-      R.dn = 0ull;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) R.fr[k] = 0ull;
+      if (S.push) {
+        const ull vis = R.vis;
+        if ((vis >> lane) & 1ull) S.sig[(uint64_t)it * kLanes + lane] = 0ull;
+      }
+      if (lane < 6) {
+        if (lane == 0) R.vis = 0ull;
+        else if (lane == 1) R.dn = 0ull;
+        else R.fr[lane - 2] = 0ull;
+      }
     }
   }
 }
@@ -924,20 +1139,40 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
   stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
 }
 
-// Streaming copy of n16 16-byte words: every thread keeps four 16-byte loads
-// in flight (one per grid stride) before it stores them, so the probe is
-// bound by HBM and not by the latency of one load at a time.
-__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n16) {
+// Streaming probes over n16 16-byte words: every thread keeps four 16-byte
+// loads in flight (one per grid stride) before it uses them, so the probe is
+// bound by HBM and not by the latency of one load at a time.  Copy: loads and
+// stores marked non-temporal (streamed past the caches).  Read: the words are
+// folded into one value that is stored only if it matches a sentinel, so the
+// loads cannot be dropped.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy(const v4u *__restrict__ src, v4u *__restrict__ dst, int64_t n16) {
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i + 3 * nth < n16; i += 4 * nth) {
-    const uint4 a = src[i], b = src[i + nth], c = src[i + 2 * nth], d = src[i + 3 * nth];
-    dst[i] = a;
-    dst[i + nth] = b;
-    dst[i + 2 * nth] = c;
-    dst[i + 3 * nth] = d;
+    v4u v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * nth]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * nth]);
   }
   for (; i < n16; i += nth) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_read(const v4u *__restrict__ src, int64_t n16, unsigned *sink) {
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned acc = 0;
+  for (; i + 3 * nth < n16; i += 4 * nth) {
+    v4u v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[i + u * nth];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  for (; i < n16; i += nth) acc ^= src[i].x;
+  if (acc == 0x9E3779B9u) sink[0] = acc;
 }
 
 // ------------------------------------------------------------ launchers
@@ -962,6 +1197,15 @@ hipError_t launch_batch_init(const BatchState &S, const uint32_t *items0, const 
 
 template <int K>
 static void launch_fwd_k(const DevGraph &G, const BatchState &S, int level, const Launch &L, hipStream_t st) {
+  if (S.push) {
+    switch (L.block) {
+      case 64: k_fwd_push<64, K><<<dim3(L.grid), dim3(64), 0, st>>>(G, S, level); break;
+      case 128: k_fwd_push<128, K><<<dim3(L.grid), dim3(128), 0, st>>>(G, S, level); break;
+      case 512: k_fwd_push<512, K><<<dim3(L.grid), dim3(512), 0, st>>>(G, S, level); break;
+      default: k_fwd_push<256, K><<<dim3(L.grid), dim3(256), 0, st>>>(G, S, level); break;
+    }
+    return;
+  }
   switch (L.block) {
     case 64: k_fwd_level<64, K><<<dim3(L.grid), dim3(64), 0, st>>>(G, S, level); break;
     case 128: k_fwd_level<128, K><<<dim3(L.grid), dim3(128), 0, st>>>(G, S, level); break;
@@ -1086,8 +1330,13 @@ hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *b
 }
 
 hipError_t launch_copy_probe(const void *src, void *dst, int64_t n16, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, static_cast<const uint4 *>(src), static_cast<uint4 *>(dst),
+  hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, static_cast<const v4u *>(src), static_cast<v4u *>(dst),
                      n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_probe(const void *src, int64_t n16, unsigned *sink, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_read, dim3(grid), dim3(256), 0, st, static_cast<const v4u *>(src), n16, sink);
   return hipGetLastError();
 }
 

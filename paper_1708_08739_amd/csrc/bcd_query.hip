@@ -229,6 +229,12 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
   HIPCHK(hipMemcpyAsync(ws->d_items0, ws->h_items0, (size_t)k * sizeof(uint32_t), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ws->d_masks0, ws->h_masks0, (size_t)k * sizeof(unsigned long long), hipMemcpyHostToDevice,
                         st));
+  const int push = g->config().push;
+  if (push && !ws->sig_zero) {
+    // counts pulled by an earlier batch on this workspace: clear them all once
+    HIPCHK(hipMemsetAsync(ws->S.sig, 0, (size_t)ws->G * (size_t)ws->n * kLanes * sizeof(unsigned long long), st));
+  }
+  ws->sig_zero = false;  // until this batch has completed
   for (int attempt = 0;; ++attempt) {
     ws->S.epoch += 1;
     BatchState S = ws->S;  // kernel arguments: this batch's epoch and capacity
@@ -237,6 +243,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     S.gused = (k + kLanes - 1) / kLanes;
     S.last_lanes = (k % kLanes) == 0 ? ~0ull : ((1ull << (k % kLanes)) - 1ull);
     S.bu_den = g->config().bottom_up;
+    S.push = push;
     S.keep_all = full ? 1 : 0;
     const int P = S.P;
     const Launch L = g->launch_parts(P);
@@ -369,6 +376,7 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
           if (stop >= 0 && l >= stop) prof->items[1] += cntp[(size_t)l * P + p];
         }
     }
+    ws->sig_zero = push != 0;  // the cleanup of a pushing batch zeroed the counts it set
     return BCD_OK;
   }
 }

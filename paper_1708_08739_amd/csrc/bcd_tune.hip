@@ -72,7 +72,11 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
   cand.block = g->weighted ? 64 : 256;
   cand.items = 2;
   cand.bottom_up = 0;
-  for (int G = 1; G <= max_groups && rc == BCD_OK; G *= 2) {
+  // widths in powers of two from the largest one <= max_groups / 8 (at
+  // least 1) up to max_groups: four widths at most
+  int g0 = 1;
+  while (g0 * 16 <= max_groups) g0 *= 2;
+  for (int G = g0; G <= max_groups && rc == BCD_OK; G *= 2) {
     if ((uint64_t)G * (uint64_t)g->n >= (1ull << 32)) break;
     double widest = -1.0;
     for (int gm : {8, 16, 32}) {
@@ -86,7 +90,7 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
     if (rc == BCD_OK && widest < 0 && G > 1) break;  // too wide for this device: stop widening
   }
   // 2. around the best: block size; for unweighted graphs also items per
-  //    step and bottom-up levels
+  //    step, bottom-up levels and pushed against pulled path counts
   if (rc == BCD_OK && best_rate >= 0) {
     const bcd_config base = best_cfg;
     std::vector<bcd_config> around;
@@ -106,6 +110,9 @@ extern "C" bcd_status bcd_autotune(bcd_graph *gh, bcd_vid r, int32_t max_groups,
         c.bottom_up = bu;
         around.push_back(c);
       }
+      c = base;
+      c.push = 1 - base.push;
+      around.push_back(c);
     }
     for (const bcd_config &x : around) {
       double rate = -1.0;

@@ -107,9 +107,10 @@ def test_multi_source_pass_groups(B, oracle, k):
     g = gg.rmat(11, 8, seed=5)
     src = gg.uniform_vertices(g.n, k, seed=k)
     want = [oracle.source_pass(g, s) for s in src]
-    for items, bu in ((1, 0), (2, -1), (4, 0), (1, 4096), (2, 4096), (4, 4096)):
-        G = dev(B, g, groups=3, items=items, bottom_up=bu)
-        print("multi k", k, "items", items, "bottom_up", bu, flush=True)
+    for items, bu, push in ((1, 0, 0), (2, -1, 0), (4, 0, 0), (1, 4096, 0), (2, 4096, 0), (4, 4096, 0),
+                            (1, 0, 1), (2, 0, 1), (4, 0, 1), (2, 4096, 1), (4, 2, 1)):
+        G = dev(B, g, groups=3, items=items, bottom_up=bu, push=push)
+        print("multi k", k, "items", items, "bottom_up", bu, "push", push, flush=True)
         d, sg, dl = G.multi_source_pass(src)
         for i, s in enumerate(src):
             od, osg, odl, ovf, _ = want[i]
@@ -120,6 +121,23 @@ def test_multi_source_pass_groups(B, oracle, k):
         od, osg, odl, ovf, _ = want[i]
         assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), ("lds", k, i, s)
         assert close(dl[i], odl), ("lds", k, i, s)
+
+
+def test_push_and_pull_alternate_on_one_workspace(B, oracle):
+    """Pulled path counts leave values in the count rows, pushed ones add
+    into them: switching the form between calls on one graph (one pooled
+    workspace) gives the same bits every time, and the oracle's values."""
+    g = gg.rmat(12, 8, seed=19)
+    r = gg.top_out_degree(g, 1)[0]
+    src = oracle.rv(g, r)[:300]
+    want, _ = oracle.dependencies(g, r, src)
+    G = dev(B, g, groups=2, bottom_up=0)
+    first = G.dependencies(r, src)
+    assert close(first, want)
+    for push, bu in ((1, 0), (0, 0), (1, 4096), (1, 0), (0, 4096), (1, 2)):
+        G.set_config(push=push, bottom_up=bu)
+        print("alternate push", push, "bottom_up", bu, flush=True)
+        assert np.array_equal(G.dependencies(r, src), first), (push, bu)
 
 
 def test_partition_count_changes_between_batches(B, oracle):
@@ -166,6 +184,9 @@ def test_bc_exact_er2000_both_engines(B, oracle):
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=5, bottom_up=4096, items=1),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=7, bottom_up=4096, items=4, block=512),
                 dict(engine=B.BCD_ENGINE_BATCHED, groups=2, bottom_up=2, items=2),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=5, push=1),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=3, push=1, items=4, bottom_up=4096),
+                dict(engine=B.BCD_ENGINE_BATCHED, groups=16, push=1, block=512, items=1),
                 dict(engine=B.BCD_ENGINE_LDS),
                 dict(engine=B.BCD_ENGINE_PLAIN)]:
         print("er2000", cfg, flush=True)
@@ -259,6 +280,8 @@ def test_sigma_overflow(B, oracle):
     g64, ids64 = gg.diamond_chain(64)
     for cfg in (dict(engine=B.BCD_ENGINE_BATCHED, items=1), dict(engine=B.BCD_ENGINE_BATCHED, items=2),
                 dict(engine=B.BCD_ENGINE_BATCHED, items=4), dict(engine=B.BCD_ENGINE_BATCHED, bottom_up=4096),
+                dict(engine=B.BCD_ENGINE_BATCHED, push=1, items=1), dict(engine=B.BCD_ENGINE_BATCHED, push=1),
+                dict(engine=B.BCD_ENGINE_BATCHED, push=1, items=4, bottom_up=4096),
                 dict(engine=B.BCD_ENGINE_PLAIN), dict(engine=B.BCD_ENGINE_LDS)):
         G = dev(B, g64, **cfg)
         with pytest.raises(B.BcdError) as e:
@@ -269,8 +292,8 @@ def test_sigma_overflow(B, oracle):
     g40, ids40 = gg.diamond_chain(40)
     src = [ids40["x"][i] for i in (0, 3, 9, 20, 30)] + [ids40["a"][2], ids40["b"][7]]
     want = [oracle.source_pass(g40, s) for s in src]
-    for items, bu in ((1, 0), (4, 0), (2, 4096), (4, 4096)):
-        d, sg, dl = dev(B, g40, groups=1, items=items, bottom_up=bu).multi_source_pass(src)
+    for items, bu, push in ((1, 0, 0), (4, 0, 0), (2, 4096, 0), (4, 4096, 0), (2, 0, 1), (4, 4096, 1)):
+        d, sg, dl = dev(B, g40, groups=1, items=items, bottom_up=bu, push=push).multi_source_pass(src)
         for i, s in enumerate(src):
             od, osg, odl, ovf, _ = want[i]
             assert np.array_equal(d[i], od) and np.array_equal(sg[i], osg), (items, s)
@@ -479,8 +502,9 @@ def test_weighted_many_batches_two_streams(B, oracle):
         assert p["launches"] > 0 and 0 < p["union_ms"] <= p["total_ms"] * (1 + 1e-9) + 1e-6
 
 
-@pytest.mark.parametrize("weighted,bottom_up", [(False, 0), (False, 4), (True, 0)])
-def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up):
+@pytest.mark.parametrize("weighted,bottom_up,push", [(False, 0, 0), (False, 4, 0), (True, 0, 0), (False, 0, 1),
+                                                     (False, 4, 1)])
+def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up, push):
     """Every source of RV(r) on R-MAT 14 (edge factor 16), elementwise against
     the oracle, in batches of 4 groups (dozens of batches, two at a time on
     two streams), top-down and with bottom-up levels: catches a wrong value on
@@ -488,11 +512,11 @@ def test_every_source_of_a_many_batch_query(B, oracle, weighted, bottom_up):
     g = gg.rmat(14, 16, seed=41, weighted=weighted, max_weight=100)
     r = gg.top_out_degree(g, 1)[0]
     rv = oracle.rv(g, r)
-    print("every source weighted", weighted, "bottom_up", bottom_up, "sources", rv.size, flush=True)
-    dep = dev(B, g, groups=4, bottom_up=bottom_up).dependencies(r, rv)
+    print("every source weighted", weighted, "bottom_up", bottom_up, "push", push, "sources", rv.size, flush=True)
+    dep = dev(B, g, groups=4, bottom_up=bottom_up, push=push).dependencies(r, rv)
     odep, _ = oracle.dependencies(g, r, rv)
     assert close(dep, odep)
-    again = dev(B, g, groups=4, bottom_up=bottom_up).dependencies(r, rv)
+    again = dev(B, g, groups=4, bottom_up=bottom_up, push=1 - push).dependencies(r, rv)
     assert np.array_equal(dep, again)
 
 
@@ -771,8 +795,9 @@ def test_rmat20_full_width(B):
     dep, cnt = G.dependencies(r, allsrc, counters=True)
     assert close(dep[:k], odep)
     assert np.array_equal(cnt[:k], ocnt)
-    # top-down levels only: the same bits
+    # top-down levels only, and pushed path counts: the same bits
     assert np.array_equal(dev(B, g, bottom_up=0).dependencies(r, allsrc)[:k], dep[:k])
+    assert np.array_equal(dev(B, g, push=1).dependencies(r, allsrc)[:k], dep[:k])
 
 
 def test_rmat20_dag_set_uneven(B, oracle):
@@ -818,6 +843,8 @@ def test_rmat22_full_width_and_draws(B, oracle):
     assert close(dep, odep)
     assert np.array_equal(cnt, ocnt)
     G3 = dev(B, g, groups=3)
+    assert np.array_equal(G3.dependencies(r, src[:384]), dep[:384])
+    G3.set_config(push=1)
     assert np.array_equal(G3.dependencies(r, src[:384]), dep[:384])
     got, st = G.bc_sampled(r, T=12, seed=7, flags=B.BCD_NO_EXACT_FALLBACK)
     want, ost = oracle.bc_sampled(g, r, 12, 7)
