@@ -444,8 +444,9 @@ def bcd_procedure(G, g, args):
     from Eq.(8) with n - 1 in place of |RV(r)|)."""
     from paper_1708_08739_amd import bcd, graphgen as gg
     ind, outd = g.in_degree(), g.out_degree()
-    pool = [v for v in gg.uniform_vertices(g.n, 40 * args.queries, seed=106) if ind[v] > 0 and outd[v] > 0]
-    qs = pool[: args.queries]
+    nq = args.max_queries or 64
+    pool = [v for v in gg.uniform_vertices(g.n, 40 * nq, seed=106) if ind[v] > 0 and outd[v] > 0]
+    qs = pool[:nq]
     rows = []
     te_bcd = 0
     t_bcd = 0.0
@@ -782,14 +783,21 @@ def main():
                                                  args.cpu_threads, f"seeded sources of RV({rq})")
             log(f"[bench] cpu baseline: {extra['cpu_baseline']}")
         cfg = G.config()
+        # one timed step is the whole workload (rmat20dagset: --steps calls)
+        nsteps = args.steps if args.workload == "rmat20dagset" else 1
+        conf = {"workload": wname, "graph": g.name, "n": g.n, "m": g.m, "engine": ename,
+                "batch_width": 64 * cfg.groups, "groups": cfg.groups, "block": cfg.block,
+                "grid_mult": cfg.grid_mult, "items": cfg.items, "bottom_up": cfg.bottom_up, "compress": cfg.compress}
+        if args.workload == "rmat18w":
+            conf["autotuned"] = not args.no_autotune
+        extra.pop("steps", None)
         print(json.dumps({"metric": "GTEPS for RV(r)-pruned BC(r) on one MI355X; p50/p99 query latency",
                           "value": round(te / wall / 1e9, 3), "unit": "GTEPS", "n_gpus": 1,
-                          "workload": wname, "wall_s": round(wall, 3), "traversed_edges": int(te),
-                          "latencies_s": [round(x, 4) for x in lat][:16],
-                          "config": {"workload": wname, "n": g.n, "m": g.m, "groups": cfg.groups,
-                                     "block": cfg.block, "grid_mult": cfg.grid_mult, "items": cfg.items,
-                                     "bottom_up": cfg.bottom_up, "compress": cfg.compress},
-                          **extra}), flush=True)
+                          "steps": nsteps, "warmup": 0, "ms_per_step": round(wall * 1e3 / nsteps, 3),
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64+f64",
+                          "data": "synthetic", "workload": wname, "wall_s": round(wall, 3),
+                          "traversed_edges": int(te), "latencies_s": [round(x, 4) for x in lat][:16],
+                          "config": conf, **extra}), flush=True)
         return
 
     def step(lat=None):
