@@ -427,6 +427,7 @@ Graph::~Graph() {
   dfree(d_irp);
   dfree(d_icol);
   dfree(d_iw);
+  dfree(d_ipos);
 }
 
 DevGraph Graph::dev() const {
@@ -439,6 +440,7 @@ DevGraph Graph::dev() const {
   G.irp = d_irp;
   G.icol = d_icol;
   G.iw = d_iw;
+  G.ipos = d_ipos;
   return G;
 }
 
@@ -607,13 +609,17 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   for (int64_t v = 0; v < n; ++v) irp[(size_t)v + 1] += irp[(size_t)v];
   std::vector<int32_t> icol((size_t)std::max<int64_t>(m, 1));
   std::vector<uint32_t> iw(weight ? (size_t)std::max<int64_t>(m, 1) : 0);
+  std::vector<uint32_t> ipos(weight ? (size_t)std::max<int64_t>(m, 1) : 0);
   {
     std::vector<int64_t> fill(irp.begin(), irp.end() - 1);
     for (int64_t u = 0; u < n; ++u)
       for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
         const int64_t p = fill[(size_t)col[e]]++;
         icol[(size_t)p] = (int32_t)u;
-        if (weight) iw[(size_t)p] = weight[e];
+        if (weight) {
+          iw[(size_t)p] = weight[e];
+          ipos[(size_t)e] = (uint32_t)p;
+        }
       }
   }
   STCHK(dalloc(&g->d_rp, (size_t)n + 1));
@@ -629,9 +635,11 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
   if (weight) {
     STCHK(dalloc(&g->d_w, (size_t)m));
     STCHK(dalloc(&g->d_iw, (size_t)m));
+    STCHK(dalloc(&g->d_ipos, (size_t)m));
     if (m > 0) {
       HIPCHK(hipMemcpy(g->d_w, weight, (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(g->d_iw, iw.data(), (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(g->d_ipos, ipos.data(), (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice));
     }
   }
   g->cfg.engine = BCD_ENGINE_BATCHED;

@@ -176,6 +176,7 @@ struct Graph {
   int64_t *d_irp = nullptr;
   int32_t *d_icol = nullptr;
   uint32_t *d_iw = nullptr;
+  uint32_t *d_ipos = nullptr;  // weighted: transpose position of every CSR arc
   mutable std::mutex cfg_mu;
   bcd_config cfg{};
   std::mutex pool_mu;

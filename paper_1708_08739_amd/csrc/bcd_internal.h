@@ -94,6 +94,7 @@ struct BatchState {
   uint32_t *rl;              // [G*n] items reached by any lane
   uint32_t *rln;             // [1]
   unsigned long long *wdn;   // [G][n] lanes on whose DAG the vertex is a target or lies below one
+  unsigned long long *dagm;  // [G][m] lanes on whose shortest-path DAG the arc lies, by transpose position
 };
 
 // Plain engine state (one source).
@@ -120,6 +121,7 @@ struct DevGraph {
   const int64_t *irp;   // transpose
   const int32_t *icol;
   const uint32_t *iw;
+  const uint32_t *ipos; // [m] weighted graphs: position of arc e of the CSR in the transpose
 };
 
 // Whether BFS level `level` (>= 2) of a batch is found bottom-up, from the

@@ -525,12 +525,12 @@ namespace bcd {
 // Device bytes of one worker's batch workspace of `groups` column groups:
 // 64-bit path-count and psi rows, backward level masks, initial item lists
 // of 16 entries per (g, v), the per-vertex target map, and the engine's own
-// arrays (weighted: distances, DAG in-arc counters, round masks; unweighted:
-// level records).
+// arrays (weighted: distances, DAG in-arc counters, round masks, per-arc DAG
+// lane masks; unweighted: level records).
 uint64_t batch_workspace_bytes(const Graph *g, int groups) {
   const uint64_t GN = (uint64_t)groups * (uint64_t)g->n;
   uint64_t b = GN * kLanes * 16 + GN * 2 * sizeof(LevMask) + GN * 16 * 12 + (uint64_t)g->n * 24;
-  if (g->weighted) b += GN * kLanes * 8 + GN * 28 + GN * 5 * 8;
+  if (g->weighted) b += GN * kLanes * 8 + GN * 28 + GN * 5 * 8 + (uint64_t)groups * (uint64_t)g->m * 8;
   else b += GN * sizeof(MaskRec);
   return b;
 }

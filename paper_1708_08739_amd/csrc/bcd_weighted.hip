@@ -5,7 +5,9 @@
 //      dist_b(w) with atomicMin and flags (g, w) for the next round;
 //   2. shortest-path-DAG in-degrees: for every reached (g, w), count the
 //      in-arcs (u, w) with dist_b(u) + len(u, w) = dist_b(w) (a pull over the
-//      reverse graph, no atomics);
+//      reverse graph, no atomics), and store each in-arc's lanes of that test
+//      as one 64-bit mask per (group, arc), so that steps 3 and 4 find the
+//      DAG lanes of an arc in one word instead of a distance per lane;
 //   3. path counts in topological rounds: a lane of a vertex is ready when
 //      all its DAG in-arcs have pushed; it then pushes sigma along its DAG
 //      out-arcs and counts them down (Kahn's order on each source's SPD);
@@ -74,6 +76,13 @@ static __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// 64-bit lane shuffle (any source lane, every lane taking part).
+static __device__ __forceinline__ ull shfl64_w(ull x, int src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src);
+  return ((ull)hi << 32) | lo;
+}
+
 static __device__ __forceinline__ Compact compact_lanes(ull em, bool mine) {
   Compact c;
   const int lane = lane_id();
@@ -206,6 +215,7 @@ __global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
     const bool fin = dw != kInf;
     uint32_t c = 0;
     const int64_t e0 = G.irp[w], e1 = G.irp[w + 1];
+    ull *dm = S.dagm + (uint64_t)g * (uint64_t)G.m;
     for (int64_t e = e0; e < e1; e += 8) {
       const int cc = (int)((e1 - e) < 8 ? (e1 - e) : 8);
       uint32_t du[8], ln[8];
@@ -218,9 +228,17 @@ __global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
           du[q] = S.wd[(gbase + (uint32_t)G.icol[e + q]) * kLanes + lane];
         }
       }
+      // lane q keeps the DAG lanes of in-arc e + q; the eight masks go out as
+      // one 64-byte store
+      ull mine = 0ull;
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (du[q] != kInf && du[q] + ln[q] == dw) ++c;
+      for (int q = 0; q < 8; ++q) {
+        const bool dag = du[q] != kInf && du[q] + ln[q] == dw;
+        if (dag) ++c;
+        const ull bq = __ballot(dag);
+        if (lane == q) mine = bq;
+      }
+      if (lane < cc) dm[e + lane] = mine;
     }
     S.wc[(uint64_t)it * kLanes + lane] = c;
     const ull fm = __ballot(fin);
@@ -236,8 +254,11 @@ __global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
 // One topological round: items whose lanes became ready push sigma along
 // their DAG out-arcs; a lane of w whose last DAG in-arc pushed is ready next
 // round.  Level lists, rotation of the mask arrays and target bookkeeping
-// mirror the unweighted forward kernel.  Lanes are compacted per item
-// (compact_lanes).
+// mirror the unweighted forward kernel.  A wavefront lane takes one out-arc
+// of the item and reads the arc's DAG mask word, so the DAG test costs one
+// load per arc for all 64 sources; pushes happen only on the (source, arc)
+// pairs of the DAG, and a head's ready and below-target lanes take one atomic
+// each.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int level) {
   const uint64_t n = (uint64_t)S.n;
@@ -266,14 +287,6 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
   constexpr int kCap = 256;
   __shared__ uint32_t st_all[(BLOCK / 64) * kCap];
   uint32_t *stg = st_all + (threadIdx.x >> 6) * kCap;
-  // per slot: the lanes made ready at the slot's head in this step, and the
-  // lanes that reach it from a vertex that is a target or lies below one
-  __shared__ ull cm_all[BLOCK], cd_all[BLOCK];
-  ull *cm = cm_all + (threadIdx.x & ~63u);
-  ull *cd = cd_all + (threadIdx.x & ~63u);
-  cm[lane] = 0ull;
-  cd[lane] = 0ull;
-  wave_lds_sync();
   int nst = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
     const uint32_t it = S.items[base + i];
@@ -282,7 +295,6 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
     const uint64_t gbase = (uint64_t)g * n;
     const ull mask = cur[it];
     if (lane == 0) S.imask[base + i] = mask;
-    const bool act = (mask >> lane) & 1ull;
     const bool is_tgt = S.tgt_of[v] >= 0;
     if (is_tgt && lane == 0) atomicMin(S.tmin, (uint32_t)level);
     if (mask == 0ull) continue;
@@ -295,70 +307,47 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
       dnv |= mask;
       if (lane == 0) atomicOr(&S.wdn[it], mask);
     }
-    const Compact cp = compact_lanes(mask, act);
-    const bool on = cp.slot < cp.slots;
-    const uint64_t vrow = (uint64_t)it * kLanes + (uint32_t)cp.src;
-    const ull sv = on ? S.sig[vrow] : 0ull;
-    const uint32_t dv = on ? S.wd[vrow] : kInf;
-    const ull bit = 1ull << cp.src;
-    const bool below = on && ((dnv >> cp.src) & 1ull);
+    // lane b holds sigma_b(v) of the ready lanes
+    const ull svl = ((mask >> lane) & 1ull) ? S.sig[(uint64_t)it * kLanes + lane] : 0ull;
+    const ull *dm = S.dagm + (uint64_t)g * (uint64_t)G.m;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    const int64_t stepw = (int64_t)cp.slots * kWU;
-    for (int64_t e = e0; e < e1; e += stepw) {
-      uint32_t wq[kWU], nd[kWU], dw[kWU];
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) {
-        const int64_t ea = e + (int64_t)u * cp.slots + cp.slot;
-        wq[u] = 0u;
-        nd[u] = kInf;
-        if (on && ea < e1) {
-          wq[u] = (uint32_t)G.col[ea];
-          nd[u] = dv + G.w[ea];
+    // lane j takes arc e + j; its DAG lanes among the ready ones come from
+    // the arc's mask word, and only those (source, arc) pairs push
+    for (int64_t e = e0; e < e1; e += kLanes) {
+      const int64_t ea = e + lane;
+      uint32_t x = 0u;
+      ull d = 0ull;
+      if (ea < e1) {
+        x = (uint32_t)G.col[ea];
+        d = dm[G.ipos[ea]] & mask;
+      }
+      const uint64_t xrow = (gbase + x) * kLanes;
+      ull rdy = 0ull, mdn = 0ull;
+      // one source of each arc per pass, lowest first; the passes are few
+      // (DAG lanes are a small share of an item's lanes)
+      while (__ballot(d != 0ull) != 0ull) {
+        const bool has = d != 0ull;
+        const int b = has ? __builtin_ctzll(d) : 0;
+        const ull sb = shfl64_w(svl, b);
+        if (has) {
+          d &= d - 1ull;
+          const ull bit = 1ull << b;
+          const ull so = atomicAdd(&S.sig[xrow + (uint32_t)b], sb);
+          const uint32_t co = atomicSub(&S.wc[xrow + (uint32_t)b], 1u);
+          if (so + sb < so) {
+            ovf = true;
+            atomicOr(&S.ovl[g], bit);
+          }
+          // the push that completes the head's DAG in-arcs makes the lane ready
+          if (co == 1u) rdy |= bit;
+          if ((dnv >> b) & 1ull) mdn |= bit;
         }
       }
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) dw[u] = nd[u] != kInf ? S.wd[(gbase + wq[u]) * kLanes + (uint32_t)cp.src] : kInf - 1u;
-      // DAG arcs of the batch: push sigma and count down, all atomics issued
-      // before any result is used
-      ull so[kWU];
-      uint32_t co[kWU];
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) {
-        so[u] = 0ull;
-        co[u] = 0u;
-        if (nd[u] != kInf && dw[u] == nd[u]) {
-          const uint64_t row = (gbase + wq[u]) * kLanes + (uint32_t)cp.src;
-          so[u] = atomicAdd(&S.sig[row], sv);
-          co[u] = atomicSub(&S.wc[row], 1u);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) {
-        const bool dag = nd[u] != kInf && dw[u] == nd[u];
-        if (dag && so[u] + sv < so[u]) {
-          ovf = true;
-          atomicOr(&S.ovl[g], bit);
-        }
-        // a lane whose push completed the head's in-arcs is ready next round;
-        // the slot's ready lanes take one atomic, and the first mark of the
-        // head appends it to the next round
-        if (__ballot(dag && (co[u] == 1u || below)) == 0ull) continue;  // no flag to set in this step
-        if (dag && co[u] == 1u) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        if (dag && below) __hip_atomic_fetch_or(&cd[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        wave_lds_sync();
-        ull m = 0ull, md = 0ull;
-        if (cp.j == 0 && on) {
-          m = cm[cp.slot];
-          md = cd[cp.slot];
-          cm[cp.slot] = 0ull;
-          cd[cp.slot] = 0ull;
-        }
-        wave_lds_sync();
-        if (md != 0ull) atomicOr(&S.wdn[gbase + wq[u]], md);
-        bool first = false;
-        if (m != 0ull) first = atomicOr(&nxt[gbase + wq[u]], m) == 0ull;
-        stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + wq[u]), next_cnt, S.items, nbase, rend, &S.flags[1]);
-      }
+      if (mdn != 0ull) atomicOr(&S.wdn[gbase + x], mdn);
+      bool first = false;
+      if (rdy != 0ull) first = atomicOr(&nxt[gbase + x], rdy) == 0ull;
+      // the first mark of the head appends it to the next round
+      stage_lanes<kCap>(stg, nst, first, (uint32_t)(gbase + x), next_cnt, S.items, nbase, rend, &S.flags[1]);
     }
   }
   stage_flush(stg, nst, next_cnt, S.items, nbase, rend, &S.flags[1]);
@@ -367,10 +356,9 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
 
 // Backward over topological round `level`: psi(v) = 1/sigma(v) + sum of
 // psi(w) over DAG out-arcs (v, w) of the lane; lanes pruned as in the
-// unweighted kernel.  Lanes are compacted (compact_lanes) and each step
-// covers kWU arcs per slot; every source's sum still runs in arc order
-// (slot-ordered reads through lane shuffles), so the result does not depend
-// on how many lanes an item has.
+// unweighted kernel.  A wavefront lane takes one out-arc and its DAG mask
+// word, psi is read only on the DAG (source, arc) pairs, and every source's
+// sum runs in arc order, so the result does not depend on the item's lanes.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int level, int ntgt, int full) {
   const uint64_t n = (uint64_t)S.n;
@@ -396,53 +384,64 @@ __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int l
     const bool need = ((mask >> lane) & 1ull) && (full || ((dnv >> lane) & 1ull) || tg >= 0);
     const ull em = __ballot(need);
     if (em == 0ull) continue;
-    const Compact cp = compact_lanes(em, need);
-    const bool on = cp.slot < cp.slots;
-    const uint64_t vrow = (uint64_t)it * kLanes + (uint32_t)cp.src;
-    const uint32_t dv = on ? S.wd[vrow] : kInf;
+    const ull *dm = S.dagm + (uint64_t)g * (uint64_t)G.m;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
-    const int64_t stepw = (int64_t)cp.slots * kWU;
-    double acc = 0.0;
-    for (int64_t e = e0; e < e1; e += stepw) {
-      uint32_t wq[kWU], nd[kWU], dw[kWU];
+    double acc = 0.0;  // lane b: the sum of source b, over its DAG arcs in arc order
+    uint64_t pairs = 0;
+    for (int64_t e = e0; e < e1; e += kLanes) {
+      // lane j takes arc e + j and its DAG lanes among the needed ones
+      const int64_t ea = e + lane;
+      uint32_t x = 0u;
+      ull d = 0ull;
+      if (ea < e1) {
+        x = (uint32_t)G.col[ea];
+        d = dm[G.ipos[ea]] & em;
+      }
+      const uint64_t xrow = (gbase + x) * kLanes;
+      // eight sources at a time: the lanes of each source's DAG arcs load its
+      // psi (all eight loads in flight together), then the source's sum takes
+      // them in arc order, so every sum runs in the same order whatever the
+      // lanes and batch
+      ull rem = em;
+      while (rem != 0ull) {
+        int bq[8];
+        ull aq[8];
+        double y[8];
 #pragma unroll
-      for (int u = 0; u < kWU; ++u) {
-        const int64_t ea = e + (int64_t)u * cp.slots + cp.slot;
-        wq[u] = 0u;
-        nd[u] = kInf;
-        if (on && ea < e1) {
-          wq[u] = (uint32_t)G.col[ea];
-          nd[u] = dv + G.w[ea];
+        for (int q = 0; q < 8; ++q) {
+          const bool live = rem != 0ull;
+          bq[q] = live ? __builtin_ctzll(rem) : 0;
+          aq[q] = __ballot(live && ((d >> bq[q]) & 1ull));
+          if (live) rem &= rem - 1ull;
+          y[q] = ((aq[q] >> lane) & 1ull) ? S.psi[xrow + (uint32_t)bq[q]] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          ull t = aq[q];
+          if (t == 0ull) continue;
+          pairs += (uint64_t)__popcll(t);
+          double a = __longlong_as_double((long long)read_lane64((ull)__double_as_longlong(acc), bq[q]));
+          while (t != 0ull) {
+            const int j = __builtin_ctzll(t);
+            t &= t - 1ull;
+            a += __longlong_as_double((long long)read_lane64((ull)__double_as_longlong(y[q]), j));
+          }
+          if (lane == bq[q]) acc = a;
         }
       }
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) dw[u] = nd[u] != kInf ? S.wd[(gbase + wq[u]) * kLanes + (uint32_t)cp.src] : kInf - 1u;
-      double x[kWU];
-#pragma unroll
-      for (int u = 0; u < kWU; ++u) {
-        x[u] = 0.0;
-        if (nd[u] != kInf && dw[u] == nd[u]) {
-          x[u] = S.psi[(gbase + wq[u]) * kLanes + (uint32_t)cp.src];
-          ++c_d;
-        }
-      }
-      // arc e + u * slots + t is in slot t of step u: add in that order; 0.0
-      // for arcs off the lane's DAG (or past the row) leaves acc unchanged
-#pragma unroll
-      for (int u = 0; u < kWU; ++u)
-        for (int t = 0; t < cp.slots; ++t) acc += __shfl(x[u], t * cp.A + cp.j);
     }
-    if (lane < cp.A) {
-      const uint64_t row = (uint64_t)it * kLanes + (uint32_t)cp.src;
+    if ((em >> lane) & 1ull) {
+      const uint64_t row = (uint64_t)it * kLanes + (uint32_t)lane;
       const double s = (double)S.sig[row];
       const double dl = s * acc;
       S.psi[row] = acc + 1.0 / s;
       if (S.dout) S.dout[row] = dl;
-      if (tg >= 0 && tg < ntgt) S.res[((uint64_t)tg * S.G + g) * kLanes + (uint32_t)cp.src] = (level > 0) ? dl : 0.0;
+      if (tg >= 0 && tg < ntgt) S.res[((uint64_t)tg * S.G + g) * kLanes + (uint32_t)lane] = (level > 0) ? dl : 0.0;
     }
     if (lane == 0) {
-      c_v += (uint64_t)cp.A;
-      c_a += (uint64_t)cp.A * (uint64_t)(e1 - e0);
+      c_v += (uint64_t)__popcll(em);
+      c_a += (uint64_t)__popcll(em) * (uint64_t)(e1 - e0);
+      c_d += pairs;
     }
   }
   flush_counters<BLOCK>(S.ctr, S.ctr_slots, C_BWD_VPAIRS, c_v, c_a, c_d, false, S.flags);
@@ -572,6 +571,7 @@ bcd_status Workspace::ensure_weighted() {
   STCHK(walloc(&S.rl, GN));
   STCHK(walloc(&S.rln, 1));
   STCHK(walloc(&S.wdn, GN));
+  STCHK(walloc(&S.dagm, (size_t)G * (size_t)graph->m));
   HIPCHK(hipMemsetAsync(S.wd, 0xFF, GN * kLanes * sizeof(uint32_t), stream));
   HIPCHK(hipMemsetAsync(S.wdn, 0, GN * sizeof(unsigned long long), stream));
   HIPCHK(hipMemsetAsync(S.wc, 0, GN * kLanes * sizeof(uint32_t), stream));
@@ -597,6 +597,7 @@ void Workspace::release_weighted() {
   f(S.rl);
   f(S.rln);
   f(S.wdn);
+  f(S.dagm);
   weighted_ready = false;
 }
 
