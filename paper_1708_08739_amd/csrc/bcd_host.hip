@@ -423,11 +423,11 @@ Graph::~Graph() {
   if (prof_ref) (void)hipEventDestroy(prof_ref);
   dfree(d_rp);
   dfree(d_col);
-  dfree(d_w);
   dfree(d_irp);
   dfree(d_icol);
-  dfree(d_iw);
-  dfree(d_ipos);
+  dfree(d_arcw);
+  dfree(d_arcp);
+  dfree(d_iarc);
 }
 
 DevGraph Graph::dev() const {
@@ -436,11 +436,11 @@ DevGraph Graph::dev() const {
   G.m = m;
   G.rp = d_rp;
   G.col = d_col;
-  G.w = d_w;
   G.irp = d_irp;
   G.icol = d_icol;
-  G.iw = d_iw;
-  G.ipos = d_ipos;
+  G.arcw = d_arcw;
+  G.arcp = d_arcp;
+  G.iarc = d_iarc;
   return G;
 }
 
@@ -633,13 +633,20 @@ bcd_status bcd_graph_load_csr(int64_t n, int64_t m, const int64_t *row_ptr, cons
     HIPCHK(hipMemcpy(g->d_icol, icol.data(), (size_t)m * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   if (weight) {
-    STCHK(dalloc(&g->d_w, (size_t)m));
-    STCHK(dalloc(&g->d_iw, (size_t)m));
-    STCHK(dalloc(&g->d_ipos, (size_t)m));
+    STCHK(dalloc(&g->d_arcw, (size_t)m));
+    STCHK(dalloc(&g->d_arcp, (size_t)m));
+    STCHK(dalloc(&g->d_iarc, (size_t)m));
     if (m > 0) {
-      HIPCHK(hipMemcpy(g->d_w, weight, (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(g->d_iw, iw.data(), (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(g->d_ipos, ipos.data(), (size_t)m * sizeof(uint32_t), hipMemcpyHostToDevice));
+      std::vector<uint2> arcw((size_t)m), arcp((size_t)m);
+      std::vector<uint2> iarc((size_t)m);
+      for (int64_t e = 0; e < m; ++e) {
+        arcw[(size_t)e] = make_uint2((uint32_t)col[e], weight[e]);
+        arcp[(size_t)e] = make_uint2((uint32_t)col[e], ipos[(size_t)e]);
+        iarc[(size_t)e] = make_uint2((uint32_t)icol[(size_t)e], iw[(size_t)e]);
+      }
+      HIPCHK(hipMemcpy(g->d_arcw, arcw.data(), (size_t)m * sizeof(uint2), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(g->d_arcp, arcp.data(), (size_t)m * sizeof(uint2), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(g->d_iarc, iarc.data(), (size_t)m * sizeof(uint2), hipMemcpyHostToDevice));
     }
   }
   g->cfg.engine = BCD_ENGINE_BATCHED;

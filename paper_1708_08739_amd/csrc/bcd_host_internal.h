@@ -172,11 +172,11 @@ struct Graph {
   std::vector<int32_t> gate;
   int64_t *d_rp = nullptr;
   int32_t *d_col = nullptr;
-  uint32_t *d_w = nullptr;
   int64_t *d_irp = nullptr;
   int32_t *d_icol = nullptr;
-  uint32_t *d_iw = nullptr;
-  uint32_t *d_ipos = nullptr;  // weighted: transpose position of every CSR arc
+  uint2 *d_arcw = nullptr;     // weighted: {head, length} per CSR arc
+  uint2 *d_arcp = nullptr;     // weighted: {head, transpose position} per CSR arc
+  uint2 *d_iarc = nullptr;     // weighted: {tail, length} per transpose arc
   mutable std::mutex cfg_mu;
   bcd_config cfg{};
   std::mutex pool_mu;

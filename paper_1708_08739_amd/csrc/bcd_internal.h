@@ -117,11 +117,14 @@ struct DevGraph {
   int64_t n, m;
   const int64_t *rp;    // [n+1]
   const int32_t *col;   // [m]
-  const uint32_t *w;    // [m] or null
   const int64_t *irp;   // transpose
   const int32_t *icol;
-  const uint32_t *iw;
-  const uint32_t *ipos; // [m] weighted graphs: position of arc e of the CSR in the transpose
+  // weighted graphs: arc fields in pairs, so that one 8-byte load brings what
+  // a kernel reads of an arc (separate 4-byte arrays and one 16-byte record
+  // of all fields both measured slower)
+  const uint2 *arcw;    // [m] CSR order: {head, length} (relaxation)
+  const uint2 *arcp;    // [m] CSR order: {head, position of the arc in the transpose} (sigma, backward)
+  const uint2 *iarc;    // [m] transpose order: {tail, length} (DAG in-degrees)
 };
 
 // Whether BFS level `level` (>= 2) of a batch is found bottom-up, from the

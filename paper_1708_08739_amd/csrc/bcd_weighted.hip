@@ -121,11 +121,14 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
   __shared__ uint32_t rst_all[(BLOCK / 64) * kCap];
   uint32_t *qst = qst_all + (threadIdx.x >> 6) * kCap;
   uint32_t *rst = rst_all + (threadIdx.x >> 6) * kCap;
-  // per slot: the lanes that improved the slot's head in this step, combined
-  // so that the head's flags take one atomic per step, not one per source
-  __shared__ ull cm_all[BLOCK];
+  // per slot: the lanes that improved the slot's head in this step, and those
+  // that reached it first, combined so that the head's flags take one atomic
+  // per step, not one per source
+  __shared__ ull cm_all[BLOCK], cr_all[BLOCK];
   ull *cm = cm_all + (threadIdx.x & ~63u);
+  ull *cr = cr_all + (threadIdx.x & ~63u);
   cm[lane] = 0ull;
+  cr[lane] = 0ull;
   wave_lds_sync();
   int nq = 0, nr = 0;
   for (uint64_t i = wave; i < count; i += nwaves) {
@@ -152,8 +155,9 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
         wq[u] = 0u;
         nd[u] = kInf;
         if (live && ea < e1) {
-          wq[u] = (uint32_t)G.col[ea];
-          nd[u] = dv + G.w[ea];
+          const uint2 a = G.arcw[ea];
+          wq[u] = a.x;
+          nd[u] = dv + a.y;
         }
       }
 #pragma unroll
@@ -172,19 +176,24 @@ __global__ __launch_bounds__(BLOCK) void k_w_relax(DevGraph G, BatchState S, int
 #pragma unroll
       for (int u = 0; u < kWU; ++u) {
         if (__ballot(imp[u]) == 0ull) continue;  // nothing improved in this step (wave-uniform)
+        // a lane that read the head unreached: the wavefront whose lowering
+        // of a lane lands first read it unreached, so the pair's first reach
+        // is among these and the reached list needs no atomic for the others
+        const bool fst = imp[u] && dw[u] == kInf;
         if (imp[u]) __hip_atomic_fetch_or(&cm[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (fst) __hip_atomic_fetch_or(&cr[cp.slot], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         wave_lds_sync();
-        ull m = 0ull;
+        ull m = 0ull, mr = 0ull;
         if (cp.j == 0 && on) {
           m = cm[cp.slot];
+          mr = cr[cp.slot];
           cm[cp.slot] = 0ull;
+          cr[cp.slot] = 0ull;
         }
         wave_lds_sync();
         bool fq = false, fr = false;
-        if (m != 0ull) {
-          fq = atomicOr(&cnxt[gbase + wq[u]], m) == 0ull;
-          fr = atomicOr(&S.vis[gbase + wq[u]], m) == 0ull;
-        }
+        if (m != 0ull) fq = atomicOr(&cnxt[gbase + wq[u]], m) == 0ull;
+        if (mr != 0ull) fr = atomicOr(&S.vis[gbase + wq[u]], mr) == 0ull;
         stage_lanes<kCap>(qst, nq, fq, (uint32_t)(gbase + wq[u]), qout_n, qout, 0, GN, nullptr);
         stage_lanes<kCap>(rst, nr, fr, (uint32_t)(gbase + wq[u]), S.rln, S.rl, 0, GN, nullptr);
       }
@@ -224,8 +233,9 @@ __global__ __launch_bounds__(BLOCK) void k_w_count(DevGraph G, BatchState S) {
         du[q] = kInf;
         ln[q] = 0u;
         if (q < cc && fin) {
-          ln[q] = G.iw[e + q];
-          du[q] = S.wd[(gbase + (uint32_t)G.icol[e + q]) * kLanes + lane];
+          const uint2 a = G.iarc[e + q];
+          ln[q] = a.y;
+          du[q] = S.wd[(gbase + a.x) * kLanes + lane];
         }
       }
       // lane q keeps the DAG lanes of in-arc e + q; the eight masks go out as
@@ -307,9 +317,11 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
       dnv |= mask;
       if (lane == 0) atomicOr(&S.wdn[it], mask);
     }
-    // lane b holds sigma_b(v) of the ready lanes
-    const ull svl = ((mask >> lane) & 1ull) ? S.sig[(uint64_t)it * kLanes + lane] : 0ull;
     const ull *dm = S.dagm + (uint64_t)g * (uint64_t)G.m;
+    const uint64_t vrow = (uint64_t)it * kLanes;
+    // lane b holds sigma_b(v) of the ready lanes (a per-pair read of the row
+    // instead measured 5 % slower on a full-width R-MAT 18 batch)
+    const ull svl = ((mask >> lane) & 1ull) ? S.sig[vrow + lane] : 0ull;
     const int64_t e0 = G.rp[v], e1 = G.rp[v + 1];
     // lane j takes arc e + j; its DAG lanes among the ready ones come from
     // the arc's mask word, and only those (source, arc) pairs push
@@ -318,18 +330,18 @@ __global__ __launch_bounds__(BLOCK) void k_w_sigma(DevGraph G, BatchState S, int
       uint32_t x = 0u;
       ull d = 0ull;
       if (ea < e1) {
-        x = (uint32_t)G.col[ea];
-        d = dm[G.ipos[ea]] & mask;
+        const uint2 a = G.arcp[ea];
+        x = a.x;
+        d = dm[a.y] & mask;
       }
       const uint64_t xrow = (gbase + x) * kLanes;
       ull rdy = 0ull, mdn = 0ull;
       // one source of each arc per pass, lowest first; the passes are few
       // (DAG lanes are a small share of an item's lanes)
       while (__ballot(d != 0ull) != 0ull) {
-        const bool has = d != 0ull;
-        const int b = has ? __builtin_ctzll(d) : 0;
-        const ull sb = shfl64_w(svl, b);
-        if (has) {
+        const int b = d != 0ull ? __builtin_ctzll(d) : 0;
+        const ull sb = shfl64_w(svl, b);  // every lane takes part in the shuffle
+        if (d != 0ull) {
           d &= d - 1ull;
           const ull bit = 1ull << b;
           const ull so = atomicAdd(&S.sig[xrow + (uint32_t)b], sb);
@@ -394,8 +406,9 @@ __global__ __launch_bounds__(BLOCK) void k_w_bwd(DevGraph G, BatchState S, int l
       uint32_t x = 0u;
       ull d = 0ull;
       if (ea < e1) {
-        x = (uint32_t)G.col[ea];
-        d = dm[G.ipos[ea]] & em;
+        const uint2 a = G.arcp[ea];
+        x = a.x;
+        d = dm[a.y] & em;
       }
       const uint64_t xrow = (gbase + x) * kLanes;
       // eight sources at a time: the lanes of each source's DAG arcs load its
