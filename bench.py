@@ -48,18 +48,25 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, each scaled by what it reads for a copy kernel of known size),
-# valid only while the unweighted kernels' sources hash to the recorded value.
+# valid only while the sources of the kernels hash to the recorded value.
 TRAFFIC_FILES = {"k_fwd_level": ["profiles/k_fwd_level_rmat16_ef8.md"],
                  "k_bwd_level": ["profiles/k_fwd_level_rmat16_ef8.md"],
-                 "k_fwd_level+k_bu_level": ["profiles/k_fwd_level_rmat22_serving.md"]}
-KERNEL_SOURCES = ["paper_1708_08739_amd/csrc/bcd_kernels.hip", "paper_1708_08739_amd/csrc/bcd_device.h",
-                  "paper_1708_08739_amd/csrc/bcd_internal.h"]
+                 "k_fwd_level+k_bu_level": ["profiles/k_fwd_level_rmat22_serving.md",
+                                            "profiles/k_fwd_level_rmat20_set.md"],
+                 "k_w_relax+k_w_count+k_w_sigma": ["profiles/k_w_kernels_rmat18w.md"]}
+_CSRC = "paper_1708_08739_amd/csrc/"
+_UNWEIGHTED_SOURCES = [_CSRC + "bcd_kernels.hip", _CSRC + "bcd_device.h", _CSRC + "bcd_internal.h"]
+_WEIGHTED_SOURCES = [_CSRC + "bcd_weighted.hip", _CSRC + "bcd_device.h", _CSRC + "bcd_internal.h"]
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources(kernel: str) -> list[str]:
+    return _WEIGHTED_SOURCES if kernel.startswith("k_w_") else _UNWEIGHTED_SOURCES
+
+
+def kernel_sources_sha256(kernel: str = "k_fwd_level") -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in kernel_sources(kernel):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -80,7 +87,7 @@ def measured_traffic(kernel: str, workload_name: str, batch_width: int):
                     if (parts.get("kernel") == kernel and parts.get("workload") == workload_name
                             and parts.get("batch_width") == str(batch_width)):
                         rec = parts
-    if not rec or rec.get("sources_sha256") != kernel_sources_sha256():
+    if not rec or rec.get("sources_sha256") != kernel_sources_sha256(kernel):
         return None
     return float(rec["bytes_per_launch"])
 
@@ -507,6 +514,15 @@ def cpu_info() -> dict:
     except (OSError, ValueError, subprocess.SubprocessError):
         pass
     try:
+        # the clock the kernel reports for the first CPU (when lscpu gives no maximum)
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("cpu MHz"):
+                    info["mhz"] = float(ln.split(":", 1)[1])
+                    break
+    except (OSError, ValueError):
+        pass
+    try:
         info["affinity"] = len(os.sched_getaffinity(0))
     except OSError:
         pass
@@ -765,10 +781,17 @@ def main():
             te, wall, summary, rows = bcd_procedure(G, g, args)
             lat = [x["t_ms"] / 1e3 for x in rows]
             extra = {"bcd_procedure": summary, "per_query": rows}
+        bw = bwr = None
         if not args.no_profile:
             G.profile_enable(False)
+        if args.probe_bw:
+            bw = round(bcd.bcd_bandwidth_probe(4 << 30, 5), 1)
+            bwr = round(bcd.bcd_read_bandwidth_probe(4 << 30, 5), 1)
+            log(f"[bench] probes: copy {bw} GB/s (4 GiB read + 4 GiB written per launch), read {bwr} GB/s")
+        if not args.no_profile:
             extra["roofline"] = roofline_from_profile(G, G.profile(0), G.profile(1), ename, wname,
-                                                      bottom_up=G.config().bottom_up > 0)
+                                                      bottom_up=G.config().bottom_up > 0, probe_gbs=bwr,
+                                                      probe_copy_gbs=bw)
             log(f"[bench] roofline: {extra['roofline']}")
         if not args.no_cpu:
             # the oracle on a bounded sample of one query's sources: for the set,
