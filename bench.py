@@ -50,7 +50,6 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE, each scaled by what it reads for a copy kernel of known size),
 # valid only while the sources of the kernels hash to the recorded value.
 TRAFFIC_FILES = {"k_fwd_level": ["profiles/k_fwd_level_rmat16_ef8.md"],
-                 "k_bwd_level": ["profiles/k_fwd_level_rmat16_ef8.md"],
                  "k_fwd_level+k_bu_level": ["profiles/k_fwd_level_rmat22_serving.md",
                                             "profiles/k_fwd_level_rmat20_set.md"],
                  "k_w_relax+k_w_count+k_w_sigma": ["profiles/k_w_kernels_rmat18w.md"]}
