@@ -653,6 +653,37 @@ def oracle_timing(args):
                                   "extrapolated_full_query_seconds": round(est_s, 1),
                                   "extrapolated": "full-query time = |RV| x mean arcs per sampled source / sample rate",
                                   "one_thread": one_thread(g, r, rv, args.cpu_budget / 4)}
+    if args.oracle_full:
+        # full runs where a query finishes within minutes: the top R-MAT 18
+        # weighted query (every source of RV(r)) and the first serving queries
+        # of R-MAT 22 with the server's draws (the same seeds, T from Eq.(8))
+        g = gg.rmat18_weighted()[0]
+        r = gg.top_out_degree(g, 1)[0]
+        rv = O.rv(g, r)
+        # in 16 slices of RV(r), so that progress shows while it runs
+        a = 0
+        b = 0.0
+        for k, part in enumerate(np.array_split(rv, 16)):
+            x, y = timed(g, r, part, threads)
+            a += x
+            b += y
+            log(f"[oracle] rmat18w full query r={r}: slice {k + 1}/16 done, {a} arcs in {b:.1f} s")
+        out["workloads"]["rmat18w"]["full_query"] = {"traversed_edges": a, "seconds": round(b, 3),
+                                                     "gteps": a / b / 1e9}
+        g = gg.rmat22()
+        qs = serving_queries(g, args.oracle_full_queries, seed=105)
+        rows = []
+        for i, r in enumerate(qs):
+            rvr = O.rv(g, r)
+            T = O.sample_count(0.01 * g.n * (g.n - 1), 0.1, O.fr_count(g, r), rvr.size)
+            t0 = time.perf_counter()
+            bc, st = O.bc_sampled(g, r, T, 305 + i, threads=threads)
+            dt = time.perf_counter() - t0
+            te = int(st["te"])
+            rows.append({"r": int(r), "rv_size": int(rvr.size), "T": int(T), "traversed_edges": te,
+                         "seconds": round(dt, 3), "gteps": te / dt / 1e9})
+            log(f"[oracle] rmat22 serving query {i} r={r} T={T}: {te} arcs in {dt:.1f} s")
+        out["workloads"]["rmat22"]["serving_queries_full"] = rows
     print(json.dumps(out), flush=True)
 
 
@@ -709,6 +740,11 @@ def main():
                     help="rmat16, rmat18w, er2000: run only the first N query vertices (profiling runs)")
     ap.add_argument("--oracle-sample", type=int, default=512,
                     help="oracle workload: sources timed per large query (extrapolated to the full query)")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="oracle workload: also run the top R-MAT 18 weighted query and the first serving "
+                         "queries of R-MAT 22 in full")
+    ap.add_argument("--oracle-full-queries", type=int, default=4,
+                    help="oracle workload with --oracle-full: R-MAT 22 serving queries run in full")
     ap.add_argument("--probe-bw", action="store_true",
                     help="also run the library's streaming-copy probe (4 GiB copied, known traffic)")
     args = ap.parse_args()

@@ -181,6 +181,28 @@ def test_bench_roofline_uses_busy_time():
     assert bench.roofline_from_profile(Stub(False), dict(fwd, launches=0), bwd, "batched", "x") is None
 
 
+def test_bench_traffic_records_follow_their_kernel_sources(tmp_path, monkeypatch):
+    """A counter-measured traffic record counts only while the sources of its
+    kernel family hash to the recorded value, and only at its own workload
+    and width; the weighted and unweighted families hash different files."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert bench.kernel_sources_sha256("k_w_relax+k_w_count+k_w_sigma") != bench.kernel_sources_sha256("k_fwd_level")
+    sha = bench.kernel_sources_sha256("k_fwd_level")
+    prof = tmp_path / "p.md"
+    prof.write_text("text\n"
+                    f"traffic: kernel=k_fwd_level workload=w1 batch_width=64 bytes_per_launch=1234 sources_sha256={sha}\n"
+                    "traffic: kernel=k_fwd_level workload=w2 batch_width=64 bytes_per_launch=99 sources_sha256=00\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {"k_fwd_level": ["p.md"]})
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda kernel="k_fwd_level": sha)
+    assert bench.measured_traffic("k_fwd_level", "w1", 64) == 1234.0
+    assert bench.measured_traffic("k_fwd_level", "w1", 128) is None  # another width
+    assert bench.measured_traffic("k_fwd_level", "w2", 64) is None   # stale sources
+    assert bench.measured_traffic("k_bu_level", "w1", 64) is None    # no file for the kernel
+
+
 def test_ctypes_structs_match_the_header(tmp_path):
     """Every struct the binding mirrors has the header's size and, field by
     field, the header's offsets (a C program built from include/bcd.h with
