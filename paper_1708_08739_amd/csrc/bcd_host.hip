@@ -193,7 +193,7 @@ bcd_status Workspace::ensure_reach() {
   STCHK(dalloc(&bitmap, words));
   STCHK(dalloc(&rq[0], (size_t)n));
   STCHK(dalloc(&rq[1], (size_t)n));
-  STCHK(dalloc(&rqn, 2));
+  STCHK(dalloc(&rqn, 8));  // two queues: length, pad, arcs (uint64)
   STCHK(halloc(&h_bitmap, words));
   if (!h_misc) STCHK(halloc(&h_misc, 64));  // shared with the plain engine
   reach_ready = true;

@@ -111,7 +111,7 @@ struct Workspace {
   bool reach_ready = false;
   uint32_t *bitmap = nullptr;
   int32_t *rq[2] = {nullptr, nullptr};
-  uint32_t *rqn = nullptr;
+  uint32_t *rqn = nullptr;  // [8]: per queue c, length at 4c, arcs of its vertices (uint64) at 4c + 2
   uint32_t *h_bitmap = nullptr;
   // host staging
   uint32_t *h_cnt = nullptr;

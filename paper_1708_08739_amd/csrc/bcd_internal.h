@@ -167,9 +167,16 @@ hipError_t launch_plain_export(const PlainState &P, uint64_t total, uint64_t *di
 
 // Reachability BFS over one CSR (reverse graph for RV, forward for FR).
 hipError_t launch_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t root, hipStream_t st);
+// Reachability levels: queue lengths *_n and the arcs their vertices have
+// in the traversed CSR *_a; a level goes bottom-up (launch_reach_bu, over the
+// other CSR) when its frontier has at least bu_arcs arcs, else top-down.
 hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap, const int32_t *qin,
-                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, uint8_t *lev, int level,
-                              Launch L, hipStream_t st);
+                              const uint32_t *qin_n, const uint64_t *qin_a, int32_t *qout, uint32_t *qout_n,
+                              uint64_t *qout_a, uint8_t *lev, int level, uint64_t bu_arcs, Launch L,
+                              hipStream_t st);
+hipError_t launch_reach_bu(const int64_t *rp, const int32_t *col, const int64_t *rp_td, uint32_t *bitmap,
+                           const uint64_t *qin_a, int32_t *qout, uint32_t *qout_n, uint64_t *qout_a, int64_t n,
+                           uint64_t bu_arcs, Launch L, hipStream_t st);
 hipError_t launch_scatter_targets(int32_t *tgt_of, const int32_t *verts, int k, int set, hipStream_t st);
 hipError_t launch_plain_gather(const PlainState &P, const int32_t *verts, int k, int32_t *d_out,
                                double *delta_out, hipStream_t st);

@@ -1099,15 +1099,27 @@ __global__ void k_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t
   }
 }
 
+// Adds a wavefront's per-lane counts into *dst with one atomic.
+static __device__ __forceinline__ void wave_add_u64(uint64_t *dst, uint64_t x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  if (lane_id() == 0 && x != 0) atomicAdd((unsigned long long *)dst, (unsigned long long)x);
+}
+
 // One BFS level on a CSR, weights ignored: a wavefront per frontier vertex,
-// lanes over arcs, first setter of a bit appends the vertex.
+// lanes over arcs, first setter of a bit appends the vertex.  Every append
+// adds the vertex's arc count (its row in this CSR) to *qout_a, the arcs the
+// next level scans top-down; a level whose frontier has at least bu_arcs of
+// them is left to k_reach_bu.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap,
                                                        const int32_t *qin, const uint32_t *qin_n,
-                                                       int32_t *qout, uint32_t *qout_n, uint8_t *lev,
-                                                       int level) {
+                                                       const uint64_t *qin_a, int32_t *qout, uint32_t *qout_n,
+                                                       uint64_t *qout_a, uint8_t *lev, int level,
+                                                       uint64_t bu_arcs) {
   const int lane = lane_id();
   const uint32_t count = *qin_n;
+  if (*qin_a >= bu_arcs) return;  // found bottom-up (the same test in both kernels)
+  uint64_t arcs = 0;
   const uint64_t wave = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * BLOCK) >> 6;
   __shared__ uint32_t st_all[(BLOCK / 64) * kStage];
@@ -1125,6 +1137,7 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
         const uint32_t bit = 1u << (u & 31);
         if (!(bitmap[u >> 5] & bit)) enq = !(atomicOr(&bitmap[u >> 5], bit) & bit);
         if (enq && lev) lev[u] = (uint8_t)(level + 1 < 254 ? level + 1 : 254);
+        if (enq) arcs += (uint64_t)(rp[u + 1] - rp[u]);
       }
       const ull eb = __ballot(enq);
       if (eb != 0ull) {
@@ -1137,6 +1150,60 @@ __global__ __launch_bounds__(BLOCK) void k_reach_level(const int64_t *rp, const 
     }
   }
   stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
+  wave_add_u64(qout_a, arcs);
+}
+
+// The same level bottom-up, for a traversal that only needs the set of
+// vertices reached (no levels): every vertex not yet reached scans its arcs
+// in the opposite direction (rp / col of the other CSR) and joins as soon as
+// one of them leads to a reached vertex.  A vertex reached earlier in the
+// same launch may be the one found, which can put a vertex in this level
+// that the top-down order would put in a later one; the set is the same.
+// Runs only when the frontier has at least bu_arcs arcs to scan top-down.
+// One thread per vertex; the vertices that join are appended, with their
+// arc counts in the top-down CSR (rp_td), as the top-down kernel appends
+// them, so the next level can go either way.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_reach_bu(const int64_t *rp, const int32_t *col, const int64_t *rp_td,
+                                                    uint32_t *bitmap, const uint64_t *qin_a, int32_t *qout,
+                                                    uint32_t *qout_n, uint64_t *qout_a, int64_t n,
+                                                    uint64_t bu_arcs) {
+  if (*qin_a < bu_arcs) return;
+  uint64_t arcs = 0;
+  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const uint64_t nth = (uint64_t)gridDim.x * BLOCK;
+  __shared__ uint32_t st_all[(BLOCK / 64) * kStage];
+  uint32_t *stg = st_all + (threadIdx.x >> 6) * kStage;
+  int nst = 0;
+  // the loop bound is the same for every lane of a wavefront (whole
+  // wavefronts stride together), so the ballots below see every lane
+  const uint64_t span = (((uint64_t)n + 63) / 64) * 64;
+  for (uint64_t u = tid; u < span; u += nth) {
+    bool join = false;
+    if (u < (uint64_t)n && !((bitmap[u >> 5] >> (u & 31)) & 1u)) {
+      const int64_t e1 = rp[u + 1];
+      for (int64_t e = rp[u]; e < e1; ++e) {
+        const uint32_t w = (uint32_t)col[e];
+        if ((bitmap[w >> 5] >> (w & 31)) & 1u) {
+          join = true;
+          break;
+        }
+      }
+      if (join) {
+        atomicOr(&bitmap[u >> 5], 1u << (u & 31));
+        arcs += (uint64_t)(rp_td[u + 1] - rp_td[u]);
+      }
+    }
+    const ull eb = __ballot(join);
+    if (eb != 0ull) {
+      const int c = __popcll(eb);
+      if (nst + c > kStage) stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
+      if (join) stg[nst + lanes_below(eb)] = (uint32_t)u;
+      nst += c;
+    }
+  }
+  stage_flush(stg, nst, qout_n, (uint32_t *)qout, 0, ~0ull, nullptr);
+  wave_add_u64(qout_a, arcs);
 }
 
 // Streaming probes over n16 16-byte words: every thread keeps four 16-byte
@@ -1323,9 +1390,17 @@ hipError_t launch_reach_init(uint32_t *bitmap, int32_t *q, uint32_t *qn, int32_t
 }
 
 hipError_t launch_reach_level(const int64_t *rp, const int32_t *col, uint32_t *bitmap, const int32_t *qin,
-                              const uint32_t *qin_n, int32_t *qout, uint32_t *qout_n, uint8_t *lev, int level,
-                              Launch L, hipStream_t st) {
-  DISPATCH_BLOCK(L, k_reach_level, rp, col, bitmap, qin, qin_n, qout, qout_n, lev, level);
+                              const uint32_t *qin_n, const uint64_t *qin_a, int32_t *qout, uint32_t *qout_n,
+                              uint64_t *qout_a, uint8_t *lev, int level, uint64_t bu_arcs, Launch L,
+                              hipStream_t st) {
+  DISPATCH_BLOCK(L, k_reach_level, rp, col, bitmap, qin, qin_n, qin_a, qout, qout_n, qout_a, lev, level, bu_arcs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reach_bu(const int64_t *rp, const int32_t *col, const int64_t *rp_td, uint32_t *bitmap,
+                           const uint64_t *qin_a, int32_t *qout, uint32_t *qout_n, uint64_t *qout_a, int64_t n,
+                           uint64_t bu_arcs, Launch L, hipStream_t st) {
+  DISPATCH_BLOCK(L, k_reach_bu, rp, col, rp_td, bitmap, qin_a, qout, qout_n, qout_a, n, bu_arcs);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ namespace bcd {
 
 // Largest graph the scratch holds: 2^22 vertices (R-MAT scale 22).
 constexpr int64_t kNoAllocMaxN = int64_t(1) << 22;
-constexpr size_t kCtrBytes = 256;                                // counters: queue sizes [2], list size
+constexpr size_t kCtrBytes = 256;  // counters: queue sizes [2], list size, queue arc counts (uint64) at words 4-7
 constexpr size_t kBitmapBytes = (size_t)(kNoAllocMaxN / 32) * 4;  // visited bits
 constexpr size_t kQueueBytes = (size_t)kNoAllocMaxN * 4;          // one frontier queue (int32 ids)
 constexpr size_t kScratchBytes = kCtrBytes + kBitmapBytes + 2 * kQueueBytes;  // 34,079,000 bytes
@@ -157,13 +157,21 @@ extern "C" bcd_status bcd_rv_noalloc(const bcd_graph *gh, bcd_vid r, bcd_vid *ou
     const Launch L = g->launch();
     int32_t *q[2] = {q0, q1};
     int cur = 0;
+    // large levels bottom-up over the out-arcs, as the allocating call does;
+    // the arcs of queue c's vertices (uint64) at ctr[4 + 2c]
+    const uint64_t bu_arcs = (uint64_t)std::max<int64_t>(64, g->m / 64);
+    uint64_t *arcs = reinterpret_cast<uint64_t *>(ctr + 4);
     for (int64_t level = 0; level <= n;) {
       // levels 8 at a time between host checks of the frontier size
       for (int i = 0; i < 8; ++i, ++level) {
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, &ctr[1 - cur], (int64_t)1, 0u);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ctr + 4 + 2 * (1 - cur), (int64_t)2, 0u);
         NA_HIPCHK(hipGetLastError(), "fill launch failed");
-        NA_HIPCHK(launch_reach_level(rp, col, bitmap, q[cur], &ctr[cur], q[1 - cur], &ctr[1 - cur], nullptr,
-                                     (int)level, L, st),
+        NA_HIPCHK(launch_reach_level(rp, col, bitmap, q[cur], &ctr[cur], &arcs[cur], q[1 - cur], &ctr[1 - cur],
+                                     &arcs[1 - cur], nullptr, (int)level, bu_arcs, L, st),
+                  "reachability launch failed");
+        NA_HIPCHK(launch_reach_bu(g->d_rp, g->d_col, rp, bitmap, &arcs[cur], q[1 - cur], &ctr[1 - cur], &arcs[1 - cur],
+                                  n, bu_arcs, L, st),
                   "reachability launch failed");
         cur = 1 - cur;
       }

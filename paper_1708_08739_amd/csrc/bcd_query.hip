@@ -62,6 +62,9 @@ bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::v
   hipStream_t st = ws->stream;
   const int64_t *rp = reverse ? g->d_irp : g->d_rp;
   const int32_t *col = reverse ? g->d_icol : g->d_col;
+  // the other direction, for levels found bottom-up
+  const int64_t *rpo = reverse ? g->d_rp : g->d_irp;
+  const int32_t *colo = reverse ? g->d_col : g->d_icol;
   Launch L = g->launch();
   if (!d_lev && lds_reach_fits(g)) {
     // small graph: the whole traversal in one workgroup, one launch
@@ -75,19 +78,32 @@ bcd_status reach_set(Graph *g, Workspace *ws, int32_t root, bool reverse, std::v
     return BCD_OK;
   }
   HIPCHK(hipMemsetAsync(ws->bitmap, 0, words * sizeof(uint32_t), st));
-  HIPCHK(hipMemsetAsync(ws->rqn, 0, 2 * sizeof(uint32_t), st));
-  HIPCHK(launch_reach_init(ws->bitmap, ws->rq[0], &ws->rqn[0], root, st));
+  // per queue c: its length at rqn[4c], the arcs of its vertices (uint64) at rqn[4c + 2]
+  HIPCHK(hipMemsetAsync(ws->rqn, 0, 8 * sizeof(uint32_t), st));
+  auto qlen = [&](int c) { return ws->rqn + 4 * c; };
+  auto qarcs = [&](int c) { return reinterpret_cast<uint64_t *>(ws->rqn + 4 * c + 2); };
+  HIPCHK(launch_reach_init(ws->bitmap, ws->rq[0], qlen(0), root, st));
   int cur = 0;
   const int chunk = 8;
+  // a level whose frontier has at least m/64 arcs to scan is found bottom-up
+  // (Beamer's direction switch), unless levels are wanted: at R-MAT 22 the
+  // two largest levels of RV(r) take about 60 M in-arc checks top-down and
+  // far fewer out-arc checks bottom-up.  The rule counts arcs, not vertices:
+  // the second level's frontier is a few ten thousand vertices of large
+  // in-degree (40 M in-arcs)
+  const uint64_t bu_arcs = d_lev ? ~0ull : (uint64_t)std::max<int64_t>(64, g->m / 64);
   for (int64_t level = 0; level <= n;) {
     for (int i = 0; i < chunk; ++i, ++level) {
-      HIPCHK(hipMemsetAsync(&ws->rqn[1 - cur], 0, sizeof(uint32_t), st));
-      HIPCHK(launch_reach_level(rp, col, ws->bitmap, ws->rq[cur], &ws->rqn[cur], ws->rq[1 - cur],
-                                &ws->rqn[1 - cur], d_lev, (int)level, L, st));
+      HIPCHK(hipMemsetAsync(qlen(1 - cur), 0, 4 * sizeof(uint32_t), st));
+      HIPCHK(launch_reach_level(rp, col, ws->bitmap, ws->rq[cur], qlen(cur), qarcs(cur), ws->rq[1 - cur],
+                                qlen(1 - cur), qarcs(1 - cur), d_lev, (int)level, bu_arcs, L, st));
+      if (!d_lev)
+        HIPCHK(launch_reach_bu(rpo, colo, rp, ws->bitmap, qarcs(cur), ws->rq[1 - cur], qlen(1 - cur),
+                               qarcs(1 - cur), n, bu_arcs, L, st));
       cur = 1 - cur;
     }
     uint32_t *h = reinterpret_cast<uint32_t *>(ws->h_misc);
-    HIPCHK(hipMemcpyAsync(h, &ws->rqn[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h, qlen(cur), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (h[0] == 0) break;
   }
