@@ -49,6 +49,46 @@ def test_rv_matches_oracle(B, oracle):
         assert np.array_equal(got, want), r
 
 
+def test_reach_bottom_up_levels_match_oracle(B, oracle):
+    """RV(r) and the forward reach behind K of Eq.(8) on graphs whose large
+    levels go bottom-up (frontiers of at least m/64 arcs), both directions,
+    against the oracle's plain BFS: R-MAT 18 (weights ignored) and a graph of
+    long chains hanging off a dense core, where the frontier shrinks again
+    after the bottom-up levels and the traversal switches back."""
+    g18, q18 = gg.rmat18_weighted()
+    cases = [(g18, q18[:4] + gg.uniform_vertices(g18.n, 4, seed=12, exclude=q18))]
+    core = gg.rmat(16, 8, seed=41)
+    n0 = core.n
+    tails = 8
+    src, dst = [], []
+    for u in range(n0):
+        for e in range(core.row_ptr[u], core.row_ptr[u + 1]):
+            src.append(u)
+            dst.append(int(core.col[e]))
+    # chains of 200 vertices into and out of the core
+    nxt = n0
+    for t in range(tails):
+        prev = t * 97 % n0
+        for _ in range(200):
+            src.append(nxt)
+            dst.append(prev)
+            src.append(prev if t % 2 else nxt)
+            dst.append(nxt if t % 2 else prev)
+            prev = nxt
+            nxt += 1
+    pairs = sorted(set(zip(src, dst)) - {(a, a) for a in range(nxt)})
+    chained = gg.from_arcs(nxt, [a for a, _ in pairs], [b for _, b in pairs], name="core_chains")
+    cases.append((chained, gg.top_out_degree(core, 2) + [n0 + 300, n0 + 199, n0 + 200 * 7 + 3]))
+    for g, rs in cases:
+        G = dev(B, g)
+        for r in rs:
+            print("reach", g.name, r, flush=True)
+            assert np.array_equal(G.rv(r), oracle.rv(g, r)), (g.name, r)
+            _, st = G.bc_sampled(r, eps=0.5, seed=3)
+            if st["rv_size"] > 0:
+                assert st["fr_size"] == oracle.fr_count(g, r), (g.name, r)
+
+
 def test_rv_small_graphs_one_workgroup(B, oracle):
     """Graphs below 2^16 vertices take the single-workgroup reachability
     kernel; RV(r) and the sampled bound's forward reach (through K) match."""
