@@ -141,7 +141,6 @@ void Workspace::release() {
   dfree(S.acc);
   dfree(S.flags);
   dfree(S.ovl);
-  dfree(S.srcdn);
   dfree(d_items0);
   dfree(d_masks0);
   dfree(d_dest0);
@@ -208,7 +207,7 @@ bcd_status Workspace::ensure_batch(int G_) {
   release_weighted();
   dfree(S.sig); dfree(S.psi); dfree(S.dout); dfree(S.vis); dfree(S.fr); dfree(S.rec); dfree(S.bt);
   dfree(S.items); dfree(S.imask); dfree(S.cnt); dfree(S.off); dfree(S.tmin);
-  dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl); dfree(S.srcdn);
+  dfree(S.tgt_of); dfree(S.res); dfree(S.ctr); dfree(S.acc); dfree(S.flags); dfree(S.ovl);
   dfree(d_items0); dfree(d_masks0); dfree(d_dest0); dfree(d_lane_slot); hfree(h_items0); hfree(h_masks0);
   hfree(h_dest0); hfree(h_res);
   res_cap = 0;
@@ -241,7 +240,6 @@ bcd_status Workspace::ensure_batch(int G_) {
   STCHK(dalloc(&S.tgt_of, (size_t)n));
   STCHK(dalloc(&S.flags, 4));
   STCHK(dalloc(&S.ovl, (size_t)G));
-  STCHK(dalloc(&S.srcdn, (size_t)G));
   S.ctr_slots = kCtrSlots;
   STCHK(dalloc(&S.ctr, (size_t)kCtrSlots * C_COUNT));
   STCHK(dalloc(&S.acc, (size_t)C_COUNT));

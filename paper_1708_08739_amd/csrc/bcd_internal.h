@@ -77,7 +77,6 @@ struct BatchState {
   uint64_t *acc;             // [C_COUNT] counters of completed batches
   uint32_t *flags;           // [4]: 0 sigma overflow, 1 item capacity exceeded
   unsigned long long *ovl;   // [G] lanes whose sigma overflowed
-  unsigned long long *srcdn; // [G] unweighted: lanes whose source vertex is a target (set on level 0)
   uint32_t epoch;
   int ctr_slots;
   // per batch (unweighted engine)

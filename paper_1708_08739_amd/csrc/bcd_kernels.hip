@@ -206,12 +206,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
   for (int p = 0; p < P; ++p) cur += S.cnt[(uint64_t)level * P + p];
   const bool pull = !bottom_up_rule(S.bu_den, level, prev, S.gused, S.n);
   const bool disc = !bottom_up_rule(S.bu_den, level + 1, cur, S.gused, S.n);
-  // Level 1 needs no pull: the only level-0 vertex of lane b is its source,
-  // and with no repeated arcs a level-1 vertex has exactly one arc from it,
-  // so sigma_b = 1 and the lane lies below a target iff its source is one
-  // (srcdn, set on level 0).  A hub on level 1 would otherwise read the
-  // record of every one of its in-arcs' tails to find that one arc.
-  const bool one = pull && level == 1;
 
   // counters, all wave-uniform: (source, vertex), (source, arc) and
   // (source, DAG arc) pairs; items and the out-degree sum over items
@@ -239,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
       mask = rec[it].fr[kc];
       e0 = G.rp[v];
       e1 = G.rp[v + 1];
-      if (level > 1 && pull) {
+      if (level > 0 && pull) {
         f0 = G.irp[v];
         f1 = G.irp[v + 1];
       }
@@ -308,11 +302,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
         c_v += (uint64_t)__popcll(mt);
         c_a += (uint64_t)__popcll(mt) * deg;
       }
-      if (one) {
-        acc[t] = 1ull;
-        dnacc[t] = mt & S.srcdn[gt];
-        c_d += (uint64_t)__popcll(mt);  // the arc from each lane's source
-      }
       for (int64_t e = F0 + SUB; e < F1; e += kLanes) {
         const int64_t my = e + lane;
         uint32_t uu = 0;
@@ -357,7 +346,6 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6, 8))) v
       if (lane == 0) {
         if (dnt != 0ull) rec[itt].dn = rec[itt].dn | dnt;
         S.imask[base + i0 + t] = S.keep_all ? mt : dnt;
-        if (level == 0 && is_tgt) atomicOr(&S.srcdn[gt], mt);
       }
       if (level > 0) {
         if (act) S.sig[(uint64_t)itt * kLanes + lane] = acc[t];

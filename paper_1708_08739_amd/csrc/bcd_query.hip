@@ -274,7 +274,6 @@ static bcd_status run_one_batch(Graph *g, Workspace *ws, int k, int ntgt, bool f
     HIPCHK(hipMemsetAsync(S.tmin, 0xFF, sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.flags, 0, 4 * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(S.ovl, 0, (size_t)ws->G * sizeof(unsigned long long), st));
-    HIPCHK(hipMemsetAsync(S.srcdn, 0, (size_t)ws->G * sizeof(unsigned long long), st));
     HIPCHK(launch_batch_init(S, ws->d_items0, ws->d_masks0, ws->d_dest0, k, st));
 
     // forward, in chunks of levels between host checks; a level found
