@@ -63,11 +63,11 @@ __global__ void k_w_init(BatchState S, const uint32_t *items0, const ull *masks0
 struct Compact {
   int A, slots, j, slot, src;
 };
-// Arcs per slot per step.  One: the wavefront's lanes are then all busy on
-// distinct (source, arc) pairs, and the resident waves give the memory
-// parallelism (R-MAT 18, 16,384 sources: 1.73 s against 1.83 / 1.90 / 2.21 s
-// with 2 / 4 / 8).
-constexpr int kWU = 1;
+// Arcs per slot per step of the relaxation: four, so that each lane has four
+// distance reads in flight before it waits (a full-width R-MAT 18 batch of
+// 8,192 sources: 0.94-0.97 s with one, 0.90-0.92 with two, 0.855-0.88 with
+// four, 0.846-0.854 with eight, which needs 74 VGPRs instead of 64).
+constexpr int kWU = 4;
 
 // Orders this wavefront's LDS accesses before and after the call (lanes of
 // one wavefront exchanging values through LDS).
